@@ -1,0 +1,246 @@
+"""CPU oracle for the variational-circuit hot path (test infrastructure only).
+
+Plain FP64 definitions from arXiv:2406.19212 (JuliVQC), written in C
+(``vqc_oracle.c``) and loaded here through ctypes.  Only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
+import this package; the HIP path never does, and the two share no code.
+
+What each function follows:
+* ``gate_matrix`` / ``dgate_matrix`` / ``kraus``: the gate and channel
+  definitions of Sec. 2.2 (with the readings listed in ``vqc_oracle.c``).
+* ``apply_matrix`` / ``run``: Eq. (3), Eq. (twoqubitgate), Alg. 1 and
+  Eq. (circuitevolve); on mixed states, Eq. (channel2) on vec(rho) (Sec. 3.4).
+* ``expectation``: Sec. 2.5 (Pauli sums), Eq. (loss_pure) / Eq. (loss_mixed).
+* ``grad_pure``: Sec. 3.3, Eqs. (diff_pure)-(diff_pure2) and Alg. 2.
+* ``grad_mixed``: Sec. 3.5, Eqs. (diff_mixed)-(diff_mixed2).
+* ``lanczos`` (in ``oracle.lanczos``) and ``mlp`` (in ``oracle.mlp``) cover
+  the ground energy and the surrogate network, which the paper does not define.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+
+CODES = {
+    "x": 1, "y": 2, "z": 3, "h": 4, "s": 5, "t": 6, "sx": 7, "sy": 8, "sw": 9,
+    "rx": 10, "ry": 11, "rz": 12, "id": 13,
+    "cz": 20, "cnot": 21, "swap": 22, "iswap": 23, "fsim": 24, "crx": 25, "cry": 26,
+    "crz": 27, "control": 28, "matrix": 29,
+    "amplitude_damping": 40, "phase_damping": 41, "depolarizing": 42,
+    "depolarizing2": 43, "kraus": 44,
+}
+CHANNELS = {"amplitude_damping", "phase_damping", "depolarizing", "depolarizing2", "kraus"}
+
+
+class OrOp(ctypes.Structure):
+    _fields_ = [
+        ("code", ctypes.c_int), ("m", ctypes.c_int), ("q", ctypes.c_int * 4),
+        ("prm", ctypes.c_double * 5), ("var", ctypes.c_int * 5),
+        ("n_data", ctypes.c_int), ("data", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        _lib.or_gate_matrix.argtypes = [P, P, P]
+        _lib.or_gate_dmatrix.argtypes = [P, P, ctypes.c_int, P]
+        _lib.or_channel_kraus.argtypes = [P, P]
+        _lib.or_superop.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
+        _lib.or_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P]
+        _lib.or_apply_op.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P]
+        _lib.or_run.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+        _lib.or_expect.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P]
+        _lib.or_grad_pure.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P,
+                                      ctypes.c_int, P, P, P]
+        _lib.or_grad_mixed.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P,
+                                       P, ctypes.c_int, P, P, ctypes.c_int]
+        _lib.or_set_threads.argtypes = [ctypes.c_int]
+        _lib.or_get_threads.restype = ctypes.c_int
+    return _lib
+
+
+def set_threads(t: int) -> None:
+    lib().or_set_threads(int(t))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class _OpTable:
+    """ctypes op array; keeps the numpy buffers it points to alive."""
+
+    def __init__(self, ops):
+        self.keep = []
+        self.arr = (OrOp * max(1, len(ops)))()
+        for i, op in enumerate(ops):
+            name = op.name if hasattr(op, "name") else op[0]
+            qubits = tuple(op.qubits if hasattr(op, "qubits") else op[1])
+            params = tuple(getattr(op, "params", ()) or ())
+            var = tuple(getattr(op, "var", ()) or ())
+            data = getattr(op, "data", None)
+            o = self.arr[i]
+            o.code = CODES[name]
+            o.m = len(qubits)
+            for k, q in enumerate(qubits):
+                o.q[k] = int(q)
+            for k in range(5):
+                o.prm[k] = float(params[k]) if k < len(params) else 0.0
+                o.var[k] = int(var[k]) if k < len(var) else -1
+            if data is not None:
+                if isinstance(data, (list, tuple)):
+                    buf = np.ascontiguousarray(np.concatenate([np.asarray(d, np.complex128).ravel()
+                                                               for d in data]))
+                else:
+                    buf = np.ascontiguousarray(np.asarray(data, np.complex128).ravel())
+                self.keep.append(buf)
+                o.n_data = buf.size
+                o.data = buf.ctypes.data
+            else:
+                o.n_data = 0
+                o.data = None
+
+    def __len__(self):
+        return len(self.arr)
+
+
+def _one(name, qubits, params=(), var=(), data=None):
+    from types import SimpleNamespace
+    return SimpleNamespace(name=name, qubits=tuple(qubits), params=tuple(params), var=tuple(var),
+                           data=data)
+
+
+def gate_matrix(name, qubits=None, params=(), data=None, theta=None) -> np.ndarray:
+    """Row-major G[out][in] of a gate (Sec. 2.2)."""
+    m = len(qubits) if qubits is not None else (1 if name in ("x", "y", "z", "h", "s", "t", "sx",
+                                                               "sy", "sw", "rx", "ry", "rz", "id")
+                                                else 2)
+    tab = _OpTable([_one(name, qubits or tuple(range(m)), params, (), data)])
+    G = np.zeros(256, np.complex128)
+    d = lib().or_gate_matrix(ctypes.byref(tab.arr[0]), None, _ptr(G))
+    if d < 0:
+        raise ValueError("not a gate: %s" % name)
+    return G[: d * d].reshape(d, d).copy()
+
+
+def dgate_matrix(name, params, k=0, m=None) -> np.ndarray:
+    m = m or (1 if name in ("rx", "ry", "rz") else 2)
+    tab = _OpTable([_one(name, tuple(range(m)), params)])
+    G = np.zeros(256, np.complex128)
+    d = lib().or_gate_dmatrix(ctypes.byref(tab.arr[0]), None, int(k), _ptr(G))
+    if d < 0:
+        raise ValueError("no derivative for %s param %d" % (name, k))
+    return G[: d * d].reshape(d, d).copy()
+
+
+def kraus(name, params=(), m=None, data=None):
+    m = m or (2 if name == "depolarizing2" else 1)
+    tab = _OpTable([_one(name, tuple(range(m)), params, (), data)])
+    K = np.zeros(16 * 16 * 64, np.complex128)
+    nk = lib().or_channel_kraus(ctypes.byref(tab.arr[0]), _ptr(K))
+    if nk < 0:
+        raise ValueError("not a channel: %s" % name)
+    d = 1 << m
+    return [K[s * d * d:(s + 1) * d * d].reshape(d, d).copy() for s in range(nk)]
+
+
+def superop(kraus_list) -> np.ndarray:
+    d = kraus_list[0].shape[0]
+    m = d.bit_length() - 1
+    K = np.ascontiguousarray(np.concatenate([k.ravel() for k in kraus_list]).astype(np.complex128))
+    S = np.zeros((d * d) ** 2, np.complex128)
+    lib().or_superop(m, len(kraus_list), _ptr(K), _ptr(S))
+    return S.reshape(d * d, d * d)
+
+
+def apply_matrix(v: np.ndarray, nbits: int, qubits, G: np.ndarray) -> None:
+    """In place: Eq. (3) / Alg. 1 for an m-qubit matrix G (row-major)."""
+    assert v.dtype == np.complex128 and v.flags.c_contiguous and v.size == 1 << nbits
+    q = np.asarray(qubits, np.int32)
+    Gc = np.ascontiguousarray(G, np.complex128)
+    lib().or_apply(_ptr(v), int(nbits), len(q), _ptr(q), _ptr(Gc))
+
+
+def initial_state(n: int, mixed: bool = False) -> np.ndarray:
+    v = np.zeros(1 << (2 * n if mixed else n), np.complex128)
+    v[0] = 1.0
+    return v
+
+
+def run(n: int, ops, theta=None, mixed: bool = False, init=None) -> np.ndarray:
+    """Run a circuit from |0..0> (or `init`) and return the state (a copy)."""
+    st = initial_state(n, mixed) if init is None else np.array(init, np.complex128).ravel().copy()
+    tab = _OpTable(ops)
+    th = None if theta is None else np.ascontiguousarray(theta, np.float64)
+    rc = lib().or_run(_ptr(st), n, int(mixed), len(ops), tab.arr, None if th is None else _ptr(th))
+    if rc:
+        raise ValueError("oracle run failed at op %d" % (-1 - rc))
+    return st
+
+
+def _terms(terms):
+    xm = np.array([t[0] for t in terms], np.uint64)
+    zm = np.array([t[1] for t in terms], np.uint64)
+    c = np.array([complex(t[2]) for t in terms], np.complex128)
+    return xm, zm, c
+
+
+def expectation(state: np.ndarray, n: int, terms, mixed: bool = False) -> complex:
+    xm, zm, c = _terms(terms)
+    st = np.ascontiguousarray(state, np.complex128).ravel()
+    out = np.zeros(1, np.complex128)
+    lib().or_expect(_ptr(st), n, int(mixed), len(terms), _ptr(xm), _ptr(zm), _ptr(c), _ptr(out))
+    return complex(out[0])
+
+
+def grad_pure(n: int, ops, theta, terms, init=None, n_params=None):
+    """Alg. 2.  Returns (energy, grad, Phi after the sweep)."""
+    xm, zm, c = _terms(terms)
+    th = np.ascontiguousarray(theta, np.float64)
+    P = int(n_params if n_params is not None else th.size)
+    grad = np.zeros(max(P, 1), np.float64)
+    e = np.zeros(1, np.float64)
+    phi = np.zeros(1 << n, np.complex128)
+    ini = None if init is None else np.ascontiguousarray(init, np.complex128)
+    tab = _OpTable(ops)
+    rc = lib().or_grad_pure(n, len(ops), tab.arr, _ptr(th), None if ini is None else _ptr(ini),
+                            len(terms), _ptr(xm), _ptr(zm), _ptr(c), P, _ptr(grad), _ptr(e),
+                            _ptr(phi))
+    if rc:
+        raise ValueError("oracle grad_pure failed (%d)" % rc)
+    return float(e[0]), grad[:P], phi
+
+
+def grad_mixed(n: int, ops, theta, terms, init=None, n_params=None, stride: int = 0):
+    """Sec. 3.5 noisy gradient.  Returns (energy, grad)."""
+    xm, zm, c = _terms(terms)
+    th = np.ascontiguousarray(theta, np.float64)
+    P = int(n_params if n_params is not None else th.size)
+    grad = np.zeros(max(P, 1), np.float64)
+    e = np.zeros(1, np.float64)
+    ini = None if init is None else np.ascontiguousarray(init, np.complex128).ravel()
+    tab = _OpTable(ops)
+    rc = lib().or_grad_mixed(n, len(ops), tab.arr, _ptr(th), None if ini is None else _ptr(ini),
+                             len(terms), _ptr(xm), _ptr(zm), _ptr(c), P, _ptr(grad), _ptr(e),
+                             int(stride))
+    if rc:
+        raise ValueError("oracle grad_mixed failed (%d)" % rc)
+    return float(e[0]), grad[:P]

@@ -1,0 +1,507 @@
+"""Pins for the CPU oracle: each check ties the oracle to something other than
+itself -- dense Kronecker operators built with numpy, matrix exponentials
+(scipy), closed forms, the FFT, parameter-shift rules, hand-derived values of
+the paper's listings (tests/golden/listings.json), and invariants."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from paper_2406_19212_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "listings.json")
+
+# textbook Pauli matrices, written independently of the oracle
+I2 = np.eye(2, dtype=complex)
+PX = np.array([[0, 1], [1, 0]], complex)
+PY = np.array([[0, -1j], [1j, 0]], complex)
+PZ = np.array([[1, 0], [0, -1]], complex)
+PAULI = {"i": I2, "x": PX, "y": PY, "z": PZ}
+
+
+# ---------------------------------------------------------------- helpers
+
+def dense_op(n, qubits, G):
+    """Full 2^n x 2^n operator of an m-qubit matrix G (row-major, local index
+    sum_t b_{q_t} 2^t), built with tensordot on the (2,)*n tensor -- a mechanism
+    unrelated to the oracle's gather/scatter loops."""
+    m = len(qubits)
+    N = 1 << n
+    out = np.zeros((N, N), complex)
+    # numpy C-order axes of psi.reshape([2]*n) are (q_{n-1}, ..., q_0)
+    axis = {q: n - 1 - q for q in range(n)}
+    # tensor form of G: axes (out_{m-1},...,out_0,in_{m-1},...,in_0)
+    Gt = G.reshape([2] * (2 * m))
+    in_axes = [axis[qubits[t]] for t in range(m)][::-1]
+    for col in range(N):
+        e = np.zeros(N, complex)
+        e[col] = 1
+        T = e.reshape([2] * n)
+        R = np.tensordot(Gt, T, axes=(list(range(m, 2 * m)), in_axes))
+        # R axes: (out_{m-1}..out_0, remaining axes in order)
+        rest = [a for a in range(n) if a not in in_axes]
+        perm_src = in_axes + rest
+        R = np.moveaxis(R, list(range(n)), perm_src)
+        out[:, col] = R.reshape(N)
+    return out
+
+
+def pauli_dense(n, term):
+    xm, zm, c = term
+    M = np.array([[1.0 + 0j]])
+    for q in range(n - 1, -1, -1):  # kron order: qubit n-1 is most significant
+        bx, bz = (xm >> q) & 1, (zm >> q) & 1
+        p = {(0, 0): I2, (1, 0): PX, (1, 1): PY, (0, 1): PZ}[(bx, bz)]
+        M = np.kron(M, p)
+    return c * M
+
+
+def ham_dense(n, terms):
+    return sum(pauli_dense(n, t) for t in terms)
+
+
+def vec(rho):
+    """v[x + 2^n y] = rho[x][y] (column-major vectorisation)."""
+    return np.asarray(rho).reshape(-1, order="F").copy()
+
+
+def unvec(v, n):
+    return v.reshape((1 << n, 1 << n), order="F")
+
+
+# ------------------------------------------------------------- application
+
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_apply_1q_every_position_vs_kron(oracle_mod, n):
+    psi = W.random_state(n, 11 + n)
+    for q in range(n):
+        G = W.random_unitary(2, 100 + q)
+        v = psi.copy()
+        oracle_mod.apply_matrix(v, n, [q], G)
+        O = np.kron(np.kron(np.eye(1 << (n - q - 1)), G), np.eye(1 << q))
+        assert np.max(np.abs(v - O @ psi)) < 1e-14
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_apply_2q_every_pair_vs_dense(oracle_mod, n):
+    psi = W.random_state(n, 21 + n)
+    for a in range(n):
+        for b in range(n):
+            if a == b:
+                continue
+            G = W.random_unitary(4, 7 * a + b)
+            v = psi.copy()
+            oracle_mod.apply_matrix(v, n, [a, b], G)
+            assert np.max(np.abs(v - dense_op(n, [a, b], G) @ psi)) < 1e-14
+
+
+def test_apply_2q_adjacent_matches_kron(oracle_mod):
+    # independent of dense_op: a 2q gate on (q, q+1) is kron(I, G, I)
+    n = 5
+    psi = W.random_state(n, 5)
+    for q in range(n - 1):
+        G = W.random_unitary(4, 40 + q)
+        v = psi.copy()
+        oracle_mod.apply_matrix(v, n, [q, q + 1], G)
+        O = np.kron(np.kron(np.eye(1 << (n - q - 2)), G), np.eye(1 << q))
+        assert np.max(np.abs(v - O @ psi)) < 1e-14
+
+
+def test_apply_4q_vs_dense(oracle_mod):
+    n = 6
+    psi = W.random_state(n, 77)
+    for k, qs in enumerate([(0, 1, 2, 3), (5, 0, 3, 1), (2, 4, 1, 5)]):
+        G = W.random_unitary(16, 300 + k)
+        v = psi.copy()
+        oracle_mod.apply_matrix(v, n, list(qs), G)
+        assert np.max(np.abs(v - dense_op(n, list(qs), G) @ psi)) < 1e-13
+
+
+def test_norm_preserved_random_circuits(oracle_mod):
+    ops, th = W.brickwall(10, 6, 3)
+    st = oracle_mod.run(10, ops, th)
+    assert abs(np.linalg.norm(st) - 1) < 1e-14
+    ops = W.rqc_grid(3, 3, 8, 5)
+    st = oracle_mod.run(9, ops)
+    assert abs(np.linalg.norm(st) - 1) < 1e-14
+
+
+# ----------------------------------------------------------- gate matrices
+
+@pytest.mark.parametrize("name,P", [("rx", PX), ("ry", PY), ("rz", PZ)])
+def test_rotations_are_exponentials(oracle_mod, name, P):
+    for t in [0.0, 0.3, -1.7, math.pi, 5.9]:
+        G = oracle_mod.gate_matrix(name, params=(t,))
+        assert np.max(np.abs(G - sla.expm(-0.5j * t * P))) < 1e-15
+
+
+def test_ry_pi_flips_zero(oracle_mod):
+    G = oracle_mod.gate_matrix("ry", params=(math.pi,))
+    out = G @ np.array([1, 0])
+    assert abs(out[1] - 1) < 1e-15
+
+
+def test_fixed_1q_gates(oracle_mod):
+    H = oracle_mod.gate_matrix("h")
+    S = oracle_mod.gate_matrix("s")
+    T = oracle_mod.gate_matrix("t")
+    X, Y, Z = (oracle_mod.gate_matrix(g) for g in "xyz")
+    assert np.allclose(X, PX, atol=0) and np.allclose(Y, PY, atol=0) and np.allclose(Z, PZ, atol=0)
+    assert np.max(np.abs(H @ PX @ H - PZ)) < 1e-15
+    assert np.max(np.abs(H @ np.array([1, 0]) - np.array([1, 1]) / math.sqrt(2))) < 1e-15
+    assert np.max(np.abs(S @ S - PZ)) < 1e-15
+    assert np.max(np.abs(T @ T - S)) < 1e-15
+    W_ = (PX + PY) / math.sqrt(2)
+    for name, G in (("sx", PX), ("sy", PY), ("sw", W_)):
+        R = oracle_mod.gate_matrix(name)
+        assert np.max(np.abs(R @ R - G)) < 1e-15
+        assert np.max(np.abs(R.conj().T @ R - I2)) < 1e-15
+        # principal root: eigenvalues of R are 1 and i
+        ev = np.sort_complex(np.linalg.eigvals(R))
+        assert np.allclose(ev, np.sort_complex(np.array([1, 1j])), atol=1e-14)
+
+
+def test_two_qubit_fixed_gates(oracle_mod):
+    CN = oracle_mod.gate_matrix("cnot", (0, 1))
+    # truth table, local index l = b_control + 2 b_target
+    for c in (0, 1):
+        for t in (0, 1):
+            e = np.zeros(4)
+            e[c + 2 * t] = 1
+            out = CN @ e
+            assert out[c + 2 * (t ^ c)] == 1
+    Ht = np.kron(oracle_mod.gate_matrix("h"), I2)  # H on local bit 1 (target)
+    assert np.max(np.abs(Ht @ CN @ Ht - oracle_mod.gate_matrix("cz", (0, 1)))) < 1e-15
+    SW = oracle_mod.gate_matrix("swap", (0, 1))
+    for l in range(4):
+        e = np.zeros(4)
+        e[l] = 1
+        assert (SW @ e)[((l & 1) << 1) | (l >> 1)] == 1
+    XXYY = np.kron(PX, PX) + np.kron(PY, PY)
+    assert np.max(np.abs(oracle_mod.gate_matrix("iswap", (0, 1)) - sla.expm(0.25j * math.pi * XXYY))) < 1e-15
+
+
+def test_fsim_is_exponential_times_cphase(oracle_mod):
+    XXYY = np.kron(PX, PX) + np.kron(PY, PY)
+    for th, ph in [(0.3, 0.1), (math.pi / 2, math.pi / 6), (-2.0, 4.0)]:
+        F = oracle_mod.gate_matrix("fsim", (0, 1), params=(th, ph, 0, 0, 0))
+        ref = np.diag([1, 1, 1, np.exp(-1j * ph)]) @ sla.expm(-0.5j * th * XXYY)
+        assert np.max(np.abs(F - ref)) < 1e-15
+        assert np.max(np.abs(F - F[[0, 2, 1, 3]][:, [0, 2, 1, 3]])) < 1e-15  # qubit-swap symmetric
+
+
+def test_fsim_delta_terms_unitary_and_z_sandwich(oracle_mod):
+    th, ph, dp, dm, do = 0.7, 0.4, 0.3, -0.2, 0.5
+    F = oracle_mod.gate_matrix("fsim", (0, 1), params=(th, ph, dp, dm, do))
+    assert np.max(np.abs(F.conj().T @ F - np.eye(4))) < 1e-15
+    F0 = oracle_mod.gate_matrix("fsim", (0, 1), params=(th, ph, 0, 0, 0))
+    # the Delta terms are diagonal phases before/after fSim: F = D_a F0 D_b
+    Da = np.diag(np.exp(1j * np.array([0, dp / 2 + (dm - do) / 2, dp / 2 + (do - dm) / 2, dp])))
+    Db = np.diag(np.exp(1j * np.array([0, dp / 2 + (dm + do) / 2, dp / 2 - (dm + do) / 2, dp])))
+    assert np.max(np.abs(Da @ F0 @ Db - F)) < 1e-15
+
+
+@pytest.mark.parametrize("name,P", [("crx", PX), ("cry", PY), ("crz", PZ)])
+def test_controlled_rotations(oracle_mod, name, P):
+    t = 1.234
+    G = oracle_mod.gate_matrix(name, (0, 1), params=(t,))
+    R = sla.expm(-0.5j * t * P)
+    # control = local bit 0: control=1 block indices (1, 3), control=0 block (0, 2)
+    assert np.max(np.abs(G[np.ix_([1, 3], [1, 3])] - R)) < 1e-15
+    assert np.max(np.abs(G[np.ix_([0, 2], [0, 2])] - I2)) < 1e-15
+    assert np.max(np.abs(G[np.ix_([0, 2], [1, 3])])) == 0
+    U = W.random_unitary(2, 9)
+    C = oracle_mod.gate_matrix("control", (0, 1), data=U)
+    assert np.max(np.abs(C[np.ix_([1, 3], [1, 3])] - U)) == 0
+
+
+@pytest.mark.parametrize("name,m,nparams", [("rx", 1, 1), ("ry", 1, 1), ("rz", 1, 1), ("crx", 2, 1),
+                                            ("cry", 2, 1), ("crz", 2, 1), ("fsim", 2, 5)])
+def test_gate_derivatives_vs_central_difference(oracle_mod, name, m, nparams):
+    p0 = np.array([0.37, 1.1, -0.4, 0.25, 0.8])[:nparams]
+    h = 1e-5
+    for k in range(nparams):
+        pp, pm = p0.copy(), p0.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (oracle_mod.gate_matrix(name, tuple(range(m)), params=tuple(pp)) -
+              oracle_mod.gate_matrix(name, tuple(range(m)), params=tuple(pm))) / (2 * h)
+        d = oracle_mod.dgate_matrix(name, tuple(p0), k, m)
+        assert np.max(np.abs(d - fd)) < 1e-9
+
+
+# ---------------------------------------------------------------- channels
+
+@pytest.mark.parametrize("name,m,p", [("amplitude_damping", 1, 0.3), ("phase_damping", 1, 0.2),
+                                      ("depolarizing", 1, 0.15), ("depolarizing2", 2, 0.1)])
+def test_channel_completeness(oracle_mod, name, m, p):
+    K = oracle_mod.kraus(name, (p,), m)
+    d = 1 << m
+    assert np.max(np.abs(sum(k.conj().T @ k for k in K) - np.eye(d))) < 1e-15
+
+
+def test_amplitude_damping_closed_form(oracle_mod):
+    g = 0.27
+    rho = W.random_density(1, 3)
+    v = vec(rho)
+    oracle_mod.apply_matrix(v, 2, [0, 1], oracle_mod.superop(oracle_mod.kraus("amplitude_damping", (g,))))
+    out = unvec(v, 1)
+    assert abs(out[1, 1] - (1 - g) * rho[1, 1]) < 1e-15
+    assert abs(out[0, 0] - (rho[0, 0] + g * rho[1, 1])) < 1e-15
+    assert abs(out[0, 1] - math.sqrt(1 - g) * rho[0, 1]) < 1e-15
+
+
+def test_phase_damping_closed_form(oracle_mod):
+    g = 0.4
+    rho = W.random_density(1, 4)
+    v = vec(rho)
+    oracle_mod.apply_matrix(v, 2, [0, 1], oracle_mod.superop(oracle_mod.kraus("phase_damping", (g,))))
+    out = unvec(v, 1)
+    assert abs(out[0, 0] - rho[0, 0]) < 1e-15 and abs(out[1, 1] - rho[1, 1]) < 1e-15
+    assert abs(out[0, 1] - math.sqrt(1 - g) * rho[0, 1]) < 1e-15
+
+
+def test_depolarizing_shrinks_bloch_vector(oracle_mod):
+    p = 0.23
+    rho = W.random_density(1, 5)
+    v = vec(rho)
+    oracle_mod.apply_matrix(v, 2, [0, 1], oracle_mod.superop(oracle_mod.kraus("depolarizing", (p,))))
+    out = unvec(v, 1)
+    assert np.max(np.abs(out - ((1 - p) * rho + p * np.trace(rho) * I2 / 2))) < 1e-15
+    for P in (PX, PY, PZ):
+        assert abs(np.trace(P @ out) - (1 - p) * np.trace(P @ rho)) < 1e-15
+
+
+def test_two_qubit_depolarizing_closed_form(oracle_mod):
+    # channel on qubits (0, 2) of a random 3-qubit rho:
+    # rho -> (1-p) rho + p * (I/4 on qubits 0,2) (x) Tr_{0,2}(rho)
+    p, n = 0.31, 3
+    rho = W.random_density(n, 6)
+    st = vec(rho)
+    from types import SimpleNamespace as NS
+    out = unvec(oracle_mod.run(n, [NS(name="depolarizing2", qubits=(0, 2), params=(p,), var=(), data=None)],
+                               mixed=True, init=st), n)
+    T = rho.reshape(2, 2, 2, 2, 2, 2)  # (q2, q1, q0, q2', q1', q0')
+    red = np.einsum("aibajb->ij", T)  # trace over q2 and q0 -> rho_q1
+    repl = np.einsum("ij,ac,bd->aibcjd", red, I2 / 2, I2 / 2).reshape(8, 8)
+    assert np.max(np.abs(out - ((1 - p) * rho + p * repl))) < 1e-15
+
+
+def test_superop_path_matches_direct_kraus_sum(oracle_mod):
+    from types import SimpleNamespace as NS
+    n = 4
+    rho = W.random_density(n, 8)
+    for k, (qs, cnt) in enumerate([((2,), 3), ((3, 1), 5), ((0,), 2), ((1, 2), 2)]):
+        K = W.random_kraus(1 << len(qs), cnt, 50 + k)
+        out = unvec(oracle_mod.run(n, [NS(name="kraus", qubits=qs, params=(), var=(), data=K)],
+                                   mixed=True, init=vec(rho)), n)
+        ref = sum(dense_op(n, list(qs), Ks) @ rho @ dense_op(n, list(qs), Ks).conj().T for Ks in K)
+        assert np.max(np.abs(out - ref)) < 1e-14
+
+
+def test_noiseless_density_equals_outer_product(oracle_mod):
+    n = 4
+    ops, th = W.brickwall(n, 3, 12)
+    psi = oracle_mod.run(n, ops, th)
+    rho = unvec(oracle_mod.run(n, ops, th, mixed=True), n)
+    assert np.max(np.abs(rho - np.outer(psi, psi.conj()))) < 1e-14
+
+
+def test_noisy_circuit_gives_valid_density(oracle_mod):
+    n = 4
+    ops, th = W.noisy_brickwall(n, 4, 13, p1=0.05, gamma=0.07, p2=0.1)
+    rho = unvec(oracle_mod.run(n, ops, th, mixed=True), n)
+    assert abs(np.trace(rho) - 1) < 1e-14
+    assert np.max(np.abs(rho - rho.conj().T)) < 1e-15
+    assert np.linalg.eigvalsh(rho).min() > -1e-14
+
+
+# -------------------------------------------------------------- observables
+
+def test_expectation_vs_dense(oracle_mod):
+    n = 6
+    terms = W.heisenberg_1d(n, hz=0.7, J=1.3) + [W.pauli_string({0: "y", 3: "x", 5: "z"}, 0.4 - 0.2j),
+                                                  W.pauli_string({1: "y", 2: "y"}, -0.9)]
+    psi = W.random_state(n, 31)
+    H = ham_dense(n, terms)
+    assert abs(oracle_mod.expectation(psi, n, terms) - psi.conj() @ H @ psi) < 1e-13
+    rho = W.random_density(n, 32)
+    assert abs(oracle_mod.expectation(vec(rho), n, terms, mixed=True) - np.trace(H @ rho)) < 1e-13
+
+
+def test_product_state_expectations(oracle_mod):
+    from types import SimpleNamespace as NS
+    for t in [0.1, 1.0, 2.5, -0.7]:
+        psi = oracle_mod.run(1, [NS(name="ry", qubits=(0,), params=(t,), var=(), data=None)])
+        assert abs(oracle_mod.expectation(psi, 1, [W.pauli_string({0: "x"})]) - math.sin(t)) < 1e-15
+        assert abs(oracle_mod.expectation(psi, 1, [W.pauli_string({0: "z"})]) - math.cos(t)) < 1e-15
+        assert abs(oracle_mod.expectation(psi, 1, [W.pauli_string({0: "y"})])) < 1e-15
+
+
+def test_listing_golden_values(oracle_mod):
+    from types import SimpleNamespace as NS
+    g = json.load(open(GOLD))
+    # Listing 1
+    st = oracle_mod.run(2, [NS(name=a, qubits=tuple(b), params=(), var=(), data=None)
+                            for a, b in g["listing1_custom_pure"]["equals_circuit"]])
+    assert np.array_equal(st, np.array(g["listing1_custom_pure"]["data"], complex))
+    st = oracle_mod.run(2, [NS(name=a, qubits=tuple(b), params=(), var=(), data=None)
+                            for a, b in g["listing1_custom_mixed"]["equals_circuit"]], mixed=True)
+    assert np.argmax(np.abs(st)) == g["listing1_custom_mixed"]["data_nonzero_index"]
+    assert abs(st[g["listing1_custom_mixed"]["data_nonzero_index"]] - 1) == 0
+    # Listing 4
+    L4 = g["listing4_probability"]
+    st = oracle_mod.run(2, [NS(name=a, qubits=tuple(b), params=tuple(c), var=(), data=None)
+                            for a, b, c in L4["circuit"]])
+    q = L4["measured_qubit"]
+    p1 = sum(abs(st[x]) ** 2 for x in range(4) if (x >> q) & 1)
+    assert abs(p1 - L4["p_outcome_1"]) < 1e-15
+    # Listing 5
+    L5 = g["listing5_heisenberg"]
+    terms = W.heisenberg_1d(L5["L"])
+    e = np.zeros(8, complex)
+    e[0] = 1
+    assert abs(oracle_mod.expectation(e, 3, terms) - L5["expect_all_zero"]) < 1e-15
+    e[:] = 0
+    e[7] = 1
+    assert abs(oracle_mod.expectation(e, 3, terms) - L5["expect_all_one"]) < 1e-15
+    e[:] = 0
+    e[2] = 1
+    assert abs(oracle_mod.expectation(e, 3, terms) - L5["expect_basis_010"]) < 1e-15
+
+
+# -------------------------------------------------------------- closed forms
+
+def test_ghz_closed_form(oracle_mod):
+    from types import SimpleNamespace as NS
+    for n in (2, 5, 11):
+        ops = [NS(name="h", qubits=(0,), params=(), var=(), data=None)]
+        ops += [NS(name="cnot", qubits=(k, k + 1), params=(), var=(), data=None) for k in range(n - 1)]
+        st = oracle_mod.run(n, ops)
+        ref = np.zeros(1 << n, complex)
+        ref[0] = ref[-1] = 1 / math.sqrt(2)
+        assert np.max(np.abs(st - ref)) < 1e-15
+
+
+def qft_ops(n):
+    """Textbook QFT: qubit n-1 is the most significant bit of the input integer;
+    H then controlled phases diag(1, e^{i pi / 2^k}), then reverse the qubits."""
+    from types import SimpleNamespace as NS
+    ops = []
+    for j in range(n - 1, -1, -1):
+        ops.append(NS(name="h", qubits=(j,), params=(), var=(), data=None))
+        for k, c in enumerate(range(j - 1, -1, -1), start=1):
+            U = np.diag([1, np.exp(1j * math.pi / 2 ** k)])
+            ops.append(NS(name="control", qubits=(c, j), params=(), var=(), data=U))
+    for a in range(n // 2):
+        ops.append(NS(name="swap", qubits=(a, n - 1 - a), params=(), var=(), data=None))
+    return ops
+
+
+@pytest.mark.parametrize("n", [1, 3, 6, 9])
+def test_qft_equals_dft(oracle_mod, n):
+    N = 1 << n
+    x = 5 % N
+    st = np.zeros(N, complex)
+    st[x] = 1
+    out = oracle_mod.run(n, qft_ops(n), init=st)
+    ref = np.exp(2j * math.pi * x * np.arange(N) / N) / math.sqrt(N)
+    assert np.max(np.abs(out - ref)) < 1e-14
+    psi = W.random_state(n, 90 + n)
+    out = oracle_mod.run(n, qft_ops(n), init=psi)
+    assert np.max(np.abs(out - np.fft.ifft(psi) * math.sqrt(N))) < 1e-14
+
+
+# ---------------------------------------------------------------- gradients
+
+def loss_pure(oracle_mod, n, ops, theta, terms):
+    return oracle_mod.expectation(oracle_mod.run(n, ops, theta), n, terms).real
+
+
+def loss_mixed(oracle_mod, n, ops, theta, terms):
+    return oracle_mod.expectation(oracle_mod.run(n, ops, theta, mixed=True), n, terms, mixed=True).real
+
+
+def shift_grad(f, theta):
+    """Parameter shift: exact for gates exp(-i t P / 2)."""
+    g = np.zeros_like(theta)
+    for k in range(theta.size):
+        tp, tm = theta.copy(), theta.copy()
+        tp[k] += math.pi / 2
+        tm[k] -= math.pi / 2
+        g[k] = (f(tp) - f(tm)) / 2
+    return g
+
+
+def test_adjoint_pure_vs_parameter_shift_brickwall(oracle_mod):
+    n = 5
+    ops, th = W.brickwall(n, 2, 41)
+    terms = W.heisenberg_1d(n, hz=0.5, J=1.0)
+    e, g, phi = oracle_mod.grad_pure(n, ops, th, terms)
+    assert abs(e - loss_pure(oracle_mod, n, ops, th, terms)) < 1e-13
+    gs = shift_grad(lambda t: loss_pure(oracle_mod, n, ops, t, terms), th)
+    assert np.max(np.abs(g - gs)) < 1e-12
+    # Alg. 2 uncomputes Phi back to the initial state
+    assert abs(phi[0] - 1) < 1e-13 and np.max(np.abs(phi[1:])) < 1e-13
+
+
+def test_adjoint_pure_vs_parameter_shift_hea(oracle_mod):
+    n = 6
+    ops = W.hea(n, 3)
+    th = W.theta_uniform(7, 1, W.count_params(ops))[0]
+    terms = W.tfim(n, 1.0)
+    e, g, _ = oracle_mod.grad_pure(n, ops, th, terms)
+    gs = shift_grad(lambda t: loss_pure(oracle_mod, n, ops, t, terms), th)
+    assert np.max(np.abs(g - gs)) < 1e-12
+
+
+def test_adjoint_pure_fsim_and_controlled_vs_fd(oracle_mod):
+    from types import SimpleNamespace as NS
+    n = 4
+    ops = [NS(name="h", qubits=(q,), params=(), var=(), data=None) for q in range(n)]
+    ops += [NS(name="fsim", qubits=(0, 2), params=(0, 0, 0, 0, 0), var=(0, 1, 2, 3, 4), data=None),
+            NS(name="crx", qubits=(3, 1), params=(0,), var=(5,), data=None),
+            NS(name="cry", qubits=(1, 2), params=(0,), var=(6,), data=None),
+            NS(name="crz", qubits=(2, 0), params=(0,), var=(7,), data=None),
+            NS(name="ry", qubits=(3,), params=(0,), var=(0,), data=None)]  # shared parameter 0
+    th = np.array([0.4, 0.9, -0.3, 0.2, 0.6, 1.3, -0.8, 2.1])
+    terms = W.heisenberg_1d(n)
+    _, g, _ = oracle_mod.grad_pure(n, ops, th, terms)
+    h = 1e-5
+    for k in range(th.size):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (loss_pure(oracle_mod, n, ops, tp, terms) - loss_pure(oracle_mod, n, ops, tm, terms)) / (2 * h)
+        assert abs(g[k] - fd) < 1e-8
+
+
+def test_adjoint_mixed_vs_parameter_shift(oracle_mod):
+    n = 3
+    ops, th = W.noisy_brickwall(n, 2, 44, p1=0.05, gamma=0.08, p2=0.1)
+    terms = W.zz(0, 1) + [W.pauli_string({2: "x"}, 0.5), W.pauli_string({0: "y", 2: "y"}, -0.3)]
+    e, g = oracle_mod.grad_mixed(n, ops, th, terms)
+    assert abs(e - loss_mixed(oracle_mod, n, ops, th, terms)) < 1e-14
+    gs = shift_grad(lambda t: loss_mixed(oracle_mod, n, ops, t, terms), th)
+    assert np.max(np.abs(g - gs)) < 1e-12
+
+
+def test_adjoint_mixed_checkpoint_stride_invariant(oracle_mod):
+    n = 3
+    ops, th = W.noisy_brickwall(n, 3, 45)
+    terms = W.zz(0, 1)
+    ref = oracle_mod.grad_mixed(n, ops, th, terms, stride=1)[1]
+    for s in (0, 4, 17, len(ops) + 3):
+        assert np.array_equal(oracle_mod.grad_mixed(n, ops, th, terms, stride=s)[1], ref)
+
+
+def test_noiseless_mixed_gradient_equals_pure(oracle_mod):
+    n = 3
+    ops, th = W.brickwall(n, 2, 46)
+    terms = W.tfim(n)
+    _, gp, _ = oracle_mod.grad_pure(n, ops, th, terms)
+    _, gm = oracle_mod.grad_mixed(n, ops, th, terms)
+    assert np.max(np.abs(gp - gm)) < 1e-13
