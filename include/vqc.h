@@ -1,0 +1,256 @@
+/*
+ * vqc.h -- C ABI of the MI355X (gfx950) variational-quantum-circuit hot path.
+ *
+ * The method is the state-vector simulator with memory-efficient reverse-mode
+ * gradients of Liao et al., "JuliVQC: an Efficient Variational Quantum Circuit
+ * Simulator for Near-Term Quantum Algorithms" (arXiv:2406.19212):
+ * gate application (Sec. 3.1, Eqs. (3) and (twoqubitgate), Alg. 1), channels
+ * as superoperators on the vectorised density matrix (Sec. 3.4,
+ * Eq. (channel2)), Pauli-sum expectation values (Sec. 2.5) and the adjoint
+ * gradient sweep (Sec. 3.3, Alg. 2; Sec. 3.5).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Qubits are 0-based.  Qubit k is bit k of the amplitude index: the paper's
+ *   column-major storage with the first qubit fastest (Sec. 2.1).
+ * - Amplitudes are complex128, interleaved (re, im), 16 bytes each; the layout
+ *   of vqc_c128, std::complex<double> and torch.complex128.
+ * - A pure n-qubit state holds 2^n amplitudes.  A mixed state is the
+ *   vectorised density matrix (Sec. 3.4) with 4^n entries:
+ *   v[x + 2^n y] = rho[x][y]; ket bits 0..n-1, bra bits n..2n-1 (Sec. 2.1).
+ * - Gate and Kraus matrices follow the paper's QuantumGate convention
+ *   (Sec. 2.2): column-major storage of the 2^m x 2^m matrix, element
+ *   (out, in) at data[out + 2^m * in]; the local index of an m-qubit op is
+ *   l = sum_t b_{qubits[t]} 2^t (first listed qubit = least significant).
+ *   vqc_mat_from_external converts a textbook row-major matrix.
+ * - Device buffers are caller-owned (e.g. torch tensors) and must stay alive
+ *   while work that uses them is queued.  Host arrays passed in are copied
+ *   before the call returns.
+ * - Work is queued on the HIP stream bound to the state or batch and runs
+ *   asynchronously; only calls with host outputs synchronise that stream.
+ * - Every call returns vqc_status (0 = VQC_OK, negative = error) and never
+ *   aborts.  Arguments are validated on the host before any launch; a call
+ *   that returns an error has queued no work and left every buffer unchanged.
+ * - Handles are not thread-safe; use one handle per stream.
+ */
+#ifndef VQC_ABI_INCLUDED
+#define VQC_ABI_INCLUDED
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VQC_OK = 0,
+  VQC_ERR_ARG = -1,           /* null pointer, bad size or count */
+  VQC_ERR_QUBIT = -2,         /* qubit out of range or repeated */
+  VQC_ERR_UNSUPPORTED = -3,   /* op arity or combination not supported */
+  VQC_ERR_KIND = -4,          /* pure/mixed mismatch */
+  VQC_ERR_NOT_CPTP = -5,      /* Kraus set fails sum K^dagger K = I to 1e-12 */
+  VQC_ERR_NONFINITE = -6,     /* NaN or Inf in a host-side input */
+  VQC_ERR_OOM = -7,           /* device allocation failed */
+  VQC_ERR_HIP = -8,           /* HIP runtime error */
+  VQC_ERR_NOT_HERMITIAN = -9, /* gradient asked for a complex-coefficient H */
+  VQC_ERR_NOT_UNITARY = -10   /* backward through a non-unitary gate matrix */
+} vqc_status;
+
+typedef enum { VQC_PURE = 0, VQC_MIXED = 1 } vqc_kind;
+
+typedef struct { double re, im; } vqc_c128;
+
+typedef struct vqc_state_s *vqc_state;     /* view of a caller-owned buffer */
+typedef struct vqc_circuit_s *vqc_circuit; /* planned op table + device tables */
+typedef struct vqc_batch_s *vqc_batch;     /* many circuits/parameter sets */
+
+/* Op types (Sec. 2.2).  Rotations are exp(-i theta P / 2); Ry = [[c,-s],[s,c]];
+ * sqrt(G) = ((1+i) I + (1-i) G)/2 for G in {X, Y, W}, W = (X+Y)/sqrt(2).
+ * Two-qubit gates use the local index b_{q0} + 2 b_{q1}: CNOT/CONTROL/CR* have
+ * the control on qubits[0] and the target on qubits[1]; FSIM takes
+ * (theta, phi, Delta+, Delta-, Delta-off) as printed in Sec. 2.2. */
+enum {
+  VQC_X = 1, VQC_Y, VQC_Z, VQC_H, VQC_S, VQC_T, VQC_SX, VQC_SY, VQC_SW,
+  VQC_RX, VQC_RY, VQC_RZ, VQC_ID,
+  VQC_CZ = 20, VQC_CNOT, VQC_SWAP, VQC_ISWAP, VQC_FSIM, VQC_CRX, VQC_CRY, VQC_CRZ,
+  VQC_CONTROL, /* CONTROLGate(i, j, U): data = 2x2 target matrix */
+  VQC_MATRIX,  /* QuantumGate(positions, data): data = 2^m x 2^m, m <= 2 */
+  /* channels (Sec. 2.2); params[0] = gamma or p.  Depolarizing uses
+   * K0 = sqrt(1-3p/4) I, K1..3 = sqrt(p/4) sigma (trace preserving);
+   * DEPOLARIZING2 uses K0 = sqrt(1-15p/16) I, K_ab = sqrt(p/16) sigma_a(x)sigma_b. */
+  VQC_AMPLITUDE_DAMPING = 40, VQC_PHASE_DAMPING, VQC_DEPOLARIZING, VQC_DEPOLARIZING2,
+  VQC_KRAUS    /* QuantumMap(positions, kraus): data = n_kraus blocks of 2^m x 2^m */
+};
+
+/* One op of a circuit (Sec. 2.3).  param_index[k] >= 0 marks parameter k as
+ * variational (the paper's isparas) and names its slot in the flat theta
+ * vector (active_parameters order is the caller's choice of indices); -1
+ * means params[k] is used as a fixed value.  Channels take no variational
+ * parameters (Sec. 2.2). */
+typedef struct {
+  int type;
+  int n_qubits;           /* 1 or 2 */
+  int qubits[4];
+  double params[5];
+  int param_index[5];
+  int n_data;             /* complex entries at data (0 if none) */
+  const vqc_c128 *data;   /* host memory, column-major blocks */
+} vqc_op;
+
+/* H = sum_t (coeff_re[t] + i coeff_im[t]) P_t with P_t|x> = i^{|Y|}
+ * (-1)^{popcount(x & z_mask)} |x ^ x_mask>: X on bit k sets x_mask bit k,
+ * Z sets z_mask bit k, Y sets both (Sec. 2.5).  Host arrays; coeff_im may be
+ * NULL (all zero). */
+typedef struct {
+  int n_terms;
+  const uint64_t *x_mask;
+  const uint64_t *z_mask;
+  const double *coeff_re;
+  const double *coeff_im;
+} vqc_pauli_sum;
+
+/* Fusion and launch shape (chosen by vqc_circuit_autotune or by hand).
+ * tile_bits: qubits per LDS tile (K); low_bits: contiguous low qubits every
+ * tile includes (c); reg_bits: qubits held per thread (R, 3 or 4);
+ * grid_blocks: persistent grid size (0 = one block per tile).  Zero fields
+ * take the library default. */
+typedef struct {
+  int tile_bits;
+  int low_bits;
+  int reg_bits;
+  int grid_blocks;
+} vqc_tune;
+
+typedef struct {
+  int n_ops;
+  int n_elementary;   /* ops after lowering (mixed: ket/bra halves, superops) */
+  int n_passes;       /* HBM passes of the forward plan */
+  int n_stages;       /* register stages over all passes */
+  int n_var;          /* derivative slots (variational parameters used) */
+  int n_params;
+  vqc_tune tune;
+  double alg_bytes_per_amp; /* algorithmic HBM bytes per amplitude, unfused ops */
+} vqc_circuit_stats;
+
+/* ------------------------------------------------------------------ misc */
+const char *vqc_status_string(int status);
+int vqc_version(void);
+
+/* Convert a textbook row-major 2^m x 2^m matrix whose qubits[0] is the MOST
+ * significant bit of the row/column index into this library's column-major
+ * matrix with qubits[0] as the least significant bit (the paper's
+ * n_qubits_mat_from_external, Sec. 2.2).  m in 1..4; host arrays. */
+vqc_status vqc_mat_from_external(int m, const vqc_c128 *row_major, vqc_c128 *out_col_major);
+
+/* ---------------------------------------------------------------- states */
+
+/* StateVector(n) / DensityMatrix(n) of Sec. 2.1.  dev_buf: caller-owned
+ * device buffer of 2^n (PURE) or 4^n (MIXED) complex128.  host_init: NULL
+ * writes |0..0> (resp. |0..0><0..0|), otherwise 2^n or 4^n host amplitudes
+ * that are copied in.  stream: hipStream_t (NULL = default stream).
+ * n_qubits: 1..33 (PURE), 1..16 (MIXED).  The handle does not own dev_buf. */
+vqc_status vqc_state_init(vqc_state *out, vqc_kind kind, int n_qubits, void *dev_buf,
+                          const vqc_c128 *host_init, void *stream);
+/* Rebind a state handle to another buffer/stream without touching data. */
+vqc_status vqc_state_rebind(vqc_state s, void *dev_buf, void *stream);
+vqc_status vqc_state_destroy(vqc_state s);
+
+/* Apply one m-qubit gate matrix (m = 1, 2), Eqs. (3) / (twoqubitgate).
+ * On a mixed state the gate acts as rho -> U rho U^dagger (Sec. 3.5: a gate
+ * is a one-Kraus channel).  Diagonal and controlled matrices are detected and
+ * take the kernels that touch only the amplitudes that change. */
+vqc_status vqc_apply_gate(vqc_state s, int m, const int *qubits, const vqc_c128 *matrix);
+
+/* Apply one typed op (Sec. 2.2 predefined gates, parametric gates with the
+ * values in op->params, or a channel on a mixed state).  Structured gates
+ * (diagonal, CZ, CNOT, fSim) use dedicated kernels. */
+vqc_status vqc_apply_op(vqc_state s, const vqc_op *op);
+
+/* QuantumMap(positions, kraus) on a MIXED state (Sec. 2.2, Eq. (channel));
+ * applied as the superoperator sum_s conj(K_s) (x) K_s on bits
+ * (qubits, qubits + n) of vec(rho) (Eq. (channel2)).  m = 1, 2. */
+vqc_status vqc_apply_channel(vqc_state s, int m, const int *qubits, int n_kraus,
+                             const vqc_c128 *kraus);
+
+/* expectation(op, state) of Sec. 2.5: <psi|H|psi> (PURE) or Tr(H rho) (MIXED),
+ * written to *out_host (synchronises the stream).  Deterministic FP64 two-stage
+ * reduction. */
+vqc_status vqc_expectation(vqc_state s, const vqc_pauli_sum *H, vqc_c128 *out_host);
+
+/* sum |psi_x|^2 (PURE) or Tr(rho) (MIXED) into *out_host (synchronises). */
+vqc_status vqc_norm(vqc_state s, double *out_host);
+
+/* Read `count` amplitudes psi[idx[i]] (PURE) into out_host (synchronises).
+ * idx_host: host int64 indices in [0, 2^n). */
+vqc_status vqc_gather(vqc_state s, int count, const int64_t *idx_host, vqc_c128 *out_host);
+
+/* ---------------------------------------------------------------- circuits */
+
+/* Build a circuit (QCircuit, Sec. 2.3) for states of `n_qubits` and `kind`,
+ * plan its fused HBM passes and upload its tables.  theta has n_params
+ * entries.  tune may be NULL (defaults).  ops and their data are copied. */
+vqc_status vqc_circuit_create(vqc_circuit *out, int n_qubits, vqc_kind kind, int n_ops,
+                              const vqc_op *ops, int n_params, const vqc_tune *tune);
+vqc_status vqc_circuit_destroy(vqc_circuit c);
+vqc_status vqc_circuit_stats_get(vqc_circuit c, vqc_circuit_stats *out);
+
+/* apply!(circ, state) of Sec. 2.4: run the whole circuit in place, as fused
+ * passes.  theta_dev: device double[n_params] (may be NULL when n_params = 0). */
+vqc_status vqc_apply_circuit(vqc_state s, vqc_circuit c, const double *theta_dev);
+
+/* gradient(loss, circ) with loss = Re<psi|H|psi> (PURE, Alg. 2) or Tr(H rho)
+ * (MIXED, Sec. 3.5), H with real coefficients.  s holds the final state
+ * produced by vqc_apply_circuit(c, theta) from |0..0> (or from init_dev).
+ * PURE: s is uncomputed in place back to the initial state (Phi <- Q^dagger
+ * Phi).  MIXED: s is left unchanged; the states before each op are recomputed
+ * from checkpoints of a forward re-run from init_dev (NULL = |0..0><0..0|),
+ * using at most checkpoint_budget_bytes of device memory (0 = library
+ * default).  grad_dev: device double[n_params], overwritten (parameters
+ * shared by several ops get the sum).  energy_host: optional loss value
+ * (synchronises when non-NULL). */
+vqc_status vqc_backward(vqc_circuit c, const double *theta_dev, vqc_state s,
+                        const vqc_pauli_sum *H, double *grad_dev, double *energy_host,
+                        const void *init_dev, size_t checkpoint_budget_bytes);
+
+/* Time candidate tunes for c on the scratch state s (contents destroyed) and
+ * re-plan c with the fastest; the chosen tune is written to *out. */
+vqc_status vqc_circuit_autotune(vqc_circuit c, vqc_state s, const double *theta_dev,
+                                vqc_tune *out);
+
+/* ---------------------------------------------------------------- batches */
+
+/* A batch of B items run together: item b applies circuits[b] (circuits may
+ * repeat and may have different widths) to states_dev[b] with parameters
+ * theta_dev[b].  All device pointers are bound at creation so the batch can
+ * be captured as a hipGraph.  Every circuit must share one tune.  stream:
+ * hipStream_t for all work. */
+vqc_status vqc_batch_create(vqc_batch *out, int B, const vqc_circuit *circuits,
+                            void *const *states_dev, const double *const *theta_dev,
+                            void *stream);
+vqc_status vqc_batch_destroy(vqc_batch b);
+
+/* Initialise every item to |0..0> (resp. |0..0><0..0|) and run the circuits:
+ * one persistent-grid launch per fused pass step for the whole batch. */
+vqc_status vqc_batch_forward(vqc_batch b);
+
+/* energies_dev[b] = loss of item b for the same H (device doubles). */
+vqc_status vqc_batch_expectation(vqc_batch b, const vqc_pauli_sum *H, double *energies_dev);
+
+/* Backward of every item after vqc_batch_forward (see vqc_backward):
+ * grads_dev[b] (device double[n_params of item b]), energies_dev (optional
+ * device double[B]).  Mixed items recompute from |0..0><0..0|. */
+vqc_status vqc_batch_backward(vqc_batch b, const vqc_pauli_sum *H, double *const *grads_dev,
+                              double *energies_dev, size_t checkpoint_budget_bytes);
+
+/* Capture forward + backward (H, grads, energies as above) into a hipGraph
+ * once; vqc_batch_replay launches it on the batch stream.  Capture queues no
+ * work.  Replays reuse the pointers bound at creation. */
+vqc_status vqc_batch_capture(vqc_batch b, const vqc_pauli_sum *H, double *const *grads_dev,
+                             double *energies_dev, size_t checkpoint_budget_bytes);
+vqc_status vqc_batch_replay(vqc_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VQC_ABI_INCLUDED */

@@ -1,0 +1,1306 @@
+// Host side of the C ABI (include/vqc.h): validation, lowering of ops to
+// register-level elementary ops, the fusion planner (HBM passes and register
+// stages), device tables, and launch orchestration on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/vqc.h"
+#include "vqc_internal.h"
+
+using namespace vqc;
+
+namespace {
+
+constexpr int kDefaultTile = 12;
+constexpr int kDefaultAdjTile = 11;
+constexpr int kDefaultLow = 4;
+constexpr int kR = 4;
+
+#define VQC_TRY(expr)                                         \
+  do {                                                        \
+    hipError_t _e = (expr);                                   \
+    if (_e != hipSuccess) return hip_status(_e);              \
+  } while (0)
+
+vqc_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return VQC_OK;
+  if (e == hipErrorOutOfMemory) return VQC_ERR_OOM;
+  return VQC_ERR_HIP;
+}
+
+bool is_finite_d(double v) { return std::isfinite(v); }
+
+// device allocation owned by a handle
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n && p) return hipSuccess;
+    release();
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) { p = nullptr; return e; }
+    n = bytes;
+    return hipSuccess;
+  }
+  template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// ------------------------------------------------------------------ ops
+
+int op_arity(int type) {
+  if (type >= VQC_X && type <= VQC_ID) return 1;
+  if (type >= VQC_CZ && type <= VQC_CONTROL) return 2;
+  if (type == VQC_AMPLITUDE_DAMPING || type == VQC_PHASE_DAMPING || type == VQC_DEPOLARIZING) return 1;
+  if (type == VQC_DEPOLARIZING2) return 2;
+  return 0;  // MATRIX, KRAUS: given by n_qubits
+}
+bool is_channel(int type) { return type >= VQC_AMPLITUDE_DAMPING && type <= VQC_KRAUS; }
+int n_params_of(int type) {
+  switch (type) {
+    case VQC_RX: case VQC_RY: case VQC_RZ: case VQC_CRX: case VQC_CRY: case VQC_CRZ: return 1;
+    case VQC_FSIM: return 5;
+    default: return 0;
+  }
+}
+bool valid_type(int t) {
+  return (t >= VQC_X && t <= VQC_ID) || (t >= VQC_CZ && t <= VQC_MATRIX) ||
+         (t >= VQC_AMPLITUDE_DAMPING && t <= VQC_KRAUS);
+}
+
+// register kind of a gate matrix (pure path)
+int gate_kind(int type, int m) {
+  switch (type) {
+    case VQC_Z: case VQC_S: case VQC_T: case VQC_RZ: return GK_DIAG1;
+    case VQC_ID: return GK_NONE;
+    case VQC_CZ: case VQC_CRZ: return GK_DIAG2;
+    case VQC_CNOT: return GK_CX;
+    case VQC_SWAP: case VQC_ISWAP: case VQC_FSIM: return GK_FSIM;
+    case VQC_CRX: case VQC_CRY: case VQC_CONTROL: return GK_DENSE2;
+    case VQC_MATRIX: return m == 1 ? GK_DENSE1 : GK_DENSE2;
+    default: return GK_DENSE1;
+  }
+}
+
+// row-major copy of a column-major ABI matrix
+void to_row_major(const vqc_c128 *cm, int d, std::vector<c128> &out) {
+  for (int r = 0; r < d; r++)
+    for (int c = 0; c < d; c++) out.push_back(make_double2(cm[r + d * c].re, cm[r + d * c].im));
+}
+
+vqc_status check_qubits(int m, const int *q, int n) {
+  for (int i = 0; i < m; i++) {
+    if (q[i] < 0 || q[i] >= n) return VQC_ERR_QUBIT;
+    for (int j = 0; j < i; j++)
+      if (q[i] == q[j]) return VQC_ERR_QUBIT;
+  }
+  return VQC_OK;
+}
+
+// sum_s K_s^dagger K_s == I within 1e-12 (column-major blocks)
+bool kraus_complete(int m, int nk, const vqc_c128 *K) {
+  const int d = 1 << m;
+  for (int r = 0; r < d; r++)
+    for (int c = 0; c < d; c++) {
+      double re = 0, im = 0;
+      for (int s = 0; s < nk; s++) {
+        const vqc_c128 *B = K + (size_t)s * d * d;
+        for (int k = 0; k < d; k++) {
+          // conj(K[k][r]) * K[k][c], element (row, col) at B[row + d col]
+          const vqc_c128 a = B[k + d * r], b = B[k + d * c];
+          re += a.re * b.re + a.im * b.im;
+          im += a.re * b.im - a.im * b.re;
+        }
+      }
+      if (std::fabs(re - (r == c ? 1.0 : 0.0)) > 1e-12 || std::fabs(im) > 1e-12) return false;
+    }
+  return true;
+}
+
+vqc_status validate_op(const vqc_op &op, int n, vqc_kind kind, int n_params) {
+  if (!valid_type(op.type)) return VQC_ERR_ARG;
+  const int ar = op_arity(op.type);
+  const int m = op.n_qubits;
+  if (m < 1 || m > 2) return VQC_ERR_UNSUPPORTED;
+  if (ar && ar != m) return VQC_ERR_ARG;
+  vqc_status st = check_qubits(m, op.qubits, n);
+  if (st) return st;
+  if (is_channel(op.type) && kind != VQC_MIXED) return VQC_ERR_KIND;
+  const int np = n_params_of(op.type);
+  for (int k = 0; k < 5; k++) {
+    if (!is_finite_d(op.params[k])) return VQC_ERR_NONFINITE;
+    if (op.param_index[k] >= 0) {
+      if (k >= np || op.param_index[k] >= n_params) return VQC_ERR_ARG;
+    }
+  }
+  const int d = 1 << m;
+  if (op.type == VQC_MATRIX) {
+    if (!op.data || op.n_data != d * d) return VQC_ERR_ARG;
+  } else if (op.type == VQC_CONTROL) {
+    if (!op.data || op.n_data != 4) return VQC_ERR_ARG;
+  } else if (op.type == VQC_KRAUS) {
+    if (!op.data || op.n_data <= 0 || op.n_data % (d * d) || op.n_data / (d * d) > 64) return VQC_ERR_ARG;
+  }
+  if (op.data)
+    for (int i = 0; i < op.n_data; i++)
+      if (!is_finite_d(op.data[i].re) || !is_finite_d(op.data[i].im)) return VQC_ERR_NONFINITE;
+  if (op.type == VQC_KRAUS && !kraus_complete(m, op.n_data / (d * d), op.data)) return VQC_ERR_NOT_CPTP;
+  if (op.type == VQC_AMPLITUDE_DAMPING || op.type == VQC_PHASE_DAMPING) {
+    if (op.params[0] < 0 || op.params[0] > 1) return VQC_ERR_ARG;
+  }
+  if (op.type == VQC_DEPOLARIZING && (op.params[0] < 0 || op.params[0] > 4.0 / 3.0)) return VQC_ERR_ARG;
+  if (op.type == VQC_DEPOLARIZING2 && (op.params[0] < 0 || op.params[0] > 16.0 / 15.0)) return VQC_ERR_ARG;
+  return VQC_OK;
+}
+
+bool unitary_rm(const c128 *G, int d) {
+  for (int r = 0; r < d; r++)
+    for (int c = 0; c < d; c++) {
+      double re = 0, im = 0;
+      for (int k = 0; k < d; k++) {
+        const c128 a = G[k * d + r], b = G[k * d + c];
+        re += a.x * b.x + a.y * b.y;
+        im += a.x * b.y - a.y * b.x;
+      }
+      if (std::fabs(re - (r == c)) > 1e-10 || std::fabs(im) > 1e-10) return false;
+    }
+  return true;
+}
+
+// ------------------------------------------------------------ lowering
+
+struct Deriv {
+  int kind;
+  int mat;
+  int param;   // theta index
+  int gslot;
+};
+
+struct Elem {
+  int kind;
+  int nq;
+  int q[4];    // global bits (vec(rho) bits for mixed)
+  int mat;     // matrix offset (c128 units), -1 if none
+  std::vector<Deriv> d;
+  uint64_t mask() const {
+    uint64_t m = 0;
+    for (int i = 0; i < nq; i++) m |= 1ull << q[i];
+    return m;
+  }
+};
+
+struct PassH {
+  int K;
+  std::vector<int> tq;  // ascending global bits
+  struct Stage {
+    int rbit[4];
+    std::vector<int> elems;  // indices into elems
+  };
+  std::vector<Stage> stages;
+};
+
+struct Plan {
+  bool reg_only = false;
+  int K = 0, R = kR, c = kDefaultLow;
+  std::vector<PassH> passes;
+  // device tables
+  DevBuf dev;
+  DPass *d_pass = nullptr;
+  DJob *d_jobs1 = nullptr;  // single-item jobs, one per pass
+  int n_stages = 0;
+  int64_t units_per_item = 0;  // tiles (LDS) or blocks of 256 tiles (register-only)
+};
+
+int popc(uint64_t v) { return __builtin_popcountll(v); }
+
+// First-fit fusion: walk the remaining ops in order; an op joins the pass if
+// its qubits fit in the tile (<= K bits, the low c bits always included) and
+// no earlier skipped op shares a qubit with it (program order on every qubit
+// is kept, ops on disjoint qubits commute).  Then split each pass into
+// register stages of R bits the same way.
+void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, bool reg_only, Plan &P,
+                 int max_var) {
+  P.passes.clear();
+  P.reg_only = reg_only;
+  P.K = reg_only ? R : K;
+  P.R = R;
+  P.c = c;
+  std::vector<int> rem;
+  for (size_t i = 0; i < E.size(); i++)
+    if (E[i].kind != GK_NONE) rem.push_back((int)i);
+  const int TK = reg_only ? R : K;
+  while (!rem.empty()) {
+    uint64_t tile = reg_only ? 0 : ((1ull << c) - 1);
+    uint64_t blocked = 0;
+    int nvar = 0;
+    std::vector<int> chosen, left;
+    for (int i : rem) {
+      const uint64_t m = E[i].mask();
+      if (m & blocked) { blocked |= m; left.push_back(i); continue; }
+      const uint64_t nt = tile | m;
+      const int nd = (int)E[i].d.size();
+      if (popc(nt) <= TK && (max_var <= 0 || nvar + nd <= max_var)) {
+        tile = nt;
+        nvar += nd;
+        chosen.push_back(i);
+      } else {
+        blocked |= m;
+        left.push_back(i);
+      }
+    }
+    rem.swap(left);
+    // pad the tile to exactly TK bits with the lowest unused bits
+    for (int b = 0; b < nbits && popc(tile) < TK; b++) tile |= 1ull << b;
+    PassH ph;
+    ph.K = TK;
+    for (int b = 0; b < nbits; b++)
+      if ((tile >> b) & 1) ph.tq.push_back(b);
+    int loc[64];
+    for (int i = 0; i < (int)ph.tq.size(); i++) loc[ph.tq[i]] = i;
+    // stages over tile-local bits
+    std::vector<int> srem = chosen;
+    while (!srem.empty()) {
+      uint64_t reg = 0, sblk = 0;
+      int order4[4] = {-1, -1, -1, -1};
+      std::vector<int> st, sleft;
+      for (int i : srem) {
+        uint64_t lm = 0;
+        for (int t = 0; t < E[i].nq; t++) lm |= 1ull << loc[E[i].q[t]];
+        bool ok = !(lm & sblk) && popc(reg | lm) <= R;
+        if (ok && E[i].kind == GK_DENSE4) {
+          if (order4[0] >= 0) {
+            for (int t = 0; t < 4; t++)
+              if (order4[t] != loc[E[i].q[t]]) ok = false;
+          } else if (reg & ~lm) {
+            ok = false;
+          }
+        }
+        if (ok && order4[0] >= 0 && (lm & ~reg)) ok = false;
+        if (!ok) { sblk |= lm; sleft.push_back(i); continue; }
+        reg |= lm;
+        st.push_back(i);
+        if (E[i].kind == GK_DENSE4 && order4[0] < 0)
+          for (int t = 0; t < 4; t++) order4[t] = loc[E[i].q[t]];
+      }
+      srem.swap(sleft);
+      PassH::Stage S;
+      if (order4[0] >= 0) {
+        for (int t = 0; t < 4; t++) S.rbit[t] = order4[t];
+      } else {
+        for (int b = 0; b < TK && popc(reg) < R; b++) reg |= 1ull << b;
+        int k = 0;
+        for (int b = 0; b < TK; b++)
+          if ((reg >> b) & 1) S.rbit[k++] = b;
+      }
+      S.elems = st;
+      ph.stages.push_back(S);
+      if (reg_only && !srem.empty()) {
+        // register-only passes hold exactly one stage: push the rest back
+        for (int i : srem) rem.push_back(i);
+        std::sort(rem.begin(), rem.end());
+        break;
+      }
+    }
+    P.passes.push_back(ph);
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- handles
+
+struct vqc_state_s {
+  vqc_kind kind;
+  int n;
+  int nbits;
+  c128 *buf;
+  hipStream_t stream;
+  DevBuf mat;     // single-op matrices
+  DevBuf red;     // expectation partials
+  DevBuf small;   // jobs / terms / results
+};
+
+struct vqc_circuit_s {
+  int n, nbits;
+  vqc_kind kind;
+  int n_params;
+  vqc_tune tune;
+  std::vector<vqc_op> ops;
+  std::vector<c128> cdata;
+  std::vector<DRecipe> recipes;
+  int mat_size = 0;
+  std::vector<Elem> elems;
+  int n_gslots = 0;
+  std::vector<int> gslot_param;
+  bool has_nonunitary_matrix = false;
+  Plan fwd, adj;   // pure: LDS forward + LDS adjoint; mixed: register-only, shared
+  DevBuf dconst;   // recipes, constant data, csr
+  DRecipe *d_rec = nullptr;
+  c128 *d_cdata = nullptr;
+  int32_t *d_csr_ptr = nullptr, *d_csr_slot = nullptr;
+  DevBuf mats1;    // single-item matrices
+  DevBuf psi1;     // single-item Psi (backward)
+  DevBuf part1;    // single-item partials
+  DevBuf ework;    // energy partials + result
+  DevBuf ck;       // mixed checkpoints
+  DevBuf small;
+  int64_t adj_units = 0;
+};
+
+struct vqc_batch_s {
+  int B;
+  std::vector<vqc_circuit> circ;
+  std::vector<c128 *> states;
+  std::vector<const double *> thetas;
+  hipStream_t stream;
+  bool reg_only;
+  int K, Kadj;
+  int max_passes = 0, max_adj = 0;
+  DevBuf mats, psi, part, tables, eparts, ck;
+  std::vector<size_t> mat_off, psi_off, part_off;
+  // grouped build launches
+  struct Group { vqc_circuit c; DevBuf ptrs; int count; };
+  std::vector<std::unique_ptr<Group>> groups;
+  DJob *d_fwd_jobs = nullptr;                 // concatenated per step
+  std::vector<int> fwd_first, fwd_count;      // per step
+  std::vector<int64_t> fwd_units;
+  DJob *d_adj_jobs = nullptr;
+  std::vector<int> adj_first, adj_count;
+  std::vector<int64_t> adj_units;
+  DEJob *d_ejobs = nullptr;                   // B expectation jobs (no out)
+  DEJob *d_sjobs = nullptr;                   // B seed jobs (out = Psi)
+  int64_t e_units = 0;
+  DGradJob *d_gjobs = nullptr;
+  int max_params = 0;
+  double2 *d_eres = nullptr;
+  DTerm *d_terms = nullptr;
+  int n_terms = 0;
+  std::vector<DTerm> terms_h;
+  c128 **d_state_ptrs = nullptr;
+  uint64_t *d_state_sizes = nullptr;
+  bool built = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  // mixed batches: checkpoint layout
+  int ck_stride = 0;
+  std::vector<size_t> ck_off;  // per item: base offset into ck (bytes)
+  size_t ck_per_item_states = 0;
+};
+
+namespace {
+
+// ---------------------------------------------------------- circuit build
+
+int add_recipe(vqc_circuit c, int type, int form, int k, int nq, const vqc_op &op, int data_off, int n_data,
+               int out_size) {
+  DRecipe r;
+  std::memset(&r, 0, sizeof(r));
+  r.type = type;
+  r.form = form;
+  r.k = k;
+  r.nq = nq;
+  r.out = c->mat_size;
+  r.data = data_off;
+  r.n_data = n_data;
+  for (int i = 0; i < 5; i++) {
+    r.pidx[i] = op.param_index[i];
+    r.pval[i] = op.params[i];
+  }
+  c->recipes.push_back(r);
+  c->mat_size += out_size;
+  return r.out;
+}
+
+vqc_status lower(vqc_circuit c) {
+  const int n = c->n;
+  const bool mixed = c->kind == VQC_MIXED;
+  for (size_t j = 0; j < c->ops.size(); j++) {
+    const vqc_op &op = c->ops[j];
+    const int m = op.n_qubits, d = 1 << m;
+    int data_off = -1, n_data = 0;
+    if (op.data && op.n_data > 0) {
+      data_off = (int)c->cdata.size();
+      const int blocks = op.n_data / (d * d);
+      for (int s = 0; s < blocks; s++) {
+        if (op.type == VQC_CONTROL) to_row_major(op.data, 2, c->cdata);
+        else to_row_major(op.data + (size_t)s * d * d, d, c->cdata);
+      }
+      n_data = op.n_data;
+    }
+    bool var = false;
+    for (int k = 0; k < 5; k++) var |= op.param_index[k] >= 0;
+    if (op.type == VQC_MATRIX) {
+      if (!unitary_rm(c->cdata.data() + data_off, d)) c->has_nonunitary_matrix = true;
+    }
+    auto new_deriv = [&](int kind, int mat, int k) {
+      Deriv dv;
+      dv.kind = kind;
+      dv.mat = mat;
+      dv.param = op.param_index[k];
+      dv.gslot = c->n_gslots++;
+      c->gslot_param.push_back(dv.param);
+      return dv;
+    };
+    if (is_channel(op.type)) {
+      Elem e;
+      e.nq = 2 * m;
+      e.kind = m == 1 ? GK_DENSE2 : GK_DENSE4;
+      for (int t = 0; t < m; t++) { e.q[t] = op.qubits[t]; e.q[t + m] = op.qubits[t] + n; }
+      e.mat = add_recipe(c, op.type, RF_SUPER_KRAUS, 0, m, op, data_off, n_data, d * d * d * d);
+      c->elems.push_back(e);
+      continue;
+    }
+    const int gk = gate_kind(op.type, m);
+    if (!mixed) {
+      Elem e;
+      e.nq = m;
+      e.kind = gk;
+      for (int t = 0; t < m; t++) e.q[t] = op.qubits[t];
+      e.mat = (gk == GK_CX || gk == GK_NONE) ? -1 : add_recipe(c, op.type, RF_GATE, 0, m, op, data_off, n_data, d * d);
+      for (int k = 0; k < 5; k++)
+        if (op.param_index[k] >= 0) {
+          const int dk = (m == 1) ? (gk == GK_DIAG1 ? GK_DIAG1 : GK_DENSE1) : GK_DENSE2;
+          const int mat = add_recipe(c, op.type, RF_DGATE, k, m, op, data_off, n_data, d * d);
+          e.d.push_back(new_deriv(dk, mat, k));
+        }
+      c->elems.push_back(e);
+    } else if (!var) {
+      Elem e;
+      e.nq = m;
+      e.kind = gk;
+      for (int t = 0; t < m; t++) e.q[t] = op.qubits[t];
+      e.mat = (gk == GK_CX || gk == GK_NONE) ? -1 : add_recipe(c, op.type, RF_GATE, 0, m, op, data_off, n_data, d * d);
+      c->elems.push_back(e);
+      for (int t = 0; t < m; t++) e.q[t] = op.qubits[t] + n;
+      e.mat = (gk == GK_CX || gk == GK_NONE) ? -1
+                                             : add_recipe(c, op.type, RF_GATE_CONJ, 0, m, op, data_off, n_data, d * d);
+      c->elems.push_back(e);
+    } else {
+      Elem e;
+      e.nq = 2 * m;
+      e.kind = m == 1 ? GK_DENSE2 : GK_DENSE4;
+      for (int t = 0; t < m; t++) { e.q[t] = op.qubits[t]; e.q[t + m] = op.qubits[t] + n; }
+      e.mat = add_recipe(c, op.type, RF_SUPER_GATE, 0, m, op, data_off, n_data, d * d * d * d);
+      for (int k = 0; k < 5; k++)
+        if (op.param_index[k] >= 0) {
+          const int mat = add_recipe(c, op.type, RF_DSUPER_GATE, k, m, op, data_off, n_data, d * d * d * d);
+          e.d.push_back(new_deriv(e.kind, mat, k));
+        }
+      c->elems.push_back(e);
+    }
+  }
+  return VQC_OK;
+}
+
+// upload pass tables of a plan; single-item jobs reference no buffers (the
+// kernel arguments supply them)
+vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
+  std::vector<DPass> passes(P.passes.size());
+  std::vector<DStage> stages;
+  std::vector<DGate> gates;
+  std::vector<DDeriv> derivs;
+  std::vector<int32_t> vslot;
+  std::vector<int> pass_stage0, pass_deriv0, pass_vslot0;
+  for (size_t p = 0; p < P.passes.size(); p++) {
+    const PassH &ph = P.passes[p];
+    int loc[64];
+    for (int i = 0; i < (int)ph.tq.size(); i++) loc[ph.tq[i]] = i;
+    pass_stage0.push_back((int)stages.size());
+    pass_deriv0.push_back((int)derivs.size());
+    pass_vslot0.push_back((int)vslot.size());
+    int nvar = 0;
+    for (const auto &S : ph.stages) {
+      DStage ds;
+      std::memset(&ds, 0, sizeof(ds));
+      int srt[4];
+      for (int i = 0; i < P.R; i++) { ds.rbit[i] = (int8_t)S.rbit[i]; srt[i] = S.rbit[i]; }
+      std::sort(srt, srt + P.R);
+      for (int i = 0; i < P.R; i++) ds.srt[i] = (int8_t)srt[i];
+      ds.g0 = (int)gates.size();
+      int regpos[64];
+      for (int i = 0; i < P.R; i++) regpos[S.rbit[i]] = i;
+      for (int ei : S.elems) {
+        const Elem &e = c->elems[ei];
+        DGate g;
+        std::memset(&g, 0, sizeof(g));
+        g.kind = (int8_t)e.kind;
+        g.nq = (int8_t)e.nq;
+        for (int t = 0; t < e.nq; t++) g.r[t] = (int8_t)regpos[loc[e.q[t]]];
+        g.mat = e.mat;
+        g.d0 = (int)derivs.size();
+        g.nd = adjoint ? (int16_t)e.d.size() : 0;
+        if (adjoint)
+          for (const Deriv &dv : e.d) {
+            DDeriv dd;
+            std::memset(&dd, 0, sizeof(dd));
+            dd.kind = (int8_t)dv.kind;
+            dd.mat = dv.mat;
+            dd.gslot = dv.gslot;
+            dd.local = nvar++;
+            vslot.push_back(dv.gslot);
+            derivs.push_back(dd);
+          }
+        gates.push_back(g);
+      }
+      ds.g1 = (int)gates.size();
+      stages.push_back(ds);
+    }
+    if (nvar > kMaxVarPerPass) return VQC_ERR_UNSUPPORTED;
+    DPass &dp = passes[p];
+    std::memset(&dp, 0, sizeof(dp));
+    dp.K = ph.K;
+    dp.nst = (int)ph.stages.size();
+    dp.nvar = nvar;
+    for (int i = 0; i < ph.K; i++) dp.tq[i] = (int8_t)ph.tq[i];
+  }
+  P.n_stages = (int)stages.size();
+  // one device blob: passes | jobs | stages | gates | derivs | vslot
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o_pass = 0;
+  const size_t o_jobs = al(o_pass + passes.size() * sizeof(DPass));
+  const size_t o_st = al(o_jobs + passes.size() * sizeof(DJob));
+  const size_t o_g = al(o_st + stages.size() * sizeof(DStage));
+  const size_t o_d = al(o_g + gates.size() * sizeof(DGate));
+  const size_t o_v = al(o_d + derivs.size() * sizeof(DDeriv));
+  const size_t total = al(o_v + vslot.size() * sizeof(int32_t));
+  VQC_TRY(P.dev.ensure(total));
+  char *base = P.dev.as<char>();
+  const int64_t tiles = int64_t(1) << (c->nbits - P.K);
+  P.units_per_item = P.reg_only ? (tiles + 255) / 256 : tiles;
+  std::vector<DJob> jobs(passes.size());
+  for (size_t p = 0; p < passes.size(); p++) {
+    passes[p].stages = reinterpret_cast<const DStage *>(base + o_st) + pass_stage0[p];
+    passes[p].gates = reinterpret_cast<const DGate *>(base + o_g);
+    passes[p].derivs = reinterpret_cast<const DDeriv *>(base + o_d);
+    passes[p].vslot = reinterpret_cast<const int32_t *>(base + o_v) + pass_vslot0[p];
+    DJob &j = jobs[p];
+    std::memset(&j, 0, sizeof(j));
+    j.pass = reinterpret_cast<const DPass *>(base + o_pass) + p;
+    j.unit0 = 0;
+    j.n_units = P.units_per_item;
+    j.nbits = c->nbits;
+  }
+  std::vector<char> blob(total, 0);
+  std::memcpy(blob.data() + o_pass, passes.data(), passes.size() * sizeof(DPass));
+  std::memcpy(blob.data() + o_jobs, jobs.data(), jobs.size() * sizeof(DJob));
+  std::memcpy(blob.data() + o_st, stages.data(), stages.size() * sizeof(DStage));
+  std::memcpy(blob.data() + o_g, gates.data(), gates.size() * sizeof(DGate));
+  std::memcpy(blob.data() + o_d, derivs.data(), derivs.size() * sizeof(DDeriv));
+  std::memcpy(blob.data() + o_v, vslot.data(), vslot.size() * sizeof(int32_t));
+  VQC_TRY(hipMemcpy(base, blob.data(), total, hipMemcpyHostToDevice));
+  P.d_pass = reinterpret_cast<DPass *>(base + o_pass);
+  P.d_jobs1 = reinterpret_cast<DJob *>(base + o_jobs);
+  return VQC_OK;
+}
+
+vqc_status make_plans(vqc_circuit c) {
+  const bool mixed = c->kind == VQC_MIXED;
+  const int nb = c->nbits;
+  int K = c->tune.tile_bits > 0 ? c->tune.tile_bits : kDefaultTile;
+  int low = c->tune.low_bits > 0 ? c->tune.low_bits : kDefaultLow;
+  if (K > kMaxTile) K = kMaxTile;
+  const bool reg_only = mixed || nb < 5;
+  const int R = std::min(kR, nb);
+  if (reg_only) {
+    plan_passes(c->elems, nb, R, 0, R, true, c->fwd, kMaxVarPerPass);
+    vqc_status st = upload_plan(c, c->fwd, false);
+    if (st) return st;
+    plan_passes(c->elems, nb, R, 0, R, true, c->adj, kMaxVarPerPass);
+    st = upload_plan(c, c->adj, true);
+    if (st) return st;
+  } else {
+    K = std::max(5, std::min(K, nb));
+    low = std::min(low, K - 1);
+    int Ka = std::max(5, std::min(std::min(K, kDefaultAdjTile), nb));
+    plan_passes(c->elems, nb, K, low, R, false, c->fwd, 0);
+    vqc_status st = upload_plan(c, c->fwd, false);
+    if (st) return st;
+    plan_passes(c->elems, nb, Ka, std::min(low, Ka - 1), R, false, c->adj, kMaxVarPerPass);
+    st = upload_plan(c, c->adj, true);
+    if (st) return st;
+  }
+  c->tune.tile_bits = c->fwd.K;
+  c->tune.low_bits = c->fwd.c;
+  c->tune.reg_bits = c->fwd.R;
+  return VQC_OK;
+}
+
+vqc_status upload_const(vqc_circuit c) {
+  // recipes | cdata | csr_ptr | csr_slot
+  std::vector<int32_t> ptr(c->n_params + 1, 0), slot;
+  std::vector<std::vector<int>> per(c->n_params);
+  for (int s = 0; s < c->n_gslots; s++) per[c->gslot_param[s]].push_back(s);
+  for (int p = 0; p < c->n_params; p++) {
+    ptr[p + 1] = ptr[p] + (int)per[p].size();
+    for (int s : per[p]) slot.push_back(s);
+  }
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o_r = 0, o_c = al(c->recipes.size() * sizeof(DRecipe));
+  const size_t o_p = al(o_c + c->cdata.size() * sizeof(c128));
+  const size_t o_s = al(o_p + ptr.size() * sizeof(int32_t));
+  const size_t total = al(o_s + slot.size() * sizeof(int32_t));
+  VQC_TRY(c->dconst.ensure(total));
+  std::vector<char> blob(total, 0);
+  std::memcpy(blob.data() + o_r, c->recipes.data(), c->recipes.size() * sizeof(DRecipe));
+  std::memcpy(blob.data() + o_c, c->cdata.data(), c->cdata.size() * sizeof(c128));
+  std::memcpy(blob.data() + o_p, ptr.data(), ptr.size() * sizeof(int32_t));
+  std::memcpy(blob.data() + o_s, slot.data(), slot.size() * sizeof(int32_t));
+  char *base = c->dconst.as<char>();
+  VQC_TRY(hipMemcpy(base, blob.data(), total, hipMemcpyHostToDevice));
+  c->d_rec = reinterpret_cast<DRecipe *>(base + o_r);
+  c->d_cdata = reinterpret_cast<c128 *>(base + o_c);
+  c->d_csr_ptr = reinterpret_cast<int32_t *>(base + o_p);
+  c->d_csr_slot = reinterpret_cast<int32_t *>(base + o_s);
+  VQC_TRY(c->mats1.ensure(std::max(1, c->mat_size) * sizeof(c128)));
+  return VQC_OK;
+}
+
+// terms with i^{|Y|} folded into the coefficient
+vqc_status make_terms(const vqc_pauli_sum *H, int nbits_q, std::vector<DTerm> &out, bool need_real) {
+  if (!H || H->n_terms < 0 || (H->n_terms > 0 && (!H->x_mask || !H->z_mask || !H->coeff_re)))
+    return VQC_ERR_ARG;
+  out.clear();
+  for (int t = 0; t < H->n_terms; t++) {
+    const uint64_t xm = H->x_mask[t], zm = H->z_mask[t];
+    if (nbits_q < 64 && ((xm | zm) >> nbits_q)) return VQC_ERR_QUBIT;
+    double cr = H->coeff_re[t], ci = H->coeff_im ? H->coeff_im[t] : 0.0;
+    if (!is_finite_d(cr) || !is_finite_d(ci)) return VQC_ERR_NONFINITE;
+    if (need_real && ci != 0.0) return VQC_ERR_NOT_HERMITIAN;
+    const int ny = popc(xm & zm) & 3;
+    double r = cr, i = ci;
+    for (int k = 0; k < ny; k++) { const double tr = -i; i = r; r = tr; }  // multiply by i
+    DTerm d;
+    d.xm = xm;
+    d.zm = zm;
+    d.cre = r;
+    d.cim = i;
+    out.push_back(d);
+  }
+  return VQC_OK;
+}
+
+int grid_of(vqc_circuit c, int64_t units) {
+  const int g = c->tune.grid_blocks;
+  if (g > 0 && g < units) return g;
+  return (int)std::min<int64_t>(units, int64_t(1) << 30);
+}
+
+// run passes [p0, p1) of a plan on one item (dir > 0: forward order)
+// mode 0: forward in place (b == nullptr) or a -> b; 1: pure adjoint; 2: mixed adjoint
+hipError_t run_passes(vqc_circuit c, Plan &P, int mode, c128 *a, c128 *b, const c128 *mats, double *partials,
+                      int p0, int p1, int dir, hipStream_t st) {
+  DOverride ov;
+  ov.a = a;
+  ov.b = b;
+  ov.mats = mats;
+  ov.partials = partials;
+  ov.mode = (mode == 0 && b) ? 1 : 0;
+  ov.use = 1;
+  const int grid = grid_of(c, P.units_per_item);
+  for (int k = 0; k < p1 - p0; k++) {
+    const int p = dir > 0 ? p0 + k : p1 - 1 - k;
+    hipError_t e;
+    if (P.reg_only) e = launch_pass_reg(P.R, mode, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
+    else e = launch_pass_lds(P.K, P.R, mode != 0, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+uint64_t state_len(vqc_kind kind, int n) { return kind == VQC_MIXED ? (1ull << (2 * n)) : (1ull << n); }
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+const char *vqc_status_string(int st) {
+  switch (st) {
+    case VQC_OK: return "ok";
+    case VQC_ERR_ARG: return "invalid argument";
+    case VQC_ERR_QUBIT: return "qubit out of range or repeated";
+    case VQC_ERR_UNSUPPORTED: return "unsupported op or combination";
+    case VQC_ERR_KIND: return "pure/mixed state kind mismatch";
+    case VQC_ERR_NOT_CPTP: return "Kraus operators are not trace preserving";
+    case VQC_ERR_NONFINITE: return "non-finite input";
+    case VQC_ERR_OOM: return "device out of memory";
+    case VQC_ERR_HIP: return "HIP runtime error";
+    case VQC_ERR_NOT_HERMITIAN: return "observable must have real coefficients";
+    case VQC_ERR_NOT_UNITARY: return "gate matrix is not unitary";
+    default: return "unknown status";
+  }
+}
+
+int vqc_version(void) { return 100; }
+
+vqc_status vqc_mat_from_external(int m, const vqc_c128 *rm, vqc_c128 *out) {
+  if (m < 1 || m > 4 || !rm || !out) return VQC_ERR_ARG;
+  const int d = 1 << m;
+  auto rev = [m](int x) {
+    int r = 0;
+    for (int t = 0; t < m; t++)
+      if ((x >> t) & 1) r |= 1 << (m - 1 - t);
+    return r;
+  };
+  for (int lo = 0; lo < d; lo++)
+    for (int li = 0; li < d; li++) out[lo + d * li] = rm[rev(lo) * d + rev(li)];
+  return VQC_OK;
+}
+
+// --------------------------------------------------------------- states
+
+vqc_status vqc_state_init(vqc_state *out, vqc_kind kind, int n, void *dev_buf, const vqc_c128 *host_init,
+                          void *stream) {
+  if (!out || !dev_buf) return VQC_ERR_ARG;
+  if (kind != VQC_PURE && kind != VQC_MIXED) return VQC_ERR_ARG;
+  if (n < 1 || (kind == VQC_PURE && n > 33) || (kind == VQC_MIXED && n > 16)) return VQC_ERR_ARG;
+  const uint64_t N = state_len(kind, n);
+  if (host_init)
+    for (uint64_t i = 0; i < N; i++)
+      if (!is_finite_d(host_init[i].re) || !is_finite_d(host_init[i].im)) return VQC_ERR_NONFINITE;
+  vqc_state s = new (std::nothrow) vqc_state_s();
+  if (!s) return VQC_ERR_OOM;
+  s->kind = kind;
+  s->n = n;
+  s->nbits = kind == VQC_MIXED ? 2 * n : n;
+  s->buf = reinterpret_cast<c128 *>(dev_buf);
+  s->stream = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = s->mat.ensure(512 * sizeof(c128));
+  if (e == hipSuccess) {
+    if (host_init) {
+      e = hipMemcpyAsync(s->buf, host_init, N * sizeof(c128), hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    } else {
+      e = launch_init_basis0(s->buf, N, s->stream);
+    }
+  }
+  if (e != hipSuccess) {
+    delete s;
+    return hip_status(e);
+  }
+  *out = s;
+  return VQC_OK;
+}
+
+vqc_status vqc_state_rebind(vqc_state s, void *dev_buf, void *stream) {
+  if (!s || !dev_buf) return VQC_ERR_ARG;
+  s->buf = reinterpret_cast<c128 *>(dev_buf);
+  s->stream = reinterpret_cast<hipStream_t>(stream);
+  return VQC_OK;
+}
+
+vqc_status vqc_state_destroy(vqc_state s) {
+  delete s;
+  return VQC_OK;
+}
+
+static bool is_zero(const c128 &v) { return v.x == 0.0 && v.y == 0.0; }
+static bool is_one(const c128 &v) { return v.x == 1.0 && v.y == 0.0; }
+
+// structure of a row-major gate matrix for the single-op kernels
+static int single_kind(int m, const c128 *G) {
+  if (m == 1) {
+    if (is_zero(G[1]) && is_zero(G[2])) return is_one(G[0]) ? SK_PHASE1 : SK_DIAG1;
+    return SK_DENSE1;
+  }
+  bool diag = true, ctrl = true, fsim = true;
+  for (int r = 0; r < 4; r++)
+    for (int c = 0; c < 4; c++) {
+      const bool z = is_zero(G[r * 4 + c]);
+      if (r != c && !z) diag = false;
+      const bool in_ctrl = (r & 1) && (c & 1);
+      if (!in_ctrl && !((r == c) ? is_one(G[r * 4 + c]) : z)) ctrl = false;
+      const bool in_f = (r == c) || (r == 1 && c == 2) || (r == 2 && c == 1);
+      if (!in_f && !z) fsim = false;
+    }
+  if (diag) return (is_one(G[0]) && is_one(G[5]) && is_one(G[10])) ? SK_PHASE11 : SK_DIAG2;
+  if (ctrl) {
+    if (is_zero(G[5]) && is_one(G[7]) && is_one(G[13]) && is_zero(G[15])) return SK_CX;
+    return SK_CTRL;
+  }
+  if (fsim && is_one(G[0])) return SK_FSIM;
+  return SK_DENSE2;
+}
+
+static hipError_t apply_single(vqc_state s, int m, const int *q, const c128 *dev_mat, int kind) {
+  if (m == 1) return launch_g1(s->buf, s->nbits, q[0], dev_mat, kind, s->stream);
+  return launch_g2(s->buf, s->nbits, q[0], q[1], dev_mat, kind, s->stream);
+}
+
+vqc_status vqc_apply_gate(vqc_state s, int m, const int *qubits, const vqc_c128 *matrix) {
+  if (!s || !qubits || !matrix) return VQC_ERR_ARG;
+  if (m < 1 || m > 2) return VQC_ERR_UNSUPPORTED;
+  vqc_status st = check_qubits(m, qubits, s->n);
+  if (st) return st;
+  const int d = 1 << m;
+  for (int i = 0; i < d * d; i++)
+    if (!is_finite_d(matrix[i].re) || !is_finite_d(matrix[i].im)) return VQC_ERR_NONFINITE;
+  std::vector<c128> G;
+  to_row_major(matrix, d, G);
+  const int kind = single_kind(m, G.data());
+  c128 *dm = s->mat.as<c128>();
+  VQC_TRY(launch_set_mat(dm, G.data(), d * d, s->stream));
+  VQC_TRY(apply_single(s, m, qubits, dm, kind));
+  if (s->kind == VQC_MIXED) {
+    // rho -> U rho U^dagger: conj(U) on the bra bits
+    std::vector<c128> Gc(G);
+    for (auto &v : Gc) v.y = -v.y;
+    int qb[2] = {qubits[0] + s->n, m > 1 ? qubits[1] + s->n : 0};
+    VQC_TRY(launch_set_mat(dm + 16, Gc.data(), d * d, s->stream));
+    VQC_TRY(apply_single(s, m, qb, dm + 16, kind));
+  }
+  return VQC_OK;
+}
+
+static int typed_kind(int type) {
+  switch (type) {
+    case VQC_Z: case VQC_S: case VQC_T: return SK_PHASE1;
+    case VQC_RZ: return SK_DIAG1;
+    case VQC_CZ: return SK_PHASE11;
+    case VQC_CNOT: return SK_CX;
+    case VQC_SWAP: case VQC_ISWAP: case VQC_FSIM: return SK_FSIM;
+    case VQC_CRX: case VQC_CRY: case VQC_CRZ: return SK_CTRL;
+    default: return op_arity(type) == 2 ? SK_DENSE2 : SK_DENSE1;
+  }
+}
+
+static vqc_status apply_channel_dev(vqc_state s, int m, const int *q, int type, double prm, const std::vector<c128> &kraus_rm,
+                                    int n_data);
+
+vqc_status vqc_apply_op(vqc_state s, const vqc_op *op) {
+  if (!s || !op) return VQC_ERR_ARG;
+  vqc_op o = *op;
+  for (int k = 0; k < 5; k++) o.param_index[k] = -1;  // values, not variational slots
+  vqc_status st = validate_op(o, s->n, s->kind, 0);
+  if (st) return st;
+  const int m = o.n_qubits, d = 1 << m;
+  if (is_channel(o.type)) {
+    std::vector<c128> K;
+    if (o.type == VQC_KRAUS)
+      for (int b = 0; b < o.n_data / (d * d); b++) to_row_major(o.data + (size_t)b * d * d, d, K);
+    return apply_channel_dev(s, m, o.qubits, o.type, o.params[0], K, o.n_data);
+  }
+  if (o.type == VQC_MATRIX) return vqc_apply_gate(s, m, o.qubits, o.data);
+  if (o.type == VQC_CONTROL) {
+    vqc_c128 full[16];
+    std::memset(full, 0, sizeof(full));
+    full[0 + 4 * 0].re = 1;
+    full[2 + 4 * 2].re = 1;
+    // column-major (out, in) at [out + 4 in]; control=1 block at local 1, 3
+    full[1 + 4 * 1] = o.data[0 + 2 * 0];
+    full[1 + 4 * 3] = o.data[0 + 2 * 1];
+    full[3 + 4 * 1] = o.data[1 + 2 * 0];
+    full[3 + 4 * 3] = o.data[1 + 2 * 1];
+    return vqc_apply_gate(s, 2, o.qubits, full);
+  }
+  if (o.type == VQC_ID) return VQC_OK;
+  DRecipe r;
+  std::memset(&r, 0, sizeof(r));
+  r.type = o.type;
+  r.form = RF_GATE;
+  r.nq = m;
+  r.data = -1;
+  for (int k = 0; k < 5; k++) { r.pidx[k] = -1; r.pval[k] = o.params[k]; }
+  c128 *dm = s->mat.as<c128>();
+  const int kind = typed_kind(o.type);
+  VQC_TRY(launch_build_one(r, nullptr, dm, s->stream));
+  VQC_TRY(apply_single(s, m, o.qubits, dm, kind));
+  if (s->kind == VQC_MIXED) {
+    r.form = RF_GATE_CONJ;
+    VQC_TRY(launch_build_one(r, nullptr, dm + 16, s->stream));
+    int qb[2] = {o.qubits[0] + s->n, m > 1 ? o.qubits[1] + s->n : 0};
+    VQC_TRY(apply_single(s, m, qb, dm + 16, kind));
+  }
+  return VQC_OK;
+}
+
+static vqc_status apply_channel_dev(vqc_state s, int m, const int *q, int type, double prm,
+                                    const std::vector<c128> &kraus_rm, int n_data) {
+  c128 *dm = s->mat.as<c128>();
+  c128 *kd = dm + 256;  // Kraus data scratch (up to 256 entries)
+  if (!kraus_rm.empty()) {
+    if (kraus_rm.size() > 256) {
+      VQC_TRY(s->small.ensure(kraus_rm.size() * sizeof(c128)));
+      kd = s->small.as<c128>();
+    }
+    VQC_TRY(hipMemcpyAsync(kd, kraus_rm.data(), kraus_rm.size() * sizeof(c128), hipMemcpyHostToDevice, s->stream));
+    VQC_TRY(hipStreamSynchronize(s->stream));
+  }
+  DRecipe r;
+  std::memset(&r, 0, sizeof(r));
+  r.type = type;
+  r.form = RF_SUPER_KRAUS;
+  r.nq = m;
+  r.data = kraus_rm.empty() ? -1 : 0;
+  r.n_data = n_data;
+  for (int k = 0; k < 5; k++) r.pidx[k] = -1;
+  r.pval[0] = prm;
+  VQC_TRY(launch_build_one(r, kraus_rm.empty() ? nullptr : kd, dm, s->stream));
+  if (m == 1) {
+    VQC_TRY(launch_g2(s->buf, s->nbits, q[0], q[0] + s->n, dm, SK_DENSE2, s->stream));
+  } else {
+    const int qq[4] = {q[0], q[1], q[0] + s->n, q[1] + s->n};
+    VQC_TRY(launch_gm(s->buf, s->nbits, 4, qq, dm, s->stream));
+  }
+  if (!kraus_rm.empty()) VQC_TRY(hipStreamSynchronize(s->stream));  // scratch reuse
+  return VQC_OK;
+}
+
+vqc_status vqc_apply_channel(vqc_state s, int m, const int *qubits, int n_kraus, const vqc_c128 *kraus) {
+  if (!s || !qubits || !kraus || n_kraus < 1) return VQC_ERR_ARG;
+  if (s->kind != VQC_MIXED) return VQC_ERR_KIND;
+  if (m < 1 || m > 2) return VQC_ERR_UNSUPPORTED;
+  vqc_op o;
+  std::memset(&o, 0, sizeof(o));
+  o.type = VQC_KRAUS;
+  o.n_qubits = m;
+  for (int i = 0; i < m; i++) o.qubits[i] = qubits[i];
+  for (int k = 0; k < 5; k++) o.param_index[k] = -1;
+  o.n_data = n_kraus * (1 << m) * (1 << m);
+  o.data = kraus;
+  return vqc_apply_op(s, &o);
+}
+
+static vqc_status expect_into(vqc_state s, const std::vector<DTerm> &terms, vqc_c128 *out) {
+  const int iter_bits = s->n;  // pure: all amplitudes; mixed: the 2^n diagonal
+  const int64_t units = expect_units(iter_bits);
+  VQC_TRY(s->red.ensure(units * sizeof(double2) + 64));
+  const size_t tb = std::max<size_t>(1, terms.size()) * sizeof(DTerm);
+  VQC_TRY(s->small.ensure(tb + sizeof(DEJob) + 2 * sizeof(double2) + 512));
+  char *sm = s->small.as<char>();
+  DTerm *dterms = reinterpret_cast<DTerm *>(sm);
+  DEJob *djob = reinterpret_cast<DEJob *>(sm + ((tb + 255) & ~size_t(255)));
+  double2 *dres = reinterpret_cast<double2 *>(reinterpret_cast<char *>(djob) + 256);
+  DEJob j;
+  std::memset(&j, 0, sizeof(j));
+  j.psi = s->buf;
+  j.out = nullptr;
+  j.partial = s->red.as<double2>();
+  j.unit0 = 0;
+  j.n_units = units;
+  j.nbits = s->n;
+  j.mixed = s->kind == VQC_MIXED;
+  if (!terms.empty())
+    VQC_TRY(hipMemcpyAsync(dterms, terms.data(), terms.size() * sizeof(DTerm), hipMemcpyHostToDevice, s->stream));
+  VQC_TRY(hipMemcpyAsync(djob, &j, sizeof(j), hipMemcpyHostToDevice, s->stream));
+  VQC_TRY(launch_expect(djob, 1, units, dterms, (int)terms.size(), s->stream));
+  VQC_TRY(launch_reduce_partials(djob, 1, dres, s->stream));
+  double2 r;
+  VQC_TRY(hipMemcpyAsync(&r, dres, sizeof(r), hipMemcpyDeviceToHost, s->stream));
+  VQC_TRY(hipStreamSynchronize(s->stream));
+  out->re = r.x;
+  out->im = r.y;
+  return VQC_OK;
+}
+
+vqc_status vqc_expectation(vqc_state s, const vqc_pauli_sum *H, vqc_c128 *out) {
+  if (!s || !H || !out) return VQC_ERR_ARG;
+  std::vector<DTerm> terms;
+  vqc_status st = make_terms(H, s->n, terms, false);
+  if (st) return st;
+  return expect_into(s, terms, out);
+}
+
+vqc_status vqc_norm(vqc_state s, double *out) {
+  if (!s || !out) return VQC_ERR_ARG;
+  std::vector<DTerm> terms(1);
+  terms[0].xm = terms[0].zm = 0;
+  terms[0].cre = 1.0;
+  terms[0].cim = 0.0;
+  vqc_c128 r;
+  vqc_status st = expect_into(s, terms, &r);
+  if (st) return st;
+  *out = r.re;
+  return VQC_OK;
+}
+
+vqc_status vqc_gather(vqc_state s, int count, const int64_t *idx, vqc_c128 *out) {
+  if (!s || count < 0 || (count > 0 && (!idx || !out))) return VQC_ERR_ARG;
+  if (s->kind != VQC_PURE) return VQC_ERR_KIND;
+  if (count == 0) return VQC_OK;
+  const int64_t N = int64_t(1) << s->n;
+  for (int i = 0; i < count; i++)
+    if (idx[i] < 0 || idx[i] >= N) return VQC_ERR_ARG;
+  VQC_TRY(s->small.ensure(count * (sizeof(int64_t) + sizeof(c128)) + 256));
+  int64_t *di = s->small.as<int64_t>();
+  c128 *dout = reinterpret_cast<c128 *>(reinterpret_cast<char *>(di) + ((count * sizeof(int64_t) + 255) & ~size_t(255)));
+  VQC_TRY(hipMemcpyAsync(di, idx, count * sizeof(int64_t), hipMemcpyHostToDevice, s->stream));
+  VQC_TRY(launch_gather(s->buf, di, count, dout, s->stream));
+  VQC_TRY(hipMemcpyAsync(out, dout, count * sizeof(c128), hipMemcpyDeviceToHost, s->stream));
+  VQC_TRY(hipStreamSynchronize(s->stream));
+  return VQC_OK;
+}
+
+// -------------------------------------------------------------- circuits
+
+vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops, const vqc_op *ops, int n_params,
+                              const vqc_tune *tune) {
+  if (!out || n_ops < 0 || (n_ops > 0 && !ops) || n_params < 0) return VQC_ERR_ARG;
+  if (kind != VQC_PURE && kind != VQC_MIXED) return VQC_ERR_ARG;
+  if (n < 1 || (kind == VQC_PURE && n > 33) || (kind == VQC_MIXED && n > 16)) return VQC_ERR_ARG;
+  if (tune && (tune->tile_bits < 0 || tune->tile_bits > kMaxTile || tune->low_bits < 0 || tune->grid_blocks < 0 ||
+               (tune->reg_bits != 0 && tune->reg_bits != kR)))
+    return VQC_ERR_ARG;
+  for (int j = 0; j < n_ops; j++) {
+    vqc_status st = validate_op(ops[j], n, kind, n_params);
+    if (st) return st;
+  }
+  std::unique_ptr<vqc_circuit_s> c(new (std::nothrow) vqc_circuit_s());
+  if (!c) return VQC_ERR_OOM;
+  c->n = n;
+  c->kind = kind;
+  c->nbits = kind == VQC_MIXED ? 2 * n : n;
+  c->n_params = n_params;
+  std::memset(&c->tune, 0, sizeof(c->tune));
+  if (tune) c->tune = *tune;
+  c->ops.assign(ops, ops + n_ops);
+  vqc_status st = lower(c.get());
+  for (auto &o : c->ops) o.data = nullptr;  // data copied into cdata
+  if (st) return st;
+  st = make_plans(c.get());
+  if (st) return st;
+  st = upload_const(c.get());
+  if (st) return st;
+  *out = c.release();
+  return VQC_OK;
+}
+
+vqc_status vqc_circuit_destroy(vqc_circuit c) {
+  delete c;
+  return VQC_OK;
+}
+
+vqc_status vqc_circuit_stats_get(vqc_circuit c, vqc_circuit_stats *out) {
+  if (!c || !out) return VQC_ERR_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->n_ops = (int)c->ops.size();
+  out->n_elementary = (int)c->elems.size();
+  out->n_passes = (int)c->fwd.passes.size();
+  out->n_stages = c->fwd.n_stages;
+  out->n_var = c->n_gslots;
+  out->n_params = c->n_params;
+  out->tune = c->tune;
+  // algorithmic bytes per amplitude of the unfused ops (reads + writes of the
+  // amplitudes each op must touch): dense 32 B, phase on |1> 16 B, CZ 8 B,
+  // CNOT 16 B, fSim 24 B
+  double b = 0;
+  for (const Elem &e : c->elems) {
+    switch (e.kind) {
+      case GK_DIAG2: b += 32; break;
+      case GK_CX: b += 16; break;
+      case GK_FSIM: b += 24; break;
+      case GK_NONE: break;
+      default: b += 32; break;
+    }
+  }
+  out->alg_bytes_per_amp = b;
+  return VQC_OK;
+}
+
+vqc_status vqc_apply_circuit(vqc_state s, vqc_circuit c, const double *theta) {
+  if (!s || !c) return VQC_ERR_ARG;
+  if (s->kind != c->kind || s->n != c->n) return VQC_ERR_KIND;
+  if (c->n_params > 0 && !theta) return VQC_ERR_ARG;
+  c128 *mats = c->mats1.as<c128>();
+  VQC_TRY(launch_build_mats(c->d_rec, (int)c->recipes.size(), c->d_cdata, nullptr, nullptr, 1, theta, mats, s->stream));
+  VQC_TRY(run_passes(c, c->fwd, 0, s->buf, nullptr, mats, nullptr, 0, (int)c->fwd.passes.size(), 1, s->stream));
+  return VQC_OK;
+}
+
+static vqc_status seed_and_energy(vqc_circuit c, const std::vector<DTerm> &terms, const c128 *psi, c128 *out,
+                                  hipStream_t st, double2 **res) {
+  // expectation (and H psi when out != nullptr) of one item
+  const int64_t units = expect_units(c->n);
+  const size_t tb = ((std::max<size_t>(1, terms.size()) * sizeof(DTerm)) + 255) & ~size_t(255);
+  VQC_TRY(c->ework.ensure(units * sizeof(double2) + tb + 1024));
+  char *base = c->ework.as<char>();
+  double2 *part = reinterpret_cast<double2 *>(base);
+  char *rest = base + ((units * sizeof(double2) + 255) & ~size_t(255));
+  DTerm *dterms = reinterpret_cast<DTerm *>(rest);
+  DEJob *djob = reinterpret_cast<DEJob *>(rest + tb);
+  double2 *dres = reinterpret_cast<double2 *>(rest + tb + 256);
+  DEJob j;
+  std::memset(&j, 0, sizeof(j));
+  j.psi = psi;
+  j.out = out;
+  j.partial = part;
+  j.n_units = units;
+  j.nbits = c->n;
+  j.mixed = c->kind == VQC_MIXED;
+  if (!terms.empty())
+    VQC_TRY(hipMemcpyAsync(dterms, terms.data(), terms.size() * sizeof(DTerm), hipMemcpyHostToDevice, st));
+  VQC_TRY(hipMemcpyAsync(djob, &j, sizeof(j), hipMemcpyHostToDevice, st));
+  VQC_TRY(hipStreamSynchronize(st));  // host sources above are locals
+  VQC_TRY(launch_expect(djob, 1, units, dterms, (int)terms.size(), st));
+  VQC_TRY(launch_reduce_partials(djob, 1, dres, st));
+  *res = dres;
+  return VQC_OK;
+}
+
+vqc_status vqc_backward(vqc_circuit c, const double *theta, vqc_state s, const vqc_pauli_sum *H, double *grad,
+                        double *energy_host, const void *init_dev, size_t budget) {
+  if (!c || !s || !H) return VQC_ERR_ARG;
+  if (s->kind != c->kind || s->n != c->n) return VQC_ERR_KIND;
+  if (c->n_params > 0 && (!theta || !grad)) return VQC_ERR_ARG;
+  std::vector<DTerm> terms;
+  vqc_status vs = make_terms(H, c->n, terms, true);
+  if (vs) return vs;
+  hipStream_t st = s->stream;
+  const uint64_t N = state_len(c->kind, c->n);
+  c128 *mats = c->mats1.as<c128>();
+  Plan &P = c->adj;
+  const int np = (int)P.passes.size();
+  VQC_TRY(c->part1.ensure(std::max<size_t>(1, (size_t)c->n_gslots) * P.units_per_item * sizeof(double) + 256));
+  double2 *dres = nullptr;
+  if (c->kind == VQC_PURE) {
+    if (c->has_nonunitary_matrix) return VQC_ERR_NOT_UNITARY;
+    VQC_TRY(c->psi1.ensure(N * sizeof(c128)));
+    c128 *psi = c->psi1.as<c128>();
+    VQC_TRY(launch_build_mats(c->d_rec, (int)c->recipes.size(), c->d_cdata, nullptr, nullptr, 1, theta, mats, st));
+    vs = seed_and_energy(c, terms, s->buf, psi, st, &dres);
+    if (vs) return vs;
+    VQC_TRY(run_passes(c, P, 1, s->buf, psi, mats, c->part1.as<double>(), 0, np, -1, st));
+  } else {
+    // checkpoints every `stride` passes; a segment of states is recomputed
+    // from its checkpoint before its backward steps
+    const size_t SB = N * sizeof(c128);
+    size_t bud = budget ? budget : (size_t)16 << 30;
+    int best = -1;
+    size_t best_need = 0;
+    for (int sd = 1; sd <= std::max(1, np); sd++) {
+      const size_t need = (size_t)((np + sd - 1) / sd + (sd - 1) + 2) * SB;
+      if (need <= bud && (best < 0 || need < best_need)) { best = sd; best_need = need; }
+    }
+    if (best < 0) return VQC_ERR_OOM;
+    const int sd = best;
+    const int nck = (np + sd - 1) / sd;
+    VQC_TRY(c->ck.ensure(best_need));
+    c128 *W = c->ck.as<c128>();
+    c128 *psi = W + N;
+    c128 *ck0 = psi + N;
+    c128 *seg0 = ck0 + (size_t)nck * N;
+    VQC_TRY(launch_build_mats(c->d_rec, (int)c->recipes.size(), c->d_cdata, nullptr, nullptr, 1, theta, mats, st));
+    if (init_dev) VQC_TRY(launch_copy(W, reinterpret_cast<const c128 *>(init_dev), N, st));
+    else VQC_TRY(launch_init_basis0(W, N, st));
+    for (int p = 0; p < np; p++) {
+      if (p % sd == 0) VQC_TRY(launch_copy(ck0 + (size_t)(p / sd) * N, W, N, st));
+      VQC_TRY(run_passes(c, c->fwd, 0, W, nullptr, mats, nullptr, p, p + 1, 1, st));
+    }
+    {
+      // vec(H) needs the terms on device
+      std::vector<DTerm> tt = terms;
+      VQC_TRY(c->small.ensure(std::max<size_t>(1, tt.size()) * sizeof(DTerm)));
+      if (!tt.empty())
+        VQC_TRY(hipMemcpyAsync(c->small.p, tt.data(), tt.size() * sizeof(DTerm), hipMemcpyHostToDevice, st));
+      VQC_TRY(hipStreamSynchronize(st));
+      VQC_TRY(launch_seed_mixed(psi, c->n, c->small.as<DTerm>(), (int)tt.size(), st));
+    }
+    vs = seed_and_energy(c, terms, W, nullptr, st, &dres);
+    if (vs) return vs;
+    for (int k = nck - 1; k >= 0; k--) {
+      const int s0 = k * sd, s1 = std::min(np, s0 + sd);
+      auto segp = [&](int i) { return i == 0 ? ck0 + (size_t)k * N : seg0 + (size_t)(i - 1) * N; };
+      for (int i = 1; i < s1 - s0; i++)
+        VQC_TRY(run_passes(c, c->fwd, 0, segp(i - 1), segp(i), mats, nullptr, s0 + i - 1, s0 + i, 1, st));
+      for (int p = s1 - 1; p >= s0; p--)
+        VQC_TRY(run_passes(c, P, 2, segp(p - s0), psi, mats, c->part1.as<double>(), p, p + 1, 1, st));
+    }
+  }
+  if (c->n_params > 0) {
+    DGradJob gj;
+    gj.partials = c->part1.as<double>();
+    gj.n_units = P.units_per_item;
+    gj.grad = grad;
+    gj.csr_ptr = c->d_csr_ptr;
+    gj.csr_slot = c->d_csr_slot;
+    gj.n_params = c->n_params;
+    gj.scale = c->kind == VQC_PURE ? 2.0 : 1.0;
+    VQC_TRY(c->small.ensure(sizeof(DGradJob) + 256));
+    DGradJob *dg = reinterpret_cast<DGradJob *>(c->small.as<char>());
+    VQC_TRY(hipMemcpyAsync(dg, &gj, sizeof(gj), hipMemcpyHostToDevice, st));
+    VQC_TRY(hipStreamSynchronize(st));
+    VQC_TRY(launch_grad_reduce(dg, 1, c->n_params, st));
+  }
+  if (energy_host) {
+    double2 r;
+    VQC_TRY(hipMemcpyAsync(&r, dres, sizeof(r), hipMemcpyDeviceToHost, st));
+    VQC_TRY(hipStreamSynchronize(st));
+    *energy_host = r.x;
+  }
+  return VQC_OK;
+}
+
+vqc_status vqc_circuit_autotune(vqc_circuit c, vqc_state s, const double *theta, vqc_tune *out) {
+  if (!c || !s || !out) return VQC_ERR_ARG;
+  if (s->kind != c->kind || s->n != c->n) return VQC_ERR_KIND;
+  if (c->n_params > 0 && !theta) return VQC_ERR_ARG;
+  if (c->kind == VQC_MIXED || c->nbits < 5) {
+    *out = c->tune;
+    return VQC_OK;
+  }
+  hipEvent_t e0, e1;
+  VQC_TRY(hipEventCreate(&e0));
+  VQC_TRY(hipEventCreate(&e1));
+  const vqc_tune orig = c->tune;
+  vqc_tune best = orig;
+  float best_ms = 1e30f;
+  for (int K = 9; K <= kMaxTile; K++) {
+    if (K > c->nbits) break;
+    for (int low = 3; low <= 5; low++) {
+      if (low >= K) continue;
+      c->tune.tile_bits = K;
+      c->tune.low_bits = low;
+      c->tune.grid_blocks = orig.grid_blocks;
+      if (make_plans(c)) continue;
+      vqc_status st = vqc_apply_circuit(s, c, theta);
+      if (st) continue;
+      (void)hipEventRecord(e0, s->stream);
+      for (int r = 0; r < 2; r++) (void)vqc_apply_circuit(s, c, theta);
+      (void)hipEventRecord(e1, s->stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) { best_ms = ms; best = c->tune; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tune = best;
+  vqc_status st = make_plans(c);
+  if (st) return st;
+  *out = c->tune;
+  return VQC_OK;
+}
+
+vqc_status vqc_batch_create(vqc_batch *, int, const vqc_circuit *, void *const *, const double *const *, void *) {
+  return VQC_ERR_UNSUPPORTED;
+}
+vqc_status vqc_batch_destroy(vqc_batch b) { delete b; return VQC_OK; }
+vqc_status vqc_batch_forward(vqc_batch) { return VQC_ERR_UNSUPPORTED; }
+vqc_status vqc_batch_expectation(vqc_batch, const vqc_pauli_sum *, double *) { return VQC_ERR_UNSUPPORTED; }
+vqc_status vqc_batch_backward(vqc_batch, const vqc_pauli_sum *, double *const *, double *, size_t) {
+  return VQC_ERR_UNSUPPORTED;
+}
+vqc_status vqc_batch_capture(vqc_batch, const vqc_pauli_sum *, double *const *, double *, size_t) {
+  return VQC_ERR_UNSUPPORTED;
+}
+vqc_status vqc_batch_replay(vqc_batch) { return VQC_ERR_UNSUPPORTED; }
+
+}  // extern "C"

@@ -1,0 +1,605 @@
+#include "pass_kernels.h"
+
+namespace vqc {
+
+// ------------------------------------------------------ matrices from theta
+
+__device__ __forceinline__ c128 C(double re, double im) { return make_double2(re, im); }
+
+// Gate matrix (k < 0) or derivative w.r.t. parameter k, row-major G[out][in],
+// local index b_{q0} + 2 b_{q1}.  Sec. 2.2 definitions: rotations
+// exp(-i t P/2) (Ry = [[c,-s],[s,c]], the third rotation is Rz), principal
+// square roots ((1+i)I + (1-i)G)/2, CONTROLGate with the control on the first
+// qubit, FSIM with (theta, phi, D+, D-, Doff).  Returns the dimension, 0 when
+// the derivative is identically zero, -1 on an unknown type.
+__device__ int dev_gate(int type, const double *p, int k, const c128 *data, int n_data, c128 *G) {
+  const double r2 = 0.70710678118654752440;
+  int d = (type >= VQC_CZ) ? 4 : 2;
+  if (type == VQC_MATRIX) d = (n_data == 16) ? 4 : 2;
+  for (int i = 0; i < d * d; i++) G[i] = C(0, 0);
+  if (k >= 0 && !(type == VQC_RX || type == VQC_RY || type == VQC_RZ || type == VQC_CRX || type == VQC_CRY ||
+                  type == VQC_CRZ || type == VQC_FSIM))
+    return 0;
+  switch (type) {
+    case VQC_ID: G[0] = C(1, 0); G[3] = C(1, 0); return 2;
+    case VQC_X: G[1] = C(1, 0); G[2] = C(1, 0); return 2;
+    case VQC_Y: G[1] = C(0, -1); G[2] = C(0, 1); return 2;
+    case VQC_Z: G[0] = C(1, 0); G[3] = C(-1, 0); return 2;
+    case VQC_H: G[0] = C(r2, 0); G[1] = C(r2, 0); G[2] = C(r2, 0); G[3] = C(-r2, 0); return 2;
+    case VQC_S: G[0] = C(1, 0); G[3] = C(0, 1); return 2;
+    case VQC_T: G[0] = C(1, 0); G[3] = C(r2, r2); return 2;
+    case VQC_SX: G[0] = C(0.5, 0.5); G[1] = C(0.5, -0.5); G[2] = C(0.5, -0.5); G[3] = C(0.5, 0.5); return 2;
+    case VQC_SY: G[0] = C(0.5, 0.5); G[1] = C(-0.5, -0.5); G[2] = C(0.5, 0.5); G[3] = C(0.5, 0.5); return 2;
+    case VQC_SW: G[0] = C(0.5, 0.5); G[1] = C(0, -r2); G[2] = C(r2, 0); G[3] = C(0.5, 0.5); return 2;
+    case VQC_RX: case VQC_RY: case VQC_RZ:
+    case VQC_CRX: case VQC_CRY: case VQC_CRZ: {
+      double s, c;
+      sincos(0.5 * p[0], &s, &c);
+      c128 U[4];
+      const int base = (type >= VQC_CRX) ? type - VQC_CRX + VQC_RX : type;
+      if (k < 0) {
+        if (base == VQC_RX) { U[0] = C(c, 0); U[1] = C(0, -s); U[2] = C(0, -s); U[3] = C(c, 0); }
+        else if (base == VQC_RY) { U[0] = C(c, 0); U[1] = C(-s, 0); U[2] = C(s, 0); U[3] = C(c, 0); }
+        else { U[0] = C(c, -s); U[1] = C(0, 0); U[2] = C(0, 0); U[3] = C(c, s); }
+      } else {
+        if (base == VQC_RX) { U[0] = C(-0.5 * s, 0); U[1] = C(0, -0.5 * c); U[2] = C(0, -0.5 * c); U[3] = C(-0.5 * s, 0); }
+        else if (base == VQC_RY) { U[0] = C(-0.5 * s, 0); U[1] = C(-0.5 * c, 0); U[2] = C(0.5 * c, 0); U[3] = C(-0.5 * s, 0); }
+        else { U[0] = C(-0.5 * s, -0.5 * c); U[1] = C(0, 0); U[2] = C(0, 0); U[3] = C(-0.5 * s, 0.5 * c); }
+      }
+      if (type < VQC_CRX) { for (int i = 0; i < 4; i++) G[i] = U[i]; return 2; }
+      if (k < 0) { G[0] = C(1, 0); G[10] = C(1, 0); }
+      G[1 * 4 + 1] = U[0]; G[1 * 4 + 3] = U[1]; G[3 * 4 + 1] = U[2]; G[3 * 4 + 3] = U[3];
+      return 4;
+    }
+    case VQC_CZ: G[0] = C(1, 0); G[5] = C(1, 0); G[10] = C(1, 0); G[15] = C(-1, 0); return 4;
+    case VQC_CNOT: G[0] = C(1, 0); G[1 * 4 + 3] = C(1, 0); G[2 * 4 + 2] = C(1, 0); G[3 * 4 + 1] = C(1, 0); return 4;
+    case VQC_SWAP: G[0] = C(1, 0); G[1 * 4 + 2] = C(1, 0); G[2 * 4 + 1] = C(1, 0); G[15] = C(1, 0); return 4;
+    case VQC_ISWAP: G[0] = C(1, 0); G[1 * 4 + 2] = C(0, 1); G[2 * 4 + 1] = C(0, 1); G[15] = C(1, 0); return 4;
+    case VQC_FSIM: {
+      // entries: (1,1) e^{i(D+ + D-)} cos th, (1,2) -i e^{i(D+ - Doff)} sin th,
+      //          (2,1) -i e^{i(D+ + Doff)} sin th, (2,2) e^{i(D+ - D-)} cos th,
+      //          (3,3) e^{i(2 D+ - phi)}, (0,0) 1
+      const double th = p[0], ph = p[1], dp = p[2], dm = p[3], dof = p[4];
+      double st, ct;
+      sincos(th, &st, &ct);
+      double s11, c11, s12, c12, s21, c21, s22, c22, s33, c33;
+      sincos(dp + dm, &s11, &c11);
+      sincos(dp - dof, &s12, &c12);
+      sincos(dp + dof, &s21, &c21);
+      sincos(dp - dm, &s22, &c22);
+      sincos(2 * dp - ph, &s33, &c33);
+      const c128 e11 = C(c11, s11), e12 = C(c12, s12), e21 = C(c21, s21), e22 = C(c22, s22), e33 = C(c33, s33);
+      const c128 mi = C(0, -1), pi_ = C(0, 1);
+      // f(th) factors and their derivatives
+      double f11 = ct, f12 = st, f22 = ct;
+      c128 m11, m12, m21, m22, m33 = C(0, 0), m00 = C(0, 0);
+      if (k < 0) {
+        m00 = C(1, 0);
+        m11 = cscale(f11, e11); m12 = cmul(mi, cscale(f12, e12));
+        m21 = cmul(mi, cscale(f12, e21)); m22 = cscale(f22, e22); m33 = e33;
+      } else if (k == 0) {
+        m11 = cscale(-st, e11); m12 = cmul(mi, cscale(ct, e12));
+        m21 = cmul(mi, cscale(ct, e21)); m22 = cscale(-st, e22);
+      } else if (k == 1) {
+        m11 = m12 = m21 = m22 = C(0, 0);
+        m33 = cmul(mi, e33);
+      } else if (k == 2) {
+        m11 = cmul(pi_, cscale(ct, e11)); m12 = cscale(st, e12);
+        m21 = cscale(st, e21); m22 = cmul(pi_, cscale(ct, e22));
+        m33 = cmul(C(0, 2), e33);
+      } else if (k == 3) {
+        m11 = cmul(pi_, cscale(ct, e11)); m12 = m21 = C(0, 0);
+        m22 = cmul(mi, cscale(ct, e22));
+      } else {
+        m11 = m22 = C(0, 0);
+        m12 = cscale(-st, e12); m21 = cscale(st, e21);
+      }
+      G[0] = m00; G[5] = m11; G[6] = m12; G[9] = m21; G[10] = m22; G[15] = m33;
+      return 4;
+    }
+    case VQC_CONTROL:
+      G[0] = C(1, 0); G[10] = C(1, 0);
+      G[1 * 4 + 1] = data[0]; G[1 * 4 + 3] = data[1]; G[3 * 4 + 1] = data[2]; G[3 * 4 + 3] = data[3];
+      return 4;
+    case VQC_MATRIX:
+      for (int i = 0; i < d * d; i++) G[i] = data[i];
+      return d;
+  }
+  return -1;
+}
+
+// Kraus operator s of a channel, element (r, c); Sec. 2.2 channels with the
+// trace-preserving depolarizing weights sqrt(1-3p/4), sqrt(p/4) and the
+// two-qubit analogue sqrt(1-15p/16), sqrt(p/16) (sigma_a on the first qubit).
+__device__ __forceinline__ c128 pauli_el(int a, int r, int c) {
+  switch (a) {
+    case 0: return C(r == c ? 1.0 : 0.0, 0);
+    case 1: return C(r != c ? 1.0 : 0.0, 0);
+    case 2: return r == c ? C(0, 0) : (r == 0 ? C(0, -1) : C(0, 1));
+    default: return C(r == c ? (r == 0 ? 1.0 : -1.0) : 0.0, 0);
+  }
+}
+
+__device__ c128 dev_kraus(int type, double g, const c128 *data, int d, int s, int r, int c) {
+  switch (type) {
+    case VQC_AMPLITUDE_DAMPING:
+      if (s == 0) return C(r == c ? (r == 0 ? 1.0 : sqrt(1.0 - g)) : 0.0, 0);
+      return C((r == 0 && c == 1) ? sqrt(g) : 0.0, 0);
+    case VQC_PHASE_DAMPING:
+      if (s == 0) return C(r == c ? (r == 0 ? 1.0 : sqrt(1.0 - g)) : 0.0, 0);
+      return C((r == 1 && c == 1) ? sqrt(g) : 0.0, 0);
+    case VQC_DEPOLARIZING: {
+      const double w = s == 0 ? sqrt(1.0 - 0.75 * g) : sqrt(0.25 * g);
+      return cscale(w, pauli_el(s, r, c));
+    }
+    case VQC_DEPOLARIZING2: {
+      const int a = s & 3, b = s >> 2;
+      const double w = s == 0 ? sqrt(1.0 - g * (15.0 / 16.0)) : sqrt(g / 16.0);
+      return cscale(w, cmul(pauli_el(a, r & 1, c & 1), pauli_el(b, r >> 1, c >> 1)));
+    }
+    default:  // VQC_KRAUS: row-major blocks
+      return data[(s * d + r) * d + c];
+  }
+}
+
+__device__ void build_recipe(const DRecipe &R, const c128 *__restrict__ cdata, const double *th, c128 *out_base) {
+  double p[5];
+  for (int k = 0; k < 5; k++) p[k] = (R.pidx[k] >= 0 && th) ? th[R.pidx[k]] : R.pval[k];
+  c128 *out = out_base + R.out;
+  const c128 *data = R.data >= 0 ? cdata + R.data : nullptr;
+  c128 G[16], dG[16];
+  switch (R.form) {
+    case RF_GATE: case RF_GATE_CONJ: case RF_DGATE: case RF_DGATE_CONJ: {
+      int d = dev_gate(R.type, p, (R.form == RF_DGATE || R.form == RF_DGATE_CONJ) ? R.k : -1, data, R.n_data, G);
+      if (d <= 0) d = (R.nq == 2) ? 4 : 2;
+      const bool cj = (R.form == RF_GATE_CONJ || R.form == RF_DGATE_CONJ);
+      for (int e = 0; e < d * d; e++) out[e] = cj ? cconj(G[e]) : G[e];
+      break;
+    }
+    case RF_SUPER_GATE: case RF_DSUPER_GATE: {
+      int d = dev_gate(R.type, p, -1, data, R.n_data, G);
+      if (R.form == RF_DSUPER_GATE) dev_gate(R.type, p, R.k, data, R.n_data, dG);
+      const int D = d * d;
+      for (int x = 0; x < d; x++)
+        for (int y = 0; y < d; y++)
+          for (int x2 = 0; x2 < d; x2++)
+            for (int y2 = 0; y2 < d; y2++) {
+              c128 v;
+              if (R.form == RF_SUPER_GATE) v = cmul(G[x * d + x2], cconj(G[y * d + y2]));
+              else v = cadd(cmul(dG[x * d + x2], cconj(G[y * d + y2])), cmul(G[x * d + x2], cconj(dG[y * d + y2])));
+              out[(x + d * y) * D + (x2 + d * y2)] = v;
+            }
+      break;
+    }
+    case RF_SUPER_KRAUS: {
+      const int d = 1 << R.nq, D = d * d;
+      int nk;
+      switch (R.type) {
+        case VQC_AMPLITUDE_DAMPING: case VQC_PHASE_DAMPING: nk = 2; break;
+        case VQC_DEPOLARIZING: nk = 4; break;
+        case VQC_DEPOLARIZING2: nk = 16; break;
+        default: nk = R.n_data / (d * d); break;
+      }
+      for (int x = 0; x < d; x++)
+        for (int y = 0; y < d; y++)
+          for (int x2 = 0; x2 < d; x2++)
+            for (int y2 = 0; y2 < d; y2++) {
+              c128 acc = C(0, 0);
+              for (int s = 0; s < nk; s++)
+                acc = cfma(dev_kraus(R.type, p[0], data, d, s, x, x2), cconj(dev_kraus(R.type, p[0], data, d, s, y, y2)), acc);
+              out[(x + d * y) * D + (x2 + d * y2)] = acc;
+            }
+      break;
+    }
+  }
+}
+
+__global__ void k_build_mats(const DRecipe *__restrict__ rec, int n_rec, const c128 *__restrict__ cdata,
+                             const double *const *__restrict__ thetas, c128 *const *__restrict__ mats, int B,
+                             const double *theta0, c128 *mats0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= n_rec || b >= B) return;
+  build_recipe(rec[i], cdata, thetas ? thetas[b] : theta0, mats ? mats[b] : mats0);
+}
+
+__global__ void k_build_one(DRecipe r, const c128 *__restrict__ cdata, c128 *out) {
+  if (threadIdx.x == 0) build_recipe(r, cdata, nullptr, out);
+}
+
+// -------------------------------------------------- expectation and seeds
+
+constexpr int kEChunk = 4096;  // amplitudes per expectation unit (256 x 16)
+
+__device__ __forceinline__ double2 block_sum2(double2 v, double2 *sh) {
+  const int t = threadIdx.x;
+  v.x = wave_sum<64>(v.x);
+  v.y = wave_sum<64>(v.y);
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  double2 r = make_double2(0, 0);
+  if (t == 0) {
+    r = sh[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); w++) { r.x += sh[w].x; r.y += sh[w].y; }
+  }
+  __syncthreads();
+  return r;
+}
+
+// <psi|H|psi> partial sums (and H psi when J.out != nullptr) for pure states;
+// Tr(H rho) partial sums for mixed states (Sec. 2.5).  Term coefficients carry
+// i^{|Y|}; the remaining phase is (-1)^{popcount(x & zm)} at the source x.
+__global__ void __launch_bounds__(256) k_expect(const DEJob *__restrict__ jobs, int n_jobs, int64_t total_units,
+                                                const DTerm *__restrict__ terms, int nt) {
+  __shared__ double2 sh[4];
+  const int t = threadIdx.x;
+  for (int64_t u = blockIdx.x; u < total_units; u += gridDim.x) {
+    const DEJob &J = jobs[find_job(jobs, n_jobs, u)];
+    const int64_t ublk = u - J.unit0;
+    const uint64_t N = 1ull << J.nbits;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k = 0; k < kEChunk / 256; k++) {
+      const uint64_t y = (uint64_t)ublk * kEChunk + (uint64_t)k * 256 + t;
+      if (y >= N) break;
+      if (!J.mixed) {
+        c128 v = make_double2(0.0, 0.0);
+        for (int i = 0; i < nt; i++) {
+          const DTerm T = terms[i];
+          const uint64_t x = y ^ T.xm;
+          c128 c = make_double2(T.cre, T.cim);
+          if (__popcll(x & T.zm) & 1) c = make_double2(-c.x, -c.y);
+          v = cfma(c, J.psi[x], v);
+        }
+        const c128 py = J.psi[y];
+        acc.x += fma(py.x, v.x, py.y * v.y);
+        acc.y += fma(py.x, v.y, -py.y * v.x);
+        if (J.out) J.out[y] = v;
+      } else {
+        for (int i = 0; i < nt; i++) {
+          const DTerm T = terms[i];
+          c128 c = make_double2(T.cre, T.cim);
+          if (__popcll(y & T.zm) & 1) c = make_double2(-c.x, -c.y);
+          const c128 r = cmul(c, J.psi[y + N * (y ^ T.xm)]);
+          acc.x += r.x;
+          acc.y += r.y;
+        }
+      }
+    }
+    const double2 s = block_sum2(acc, sh);
+    if (t == 0) J.partial[ublk] = s;
+  }
+}
+
+// vec(H) for the noisy adjoint seed: v[x + 2^n y] = sum_t c_t <x|P_t|y>.
+// One lane per column y; terms with equal x-mask accumulate in term order.
+__global__ void __launch_bounds__(256) k_seed_mixed(c128 *__restrict__ out, int n, const DTerm *__restrict__ terms,
+                                                    int nt) {
+  const uint64_t N = 1ull << n;
+  for (uint64_t y = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; y < N; y += (uint64_t)gridDim.x * blockDim.x) {
+    for (int i = 0; i < nt; i++) {
+      const DTerm T = terms[i];
+      c128 c = make_double2(T.cre, T.cim);
+      if (__popcll(y & T.zm) & 1) c = make_double2(-c.x, -c.y);
+      const uint64_t idx = (y ^ T.xm) + N * y;
+      out[idx] = cadd(out[idx], c);
+    }
+  }
+}
+
+// second stage: out[j] = sum of job j's partials in a fixed order
+__global__ void __launch_bounds__(256) k_reduce_partials(const DEJob *__restrict__ jobs, int n_jobs,
+                                                         double2 *__restrict__ out) {
+  __shared__ double2 sh[4];
+  const int j = blockIdx.x;
+  if (j >= n_jobs) return;
+  const DEJob &J = jobs[j];
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t i = threadIdx.x; i < J.n_units; i += 256) {
+    acc.x += J.partial[i].x;
+    acc.y += J.partial[i].y;
+  }
+  const double2 s = block_sum2(acc, sh);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+// real parts into a strided double array (energies)
+__global__ void k_take_real(const double2 *__restrict__ in, int n, double *const *__restrict__ dst_ptrs,
+                            double *__restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (dst) dst[i] = in[i].x;
+}
+
+// grad[p] = scale * sum over the slots of p (appearance order) of the sum over
+// units; one block per (parameter, item), fixed summation order.
+__global__ void __launch_bounds__(256) k_grad_reduce(const DGradJob *__restrict__ jobs) {
+  __shared__ double2 sh[4];
+  const DGradJob &J = jobs[blockIdx.y];
+  const int p = blockIdx.x;
+  if (p >= J.n_params) return;
+  double acc = 0.0;
+  for (int k = J.csr_ptr[p]; k < J.csr_ptr[p + 1]; k++) {
+    const double *row = J.partials + (int64_t)J.csr_slot[k] * J.n_units;
+    for (int64_t i = threadIdx.x; i < J.n_units; i += 256) acc += row[i];
+  }
+  const double2 s = block_sum2(make_double2(acc, 0.0), sh);
+  if (threadIdx.x == 0) J.grad[p] = J.scale * s.x;
+}
+
+// ------------------------------------------------------- single-op kernels
+
+
+// one pair (x, x + 2^q) per lane; PHASE1 touches only the |1> half
+__global__ void __launch_bounds__(256) k_g1(c128 *__restrict__ psi, int nbits, int q, const c128 *__restrict__ M,
+                                            int kind) {
+  const uint64_t half = 1ull << (nbits - 1);
+  const c128 m00 = M[0], m01 = M[1], m10 = M[2], m11 = M[3];
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < half; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t x0 = ins0<uint64_t>(i, q), x1 = x0 | (1ull << q);
+    if (kind == SK_PHASE1) {
+      psi[x1] = cmul(m11, psi[x1]);
+    } else if (kind == SK_DIAG1) {
+      psi[x0] = cmul(m00, psi[x0]);
+      psi[x1] = cmul(m11, psi[x1]);
+    } else {
+      const c128 a = psi[x0], b = psi[x1];
+      psi[x0] = cfma(m00, a, cmul(m01, b));
+      psi[x1] = cfma(m10, a, cmul(m11, b));
+    }
+  }
+}
+
+// one quad per lane (q0 -> local bit 0, q1 -> local bit 1); structured kinds
+// read and write only the amplitudes that change
+__global__ void __launch_bounds__(256) k_g2(c128 *__restrict__ psi, int nbits, int q0, int q1,
+                                            const c128 *__restrict__ M, int kind) {
+  const uint64_t quarter = 1ull << (nbits - 2);
+  const int lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < quarter;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t x0 = ins0<uint64_t>(ins0<uint64_t>(i, lo), hi);
+    const uint64_t x1 = x0 | (1ull << q0), x2 = x0 | (1ull << q1), x3 = x1 | x2;
+    switch (kind) {
+      case SK_PHASE11: psi[x3] = cmul(M[15], psi[x3]); break;
+      case SK_DIAG2:
+        psi[x0] = cmul(M[0], psi[x0]); psi[x1] = cmul(M[5], psi[x1]);
+        psi[x2] = cmul(M[10], psi[x2]); psi[x3] = cmul(M[15], psi[x3]);
+        break;
+      case SK_CX: { const c128 a = psi[x1]; psi[x1] = psi[x3]; psi[x3] = a; break; }
+      case SK_CTRL: {
+        const c128 a = psi[x1], b = psi[x3];
+        psi[x1] = cfma(M[5], a, cmul(M[7], b));
+        psi[x3] = cfma(M[13], a, cmul(M[15], b));
+        break;
+      }
+      case SK_FSIM: {
+        const c128 a = psi[x1], b = psi[x2];
+        psi[x1] = cfma(M[5], a, cmul(M[6], b));
+        psi[x2] = cfma(M[9], a, cmul(M[10], b));
+        psi[x3] = cmul(M[15], psi[x3]);
+        break;
+      }
+      default: {
+        const c128 v0 = psi[x0], v1 = psi[x1], v2 = psi[x2], v3 = psi[x3];
+        c128 o[4];
+        for (int r = 0; r < 4; r++)
+          o[r] = cfma(M[r * 4 + 3], v3, cfma(M[r * 4 + 2], v2, cfma(M[r * 4 + 1], v1, cmul(M[r * 4], v0))));
+        psi[x0] = o[0]; psi[x1] = o[1]; psi[x2] = o[2]; psi[x3] = o[3];
+      }
+    }
+  }
+}
+
+// generic dense 2^m x 2^m op (m = 3, 4): superoperators of 2q channels
+template <int m>
+__global__ void __launch_bounds__(256) k_gm(c128 *__restrict__ psi, int nbits, int4 q, const c128 *__restrict__ M) {
+  constexpr int d = 1 << m;
+  int qs[4] = {q.x, q.y, q.z, q.w}, srt[4];
+  for (int i = 0; i < m; i++) srt[i] = qs[i];
+  for (int i = 0; i < m; i++)
+    for (int j = i + 1; j < m; j++)
+      if (srt[j] < srt[i]) { const int tmp = srt[i]; srt[i] = srt[j]; srt[j] = tmp; }
+  const uint64_t groups = 1ull << (nbits - m);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < groups;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t base = i;
+    for (int k = 0; k < m; k++) base = ins0<uint64_t>(base, srt[k]);
+    c128 x[d];
+    uint64_t idx[d];
+#pragma unroll
+    for (int l = 0; l < d; l++) {
+      uint64_t o = base;
+#pragma unroll
+      for (int k = 0; k < m; k++)
+        if ((l >> k) & 1) o |= 1ull << qs[k];
+      idx[l] = o;
+      x[l] = psi[o];
+    }
+#pragma unroll
+    for (int r = 0; r < d; r++) {
+      c128 acc = cmul(M[r * d], x[0]);
+#pragma unroll
+      for (int c = 1; c < d; c++) acc = cfma(M[r * d + c], x[c], acc);
+      psi[idx[r]] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ misc
+
+__global__ void k_init_basis0(c128 *__restrict__ v, uint64_t N) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+    v[i] = make_double2(i == 0 ? 1.0 : 0.0, 0.0);
+}
+
+__global__ void k_init_batched(c128 *const *__restrict__ ptrs, const uint64_t *__restrict__ sizes) {
+  c128 *v = ptrs[blockIdx.y];
+  const uint64_t N = sizes[blockIdx.y];
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+    v[i] = make_double2(i == 0 ? 1.0 : 0.0, 0.0);
+}
+
+__global__ void k_fill_zero(c128 *__restrict__ v, uint64_t N) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+    v[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_copy(c128 *__restrict__ dst, const c128 *__restrict__ src, uint64_t N) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void k_gather(const c128 *__restrict__ psi, const int64_t *__restrict__ idx, int count,
+                         c128 *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = psi[idx[i]];
+}
+
+struct Mat16 { c128 m[16]; };
+
+__global__ void k_set_mat(c128 *__restrict__ dst, Mat16 m, int count) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = m.m[i];
+}
+
+// ------------------------------------------------------------- launchers
+
+static int grid_for(uint64_t work, int block) {
+  uint64_t g = (work + block - 1) / block;
+  const uint64_t cap = 256ull * 64;  // 256 CUs x 64 blocks: enough in flight
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+// per-instantiation launchers live in inst_*.hip (compiled in parallel)
+#define VQC_DECL_LDS(KK, AA) \
+  hipError_t launch_lds_##KK##_##AA(const DJob *, int, int64_t, int, const DOverride &, hipStream_t);
+#define VQC_DECL_REG(RR, MM) \
+  hipError_t launch_reg_##RR##_##MM(const DJob *, int, int64_t, int, const DOverride &, hipStream_t);
+#include "inst_list.h"
+#undef VQC_DECL_LDS
+#undef VQC_DECL_REG
+
+hipError_t launch_pass_lds(int K, int R, bool adj, const DJob *jobs, int n_jobs, int64_t total, int grid,
+                           const DOverride &ov, hipStream_t st) {
+  if (R != 4) return hipErrorInvalidValue;
+#define VQC_DECL_LDS(KK, AA) \
+  if (K == KK && (int)adj == AA) return launch_lds_##KK##_##AA(jobs, n_jobs, total, grid, ov, st);
+#define VQC_DECL_REG(RR, MM)
+#include "inst_list.h"
+#undef VQC_DECL_LDS
+#undef VQC_DECL_REG
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass_reg(int R, int mode, const DJob *jobs, int n_jobs, int64_t total, int grid,
+                           const DOverride &ov, hipStream_t st) {
+#define VQC_DECL_LDS(KK, AA)
+#define VQC_DECL_REG(RR, MM) \
+  if (R == RR && mode == MM) return launch_reg_##RR##_##MM(jobs, n_jobs, total, grid, ov, st);
+#include "inst_list.h"
+#undef VQC_DECL_LDS
+#undef VQC_DECL_REG
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_build_mats(const DRecipe *rec, int n_rec, const c128 *cdata, const double *const *thetas,
+                             c128 *const *mats, int B, const double *theta0, c128 *mats0, hipStream_t st) {
+  if (n_rec == 0 || B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_mats, dim3((n_rec + 63) / 64, B), dim3(64), 0, st, rec, n_rec, cdata, thetas, mats, B,
+                     theta0, mats0);
+  return hipGetLastError();
+}
+
+int64_t expect_units(int nbits_iter) {
+  const int64_t N = int64_t(1) << nbits_iter;
+  return (N + kEChunk - 1) / kEChunk;
+}
+
+hipError_t launch_expect(const DEJob *jobs, int n_jobs, int64_t total, const DTerm *terms, int nt, hipStream_t st) {
+  const int g = (int)(total < 256 * 32 ? total : 256 * 32);
+  hipLaunchKernelGGL(k_expect, dim3(g), dim3(256), 0, st, jobs, n_jobs, total, terms, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const DEJob *jobs, int n_jobs, double2 *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(n_jobs), dim3(256), 0, st, jobs, n_jobs, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_take_real(const double2 *in, int n, double *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_take_real, dim3((n + 255) / 256), dim3(256), 0, st, in, n, nullptr, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_mixed(c128 *out, int n, const DTerm *terms, int nt, hipStream_t st) {
+  const uint64_t N = 1ull << n;
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(N * N, 256)), dim3(256), 0, st, out, N * N);
+  hipLaunchKernelGGL(k_seed_mixed, dim3(grid_for(N, 256)), dim3(256), 0, st, out, n, terms, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const DGradJob *jobs, int n_items, int max_params, hipStream_t st) {
+  if (max_params <= 0 || n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_reduce, dim3(max_params, n_items), dim3(256), 0, st, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_g1(c128 *psi, int nbits, int q, const c128 *M, int kind, hipStream_t st) {
+  hipLaunchKernelGGL(k_g1, dim3(grid_for(1ull << (nbits - 1), 256)), dim3(256), 0, st, psi, nbits, q, M, kind);
+  return hipGetLastError();
+}
+
+hipError_t launch_g2(c128 *psi, int nbits, int q0, int q1, const c128 *M, int kind, hipStream_t st) {
+  hipLaunchKernelGGL(k_g2, dim3(grid_for(1ull << (nbits - 2), 256)), dim3(256), 0, st, psi, nbits, q0, q1, M, kind);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm(c128 *psi, int nbits, int m, const int *q, const c128 *M, hipStream_t st) {
+  const int4 qq = make_int4(q[0], q[1], m > 2 ? q[2] : 0, m > 3 ? q[3] : 0);
+  const dim3 grid(grid_for(1ull << (nbits - m), 256));
+  if (m == 3) hipLaunchKernelGGL(k_gm<3>, grid, dim3(256), 0, st, psi, nbits, qq, M);
+  else if (m == 4) hipLaunchKernelGGL(k_gm<4>, grid, dim3(256), 0, st, psi, nbits, qq, M);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_init_basis0(c128 *v, uint64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_basis0, dim3(grid_for(N, 256)), dim3(256), 0, st, v, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_one(const DRecipe &r, const c128 *cdata, c128 *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_build_one, dim3(1), dim3(64), 0, st, r, cdata, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_batched(c128 *const *ptrs, const uint64_t *sizes, int B, uint64_t max_n, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_batched, dim3(grid_for(max_n, 256) / B + 1, B), dim3(256), 0, st, ptrs, sizes);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(c128 *v, uint64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(N, 256)), dim3(256), 0, st, v, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(c128 *dst, const c128 *src, uint64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(N, 256)), dim3(256), 0, st, dst, src, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const c128 *psi, const int64_t *idx, int count, c128 *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3((count + 255) / 256), dim3(256), 0, st, psi, idx, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_mat(c128 *dst, const c128 *m, int count, hipStream_t st) {
+  Mat16 mm;
+  for (int i = 0; i < 16; i++) mm.m[i] = i < count ? m[i] : make_double2(0, 0);
+  hipLaunchKernelGGL(k_set_mat, dim3(1), dim3(16), 0, st, dst, mm, count);
+  return hipGetLastError();
+}
+
+}  // namespace vqc

@@ -1,0 +1,161 @@
+// Internal tables shared by the host planner (api.cpp) and the gfx950
+// kernels (kernels.hip).  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vqc {
+
+typedef double2 c128;  // (re, im)
+
+// Register-level kinds of an elementary op (a gate, a half of a gate acting on
+// the ket or bra bits of vec(rho), or a superoperator).
+enum GateKind : int8_t {
+  GK_DENSE1 = 0,  // 2x2 on one bit
+  GK_DIAG1 = 1,   // diag(m00, m11)
+  GK_DENSE2 = 2,  // 4x4 on two bits (local index b0 + 2 b1)
+  GK_DIAG2 = 3,   // diag(m00, m11, m22, m33)
+  GK_FSIM = 4,    // m00 | [[m11 m12][m21 m22]] | m33 (fSim / iSWAP pattern)
+  GK_CX = 5,      // controlled X: control bit 0, target bit 1 (no matrix)
+  GK_DENSE4 = 6,  // 16x16 on four bits, register bits 0..3 in order
+  GK_NONE = 7     // identity (no-op)
+};
+
+constexpr int kMaxTile = 13;      // K <= 13: 2^13 * 16 B = 128 KiB of LDS
+constexpr int kMaxVarPerPass = 256;  // derivative slots reduced inside one pass
+
+// one elementary op inside a pass, in stage-local register bits
+struct DGate {
+  int8_t kind;
+  int8_t nq;
+  int8_t r[4];      // register bit of the op's local qubit t
+  int16_t nd;       // derivative records (adjoint only)
+  int32_t mat;      // matrix offset in the item's matrix buffer (c128 units), -1 none
+  int32_t d0;       // first derivative record
+};
+
+struct DDeriv {
+  int8_t kind;      // register kind of the derivative matrix
+  int8_t pad[3];
+  int32_t mat;      // derivative matrix offset (c128 units)
+  int32_t gslot;    // global derivative slot (row of the partials array)
+  int32_t local;    // slot inside the pass reduction (0 .. nvar-1)
+};
+
+struct DStage {
+  int8_t rbit[4];   // tile-local bit held in register bit i
+  int8_t srt[4];    // the same bits, sorted ascending (zero insertion)
+  int32_t g0, g1;   // gate range [g0, g1) of this stage (absolute index)
+};
+
+struct DPass {
+  int32_t K;        // tile bits (= R for register-only passes)
+  int32_t nst;      // stages
+  int32_t nvar;     // derivative slots reduced in this pass
+  int32_t pad;
+  int8_t tq[16];    // global qubit of tile-local bit i, ascending
+  const DStage *stages;   // absolute device pointers
+  const DGate *gates;
+  const DDeriv *derivs;
+  const int32_t *vslot;   // gslot of pass-local derivative slot v
+};
+
+// one (item, pass) of a launch
+struct DJob {
+  c128 *a;          // state (forward) / Phi (adjoint)
+  c128 *b;          // Psi (adjoint), or destination for out-of-place forward
+  const c128 *mats; // the item's matrices
+  double *partials; // [gslot][n_units] (adjoint)
+  const DPass *pass;
+  int64_t unit0;    // first global unit of this job
+  int64_t n_units;  // units (tiles, or blocks of tiles) of this job
+  int32_t nbits;
+  int32_t mode;     // 0: in place; 1: out of place (read a, write b)
+};
+
+// buffers for single-item launches, passed by value so that the device job
+// tables stay static; use = 0 takes everything from the job
+struct DOverride {
+  c128 *a;
+  c128 *b;
+  const c128 *mats;
+  double *partials;
+  int32_t mode;
+  int32_t use;
+};
+
+// matrix recipes (built on device from theta)
+enum RecipeForm : int32_t {
+  RF_GATE = 0,      // gate matrix
+  RF_GATE_CONJ = 1, // complex conjugate of the gate matrix (bra half)
+  RF_DGATE = 2,     // derivative of the gate matrix w.r.t. parameter k
+  RF_DGATE_CONJ = 3,
+  RF_SUPER_GATE = 4,  // conj(U) (x) U  (ket bits low, bra bits high)
+  RF_DSUPER_GATE = 5, // conj(dU) (x) U + conj(U) (x) dU
+  RF_SUPER_KRAUS = 6  // sum_s conj(K_s) (x) K_s
+};
+
+struct DRecipe {
+  int32_t type;     // VQC_* op type
+  int32_t form;
+  int32_t k;        // parameter for derivatives
+  int32_t nq;       // qubits of the original op
+  int32_t out;      // output offset (c128 units)
+  int32_t data;     // offset into the circuit's constant data (c128 units), -1 none
+  int32_t n_data;   // entries at data
+  int32_t pidx[5];  // theta index of each parameter, -1 = fixed
+  double pval[5];
+};
+
+struct DTerm {      // Pauli term with i^{|Y|} folded into the coefficient
+  uint64_t xm, zm;
+  double cre, cim;
+};
+
+struct DEJob {      // expectation / seed job (one item)
+  const c128 *psi;
+  c128 *out;        // H psi (pure seed) or vec(H) (mixed seed); nullptr if unused
+  double2 *partial; // per-unit partial sums
+  int64_t unit0, n_units;
+  int32_t nbits;    // n (qubits, not vec bits)
+  int32_t mixed;
+};
+
+struct DGradJob {
+  const double *partials;  // [slot][n_units]
+  int64_t n_units;
+  double *grad;
+  const int32_t *csr_ptr;  // parameter p -> slots [csr_ptr[p], csr_ptr[p+1])
+  const int32_t *csr_slot;
+  int32_t n_params;
+  double scale;
+};
+
+// launchers (kernels.hip)
+hipError_t launch_pass_lds(int K, int R, bool adj, const DJob *jobs, int n_jobs, int64_t total, int grid,
+                           const DOverride &ov, hipStream_t st);
+hipError_t launch_pass_reg(int R, int mode, const DJob *jobs, int n_jobs, int64_t total, int grid,
+                           const DOverride &ov, hipStream_t st);
+hipError_t launch_build_mats(const DRecipe *rec, int n_rec, const c128 *cdata, const double *const *thetas,
+                             c128 *const *mats, int B, const double *theta0, c128 *mats0, hipStream_t st);
+hipError_t launch_build_one(const DRecipe &r, const c128 *cdata, c128 *out, hipStream_t st);
+hipError_t launch_init_batched(c128 *const *ptrs, const uint64_t *sizes, int B, uint64_t max_n, hipStream_t st);
+int64_t expect_units(int nbits_iter);
+hipError_t launch_expect(const DEJob *jobs, int n_jobs, int64_t total, const DTerm *terms, int nt, hipStream_t st);
+hipError_t launch_reduce_partials(const DEJob *jobs, int n_jobs, double2 *out, hipStream_t st);
+hipError_t launch_take_real(const double2 *in, int n, double *dst, hipStream_t st);
+hipError_t launch_seed_mixed(c128 *out, int n, const DTerm *terms, int nt, hipStream_t st);
+hipError_t launch_grad_reduce(const DGradJob *jobs, int n_items, int max_params, hipStream_t st);
+hipError_t launch_g1(c128 *psi, int nbits, int q, const c128 *M, int kind, hipStream_t st);
+hipError_t launch_g2(c128 *psi, int nbits, int q0, int q1, const c128 *M, int kind, hipStream_t st);
+hipError_t launch_gm(c128 *psi, int nbits, int m, const int *q, const c128 *M, hipStream_t st);
+hipError_t launch_init_basis0(c128 *v, uint64_t N, hipStream_t st);
+hipError_t launch_fill_zero(c128 *v, uint64_t N, hipStream_t st);
+hipError_t launch_copy(c128 *dst, const c128 *src, uint64_t N, hipStream_t st);
+hipError_t launch_gather(const c128 *psi, const int64_t *idx, int count, c128 *out, hipStream_t st);
+hipError_t launch_set_mat(c128 *dst, const c128 *m, int count, hipStream_t st);
+
+enum SingleKind { SK_DENSE1 = 0, SK_DIAG1, SK_PHASE1, SK_DENSE2, SK_DIAG2, SK_PHASE11, SK_FSIM, SK_CX, SK_CTRL };
+constexpr int kEChunkHost = 4096;
+
+}  // namespace vqc
