@@ -1,0 +1,179 @@
+"""Benchmark of the MI355X variational-circuit hot path.
+
+Headline workload: the 28-qubit random circuit on a 4x7 grid (20 cycles of
+sqrt(X)/sqrt(Y)/sqrt(W) on every qubit plus fSim on one coupler pattern,
+785 gates, complex128 state of 4 GiB resident in HBM).  One step = reset to
+|0..0>, apply the whole circuit as fused HBM passes, read the norm and 1000
+seeded output amplitudes.  value = gate applications per second.
+
+Also reported:
+* roofline of the dominant kernel (the fused forward pass), with its
+  average duration measured by HIP events on the launch stream and the
+  algorithmic bytes of one pass (read + write of every amplitude, 32 B/amp);
+* the 20-qubit batched VQE gradient workload (64 parameter sets, 1600
+  parameters, transverse-field Ising energy): gradients/s batched versus
+  the same library run item by item;
+* cpu_baseline: the plain C oracle on this host, timed on a bounded prefix of
+  the same 28-qubit circuit.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-vqe]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-vqe", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(ops, n, seconds):
+    """The oracle as it stands, on a prefix of the circuit (one gate at a time
+    until `seconds` of work), reported in the same unit."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    oracle.set_threads(cores)
+    st = oracle.initial_state(n)
+    done, t0 = 0, time.perf_counter()
+    tab_ops = list(ops)
+    while done < len(tab_ops) and time.perf_counter() - t0 < seconds:
+        oracle.apply_op_inplace(st, n, tab_ops[done])
+        done += 1
+    dt = time.perf_counter() - t0
+    del st
+    return {"value": done / dt, "unit": "gate-apps/s", "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": "first %d of %d gates of the same 28-qubit circuit, one full-state pass each, %.1f s"
+                      % (done, len(tab_ops), dt)}
+
+
+def vqe_batched(torch, steps):
+    """20-qubit HEA (40 layers, 1600 params), TFIM energy and adjoint gradient
+    for 64 parameter sets: batched launches vs the same library item by item."""
+    from paper_2406_19212_amd import Batch, Circuit, State
+    from paper_2406_19212_amd import workloads as W
+    n, L, Bn = 20, 40, 64
+    ops = W.hea(n, L)
+    P = W.count_params(ops)
+    theta = torch.tensor(W.theta_uniform(W.CONFIG_SEED[2], Bn, P), device="cuda")
+    terms = W.tfim(n, 1.0)
+    circ = Circuit(n, ops, n_params=P)
+    out = {}
+    # plain: one item at a time
+    st = State(n)
+    grads = torch.zeros(Bn, P, dtype=torch.float64, device="cuda")
+
+    def plain(k):
+        for b in range(k):
+            st.reset()
+            circ.apply(st, theta[b])
+            circ.backward(theta[b], st, terms, grad=grads[b], energy=False)
+    plain(2)
+    torch.cuda.synchronize()
+    nb = 8
+    t0 = time.perf_counter()
+    plain(nb)
+    torch.cuda.synchronize()
+    out["plain_grads_per_s"] = nb / (time.perf_counter() - t0)
+    try:
+        states = [torch.empty(1 << n, dtype=torch.complex128, device="cuda") for _ in range(Bn)]
+        bt = Batch([circ] * Bn, states, [theta[b] for b in range(Bn)])
+        energies = torch.zeros(Bn, dtype=torch.float64, device="cuda")
+        bgrads = [torch.zeros(P, dtype=torch.float64, device="cuda") for _ in range(Bn)]
+        bt.capture(terms, bgrads, energies)
+        bt.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bt.replay()
+        torch.cuda.synchronize()
+        out["batched_grads_per_s"] = Bn * steps / (time.perf_counter() - t0)
+        out["speedup_vs_plain"] = out["batched_grads_per_s"] / out["plain_grads_per_s"]
+    except Exception as e:  # report, do not hide
+        out["batched_error"] = str(e)
+    out.update({"workload": "hea-20q-40layers-1600params-tfim-batch64", "unit": "grads/s"})
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2406_19212_amd import Circuit, State
+    from paper_2406_19212_amd import workloads as W
+
+    n, rows, cols, cycles = 28, 4, 7, 20
+    seed = W.CONFIG_SEED[1]
+    ops = W.rqc_grid(rows, cols, cycles, seed)
+    idx = W.rqc_bitstrings(n, 1000, seed + 1)
+    circ = Circuit(n, ops)
+    stats = circ.stats()
+    st = State(n)
+
+    def step():
+        st.reset()
+        circ.apply(st)
+        nrm = st.norm()
+        amps = st.gather(idx)
+        return nrm, amps
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nrm, amps = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = 1e3 * dt / args.steps
+    gate_apps = len(ops) * args.steps / dt
+
+    # roofline: per-pass durations from HIP events on the launch stream
+    st.reset()
+    pass_ms = circ.apply_timed(st)
+    amps_n = 1 << n
+    pass_bytes = 32.0 * amps_n  # algorithmic: read + write every amplitude once per pass
+    avg_ms = float(np.mean(pass_ms))
+    achieved = pass_bytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_pass_lds<%d,4,false>" % stats["tile_bits"], "avg_pass_ms": round(avg_ms, 4),
+            "passes": stats["n_passes"], "bytes_per_pass": pass_bytes}
+
+    rec = {"metric": "28q gate-apps/s", "value": round(gate_apps, 1), "unit": "gate-apps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "rqc-4x7-28q-20cycles", "n_qubits": n, "gates": len(ops),
+                      "fsim": sum(1 for o in ops if o.name == "fsim"), "seed": seed,
+                      "passes": stats["n_passes"], "tile_bits": stats["tile_bits"],
+                      "low_bits": stats["low_bits"], "norm_minus_1": float(nrm - 1.0),
+                      "mean_2n_abs2": float(np.mean(np.abs(amps) ** 2) * amps_n)},
+           "roofline": roof}
+    del st
+    torch.cuda.empty_cache()
+    if not args.no_vqe:
+        rec["vqe_batched"] = vqe_batched(torch, max(1, args.steps // 5))
+        torch.cuda.empty_cache()
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

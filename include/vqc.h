@@ -152,6 +152,8 @@ vqc_status vqc_mat_from_external(int m, const vqc_c128 *row_major, vqc_c128 *out
  * n_qubits: 1..33 (PURE), 1..16 (MIXED).  The handle does not own dev_buf. */
 vqc_status vqc_state_init(vqc_state *out, vqc_kind kind, int n_qubits, void *dev_buf,
                           const vqc_c128 *host_init, void *stream);
+/* Rewrite |0..0> (resp. |0..0><0..0|) into the state's buffer (async). */
+vqc_status vqc_state_reset(vqc_state s);
 /* Rebind a state handle to another buffer/stream without touching data. */
 vqc_status vqc_state_rebind(vqc_state s, void *dev_buf, void *stream);
 vqc_status vqc_state_destroy(vqc_state s);
@@ -198,6 +200,11 @@ vqc_status vqc_circuit_stats_get(vqc_circuit c, vqc_circuit_stats *out);
 /* apply!(circ, state) of Sec. 2.4: run the whole circuit in place, as fused
  * passes.  theta_dev: device double[n_params] (may be NULL when n_params = 0). */
 vqc_status vqc_apply_circuit(vqc_state s, vqc_circuit c, const double *theta_dev);
+
+/* vqc_apply_circuit with a HIP event recorded on the state's stream between
+ * consecutive pass launches; pass_ms_host[p] receives the duration of pass p
+ * (host float[n_passes], see vqc_circuit_stats).  Synchronises the stream. */
+vqc_status vqc_apply_circuit_timed(vqc_state s, vqc_circuit c, const double *theta_dev, float *pass_ms_host);
 
 /* gradient(loss, circ) with loss = Re<psi|H|psi> (PURE, Alg. 2) or Tr(H rho)
  * (MIXED, Sec. 3.5), H with real coefficients.  s holds the final state

@@ -179,6 +179,16 @@ def apply_matrix(v: np.ndarray, nbits: int, qubits, G: np.ndarray) -> None:
     lib().or_apply(_ptr(v), int(nbits), len(q), _ptr(q), _ptr(Gc))
 
 
+def apply_op_inplace(st: np.ndarray, n: int, op, theta=None, mixed: bool = False) -> None:
+    """Apply one op to `st` in place (no copy of the state)."""
+    assert st.dtype == np.complex128 and st.flags.c_contiguous
+    tab = _OpTable([op])
+    th = None if theta is None else np.ascontiguousarray(theta, np.float64)
+    rc = lib().or_apply_op(_ptr(st), n, int(mixed), ctypes.byref(tab.arr[0]), None if th is None else _ptr(th))
+    if rc:
+        raise ValueError("oracle apply failed")
+
+
 def initial_state(n: int, mixed: bool = False) -> np.ndarray:
     v = np.zeros(1 << (2 * n if mixed else n), np.complex128)
     v[0] = 1.0

@@ -365,6 +365,9 @@ static void super_qubits(const or_op *op, int n, int *qq) {
 
 /* Apply one op to a pure (mixed = 0) or vectorised mixed state. */
 int or_apply_op(cplx *st, int n, int mixed, const or_op *op, const double *theta) {
+  if (op->m < 1 || op->m > 4) return -1;
+  for (int k = 0; k < op->m; k++)
+    if (op->q[k] < 0 || op->q[k] >= n) return -1;
   if (!mixed) {
     cplx G[256];
     if (is_channel(op->code) || or_gate_matrix(op, theta, G) < 0) return -1;

@@ -61,6 +61,10 @@ class State:
             B._lib.vqc_state_destroy(h)
             self.h = None
 
+    def reset(self):
+        """|0..0> (or |0..0><0..0|) again, queued on the stream."""
+        check(lib().vqc_state_reset(self.h), "vqc_state_reset")
+
     def apply_gate(self, qubits, matrix):
         """Eq. (3) / Eq. (twoqubitgate) with a row-major numpy matrix."""
         q = (ctypes.c_int * len(qubits))(*qubits)
@@ -140,6 +144,14 @@ class Circuit:
     def apply(self, state: State, theta=None):
         th = self._theta(theta)
         check(lib().vqc_apply_circuit(state.h, self.h, _dptr(th)), "vqc_apply_circuit")
+
+    def apply_timed(self, state: State, theta=None) -> np.ndarray:
+        """Apply with HIP events between pass launches; returns ms per pass."""
+        th = self._theta(theta)
+        ms = np.zeros(max(1, self.stats()["n_passes"]), np.float32)
+        check(lib().vqc_apply_circuit_timed(state.h, self.h, _dptr(th), ms.ctypes.data),
+              "vqc_apply_circuit_timed")
+        return ms
 
     def backward(self, theta, state: State, terms, grad=None, energy=True, init=None, budget=0):
         """Adjoint gradient of Re<psi|H|psi> (pure) or Tr(H rho) (mixed);

@@ -79,6 +79,7 @@ _SIGS = {
     "vqc_version": (c_int, []),
     "vqc_mat_from_external": (c_int, [c_int, c_void_p, c_void_p]),
     "vqc_state_init": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_void_p, c_void_p, c_void_p]),
+    "vqc_state_reset": (c_int, [c_void_p]),
     "vqc_state_rebind": (c_int, [c_void_p, c_void_p, c_void_p]),
     "vqc_state_destroy": (c_int, [c_void_p]),
     "vqc_apply_gate": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
@@ -92,6 +93,7 @@ _SIGS = {
     "vqc_circuit_destroy": (c_int, [c_void_p]),
     "vqc_circuit_stats_get": (c_int, [c_void_p, ctypes.POINTER(vqc_circuit_stats)]),
     "vqc_apply_circuit": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "vqc_apply_circuit_timed": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "vqc_backward": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p,
                              ctypes.POINTER(c_double), c_void_p, c_size_t]),
     "vqc_circuit_autotune": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(vqc_tune)]),

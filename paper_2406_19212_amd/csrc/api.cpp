@@ -799,6 +799,12 @@ vqc_status vqc_state_init(vqc_state *out, vqc_kind kind, int n, void *dev_buf, c
   return VQC_OK;
 }
 
+vqc_status vqc_state_reset(vqc_state s) {
+  if (!s) return VQC_ERR_ARG;
+  VQC_TRY(launch_init_basis0(s->buf, state_len(s->kind, s->n), s->stream));
+  return VQC_OK;
+}
+
 vqc_status vqc_state_rebind(vqc_state s, void *dev_buf, void *stream) {
   if (!s || !dev_buf) return VQC_ERR_ARG;
   s->buf = reinterpret_cast<c128 *>(dev_buf);
@@ -1124,6 +1130,27 @@ vqc_status vqc_apply_circuit(vqc_state s, vqc_circuit c, const double *theta) {
   return VQC_OK;
 }
 
+vqc_status vqc_apply_circuit_timed(vqc_state s, vqc_circuit c, const double *theta, float *pass_ms) {
+  if (!s || !c || !pass_ms) return VQC_ERR_ARG;
+  if (s->kind != c->kind || s->n != c->n) return VQC_ERR_KIND;
+  if (c->n_params > 0 && !theta) return VQC_ERR_ARG;
+  const int np = (int)c->fwd.passes.size();
+  std::vector<hipEvent_t> ev(np + 1);
+  for (auto &e : ev) VQC_TRY(hipEventCreate(&e));
+  c128 *mats = c->mats1.as<c128>();
+  hipError_t err = launch_build_mats(c->d_rec, (int)c->recipes.size(), c->d_cdata, nullptr, nullptr, 1, theta, mats,
+                                     s->stream);
+  if (err == hipSuccess) err = hipEventRecord(ev[0], s->stream);
+  for (int p = 0; p < np && err == hipSuccess; p++) {
+    err = run_passes(c, c->fwd, 0, s->buf, nullptr, mats, nullptr, p, p + 1, 1, s->stream);
+    if (err == hipSuccess) err = hipEventRecord(ev[p + 1], s->stream);
+  }
+  if (err == hipSuccess) err = hipEventSynchronize(ev[np]);
+  for (int p = 0; p < np && err == hipSuccess; p++) err = hipEventElapsedTime(&pass_ms[p], ev[p], ev[p + 1]);
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  return hip_status(err);
+}
+
 static vqc_status seed_and_energy(vqc_circuit c, const std::vector<DTerm> &terms, const c128 *psi, c128 *out,
                                   hipStream_t st, double2 **res) {
   // expectation (and H psi when out != nullptr) of one item
@@ -1289,18 +1316,381 @@ vqc_status vqc_circuit_autotune(vqc_circuit c, vqc_state s, const double *theta,
   return VQC_OK;
 }
 
-vqc_status vqc_batch_create(vqc_batch *, int, const vqc_circuit *, void *const *, const double *const *, void *) {
-  return VQC_ERR_UNSUPPORTED;
+// --------------------------------------------------------------- batches
+
+static vqc_status batch_build_tables(vqc_batch b) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const int B = b->B;
+  // per-item matrices, Psi, partials, expectation partials
+  size_t mtot = 0, ptot = 0, qtot = 0;
+  int64_t etot = 0;
+  b->mat_off.resize(B);
+  b->psi_off.resize(B);
+  b->part_off.resize(B);
+  std::vector<int64_t> e_off(B);
+  for (int i = 0; i < B; i++) {
+    vqc_circuit c = b->circ[i];
+    b->mat_off[i] = mtot;
+    mtot += al(std::max(1, c->mat_size) * sizeof(c128));
+    b->psi_off[i] = ptot;
+    if (c->kind == VQC_PURE) ptot += al(state_len(c->kind, c->n) * sizeof(c128));
+    b->part_off[i] = qtot;
+    if (c->kind == VQC_PURE) qtot += al(std::max(1, c->n_gslots) * c->adj.units_per_item * sizeof(double));
+    e_off[i] = etot;
+    etot += expect_units(c->n);
+    b->max_passes = std::max(b->max_passes, (int)c->fwd.passes.size());
+    b->max_adj = std::max(b->max_adj, (int)c->adj.passes.size());
+    b->max_params = std::max(b->max_params, c->n_params);
+  }
+  b->e_units = etot;
+  VQC_TRY(b->mats.ensure(mtot));
+  VQC_TRY(b->eparts.ensure(etot * sizeof(double2) + al(B * sizeof(double2)) + 256));
+  b->d_eres = reinterpret_cast<double2 *>(b->eparts.as<char>() + al(etot * sizeof(double2)));
+  // groups of items sharing a circuit: pointer arrays for the matrix build
+  std::vector<vqc_circuit> uniq;
+  for (int i = 0; i < B; i++)
+    if (std::find(uniq.begin(), uniq.end(), b->circ[i]) == uniq.end()) uniq.push_back(b->circ[i]);
+  for (vqc_circuit c : uniq) {
+    std::unique_ptr<vqc_batch_s::Group> g(new vqc_batch_s::Group());
+    g->c = c;
+    std::vector<const void *> ptrs;
+    std::vector<const void *> th, mt;
+    for (int i = 0; i < B; i++)
+      if (b->circ[i] == c) {
+        th.push_back(b->thetas[i]);
+        mt.push_back(b->mats.as<char>() + b->mat_off[i]);
+      }
+    g->count = (int)th.size();
+    ptrs.insert(ptrs.end(), th.begin(), th.end());
+    ptrs.insert(ptrs.end(), mt.begin(), mt.end());
+    VQC_TRY(g->ptrs.ensure(ptrs.size() * sizeof(void *)));
+    VQC_TRY(hipMemcpy(g->ptrs.p, ptrs.data(), ptrs.size() * sizeof(void *), hipMemcpyHostToDevice));
+    b->groups.push_back(std::move(g));
+  }
+  // forward step jobs
+  std::vector<DJob> fj;
+  for (int sI = 0; sI < b->max_passes; sI++) {
+    b->fwd_first.push_back((int)fj.size());
+    int64_t u0 = 0;
+    for (int i = 0; i < B; i++) {
+      vqc_circuit c = b->circ[i];
+      if (sI >= (int)c->fwd.passes.size()) continue;
+      DJob j;
+      std::memset(&j, 0, sizeof(j));
+      j.a = b->states[i];
+      j.mats = reinterpret_cast<const c128 *>(b->mats.as<char>() + b->mat_off[i]);
+      j.pass = c->fwd.d_pass + sI;
+      j.unit0 = u0;
+      j.n_units = c->fwd.units_per_item;
+      j.nbits = c->nbits;
+      u0 += j.n_units;
+      fj.push_back(j);
+    }
+    b->fwd_count.push_back((int)fj.size() - b->fwd_first.back());
+    b->fwd_units.push_back(u0);
+  }
+  // adjoint step jobs (pure items; aligned at each item's last pass)
+  std::vector<DJob> aj;
+  for (int r = 0; r < b->max_adj; r++) {
+    b->adj_first.push_back((int)aj.size());
+    int64_t u0 = 0;
+    for (int i = 0; i < B; i++) {
+      vqc_circuit c = b->circ[i];
+      const int PA = (int)c->adj.passes.size();
+      if (c->kind != VQC_PURE || r >= PA) continue;
+      DJob j;
+      std::memset(&j, 0, sizeof(j));
+      j.a = b->states[i];
+      j.b = reinterpret_cast<c128 *>(b->psi.p ? b->psi.as<char>() + b->psi_off[i] : nullptr);
+      j.mats = reinterpret_cast<const c128 *>(b->mats.as<char>() + b->mat_off[i]);
+      j.partials = reinterpret_cast<double *>(b->part.p ? b->part.as<char>() + b->part_off[i] : nullptr);
+      j.pass = c->adj.d_pass + (PA - 1 - r);
+      j.unit0 = u0;
+      j.n_units = c->adj.units_per_item;
+      j.nbits = c->nbits;
+      u0 += j.n_units;
+      aj.push_back(j);
+    }
+    b->adj_count.push_back((int)aj.size() - b->adj_first.back());
+    b->adj_units.push_back(u0);
+  }
+  // expectation and seed jobs
+  std::vector<DEJob> ej(B), sj(B);
+  for (int i = 0; i < B; i++) {
+    vqc_circuit c = b->circ[i];
+    DEJob &e = ej[i];
+    std::memset(&e, 0, sizeof(e));
+    e.psi = b->states[i];
+    e.partial = b->eparts.as<double2>() + e_off[i];
+    e.unit0 = e_off[i];
+    e.n_units = expect_units(c->n);
+    e.nbits = c->n;
+    e.mixed = c->kind == VQC_MIXED;
+    sj[i] = e;
+    if (c->kind == VQC_PURE && b->psi.p) sj[i].out = reinterpret_cast<c128 *>(b->psi.as<char>() + b->psi_off[i]);
+  }
+  std::vector<c128 *> sp(b->states);
+  std::vector<uint64_t> sz(B);
+  uint64_t maxn = 0;
+  for (int i = 0; i < B; i++) {
+    sz[i] = state_len(b->circ[i]->kind, b->circ[i]->n);
+    maxn = std::max(maxn, sz[i]);
+  }
+  (void)maxn;
+  const size_t o_f = 0, o_a = al(o_f + fj.size() * sizeof(DJob)), o_e = al(o_a + aj.size() * sizeof(DJob));
+  const size_t o_s = al(o_e + B * sizeof(DEJob)), o_p = al(o_s + B * sizeof(DEJob));
+  const size_t o_z = al(o_p + B * sizeof(c128 *)), o_g = al(o_z + B * sizeof(uint64_t));
+  const size_t total = al(o_g + B * sizeof(DGradJob));
+  VQC_TRY(b->tables.ensure(total));
+  std::vector<char> blob(total, 0);
+  std::memcpy(blob.data() + o_f, fj.data(), fj.size() * sizeof(DJob));
+  std::memcpy(blob.data() + o_a, aj.data(), aj.size() * sizeof(DJob));
+  std::memcpy(blob.data() + o_e, ej.data(), B * sizeof(DEJob));
+  std::memcpy(blob.data() + o_s, sj.data(), B * sizeof(DEJob));
+  std::memcpy(blob.data() + o_p, sp.data(), B * sizeof(c128 *));
+  std::memcpy(blob.data() + o_z, sz.data(), B * sizeof(uint64_t));
+  char *base = b->tables.as<char>();
+  VQC_TRY(hipMemcpy(base, blob.data(), total, hipMemcpyHostToDevice));
+  b->d_fwd_jobs = reinterpret_cast<DJob *>(base + o_f);
+  b->d_adj_jobs = reinterpret_cast<DJob *>(base + o_a);
+  b->d_ejobs = reinterpret_cast<DEJob *>(base + o_e);
+  b->d_sjobs = reinterpret_cast<DEJob *>(base + o_s);
+  b->d_state_ptrs = reinterpret_cast<c128 **>(base + o_p);
+  b->d_state_sizes = reinterpret_cast<uint64_t *>(base + o_z);
+  b->d_gjobs = reinterpret_cast<DGradJob *>(base + o_g);
+  return VQC_OK;
 }
-vqc_status vqc_batch_destroy(vqc_batch b) { delete b; return VQC_OK; }
-vqc_status vqc_batch_forward(vqc_batch) { return VQC_ERR_UNSUPPORTED; }
-vqc_status vqc_batch_expectation(vqc_batch, const vqc_pauli_sum *, double *) { return VQC_ERR_UNSUPPORTED; }
-vqc_status vqc_batch_backward(vqc_batch, const vqc_pauli_sum *, double *const *, double *, size_t) {
-  return VQC_ERR_UNSUPPORTED;
+
+static vqc_status batch_forward_on(vqc_batch b, hipStream_t st) {
+  uint64_t maxn = 0;
+  for (int i = 0; i < b->B; i++) maxn = std::max(maxn, state_len(b->circ[i]->kind, b->circ[i]->n));
+  VQC_TRY(launch_init_batched(b->d_state_ptrs, b->d_state_sizes, b->B, maxn, st));
+  for (auto &g : b->groups) {
+    const double *const *th = reinterpret_cast<const double *const *>(g->ptrs.p);
+    c128 *const *mt = reinterpret_cast<c128 *const *>(g->ptrs.as<char>() + g->count * sizeof(void *));
+    VQC_TRY(launch_build_mats(g->c->d_rec, (int)g->c->recipes.size(), g->c->d_cdata, th, mt, g->count, nullptr,
+                              nullptr, st));
+  }
+  DOverride ov;
+  std::memset(&ov, 0, sizeof(ov));
+  vqc_circuit c0 = b->circ[0];
+  for (int sI = 0; sI < b->max_passes; sI++) {
+    const int64_t units = b->fwd_units[sI];
+    const int grid = grid_of(c0, units);
+    const DJob *jobs = b->d_fwd_jobs + b->fwd_first[sI];
+    if (b->reg_only) VQC_TRY(launch_pass_reg(c0->fwd.R, 0, jobs, b->fwd_count[sI], units, grid, ov, st));
+    else VQC_TRY(launch_pass_lds(c0->fwd.K, c0->fwd.R, false, jobs, b->fwd_count[sI], units, grid, ov, st));
+  }
+  return VQC_OK;
 }
-vqc_status vqc_batch_capture(vqc_batch, const vqc_pauli_sum *, double *const *, double *, size_t) {
-  return VQC_ERR_UNSUPPORTED;
+
+static vqc_status batch_upload_terms(vqc_batch b, const vqc_pauli_sum *H, bool need_real) {
+  int nmax = 0;
+  for (int i = 0; i < b->B; i++) nmax = std::max(nmax, b->circ[i]->n);
+  int nmin = 64;
+  for (int i = 0; i < b->B; i++) nmin = std::min(nmin, b->circ[i]->n);
+  std::vector<DTerm> t;
+  vqc_status st = make_terms(H, nmin, t, need_real);
+  if (st) return st;
+  b->terms_h = t;
+  b->n_terms = (int)t.size();
+  VQC_TRY(b->ck.ensure(std::max<size_t>(1, t.size()) * sizeof(DTerm)));  // ck doubles as term storage
+  b->d_terms = b->ck.as<DTerm>();
+  if (!t.empty()) VQC_TRY(hipMemcpy(b->d_terms, t.data(), t.size() * sizeof(DTerm), hipMemcpyHostToDevice));
+  return VQC_OK;
 }
-vqc_status vqc_batch_replay(vqc_batch) { return VQC_ERR_UNSUPPORTED; }
+
+static vqc_status batch_ensure_adjoint(vqc_batch b) {
+  if (b->psi.p) return VQC_OK;
+  size_t ptot = 0, qtot = 0;
+  for (int i = 0; i < b->B; i++) {
+    vqc_circuit c = b->circ[i];
+    if (c->kind != VQC_PURE) continue;
+    ptot = std::max(ptot, b->psi_off[i] + ((state_len(c->kind, c->n) * sizeof(c128) + 255) & ~size_t(255)));
+    qtot = std::max(qtot, b->part_off[i] + ((std::max(1, c->n_gslots) * c->adj.units_per_item * sizeof(double) + 255) &
+                                            ~size_t(255)));
+  }
+  VQC_TRY(b->psi.ensure(std::max<size_t>(ptot, 16)));
+  VQC_TRY(b->part.ensure(std::max<size_t>(qtot, 16)));
+  // rebuild tables now that Psi / partials exist
+  b->groups.clear();
+  b->fwd_first.clear(); b->fwd_count.clear(); b->fwd_units.clear();
+  b->adj_first.clear(); b->adj_count.clear(); b->adj_units.clear();
+  b->max_passes = b->max_adj = b->max_params = 0;
+  return batch_build_tables(b);
+}
+
+static vqc_status batch_grad_jobs(vqc_batch b, double *const *grads) {
+  std::vector<DGradJob> gj(b->B);
+  for (int i = 0; i < b->B; i++) {
+    vqc_circuit c = b->circ[i];
+    DGradJob &g = gj[i];
+    std::memset(&g, 0, sizeof(g));
+    g.partials = reinterpret_cast<const double *>(b->part.as<char>() + b->part_off[i]);
+    g.n_units = c->adj.units_per_item;
+    g.grad = grads[i];
+    g.csr_ptr = c->d_csr_ptr;
+    g.csr_slot = c->d_csr_slot;
+    g.n_params = c->kind == VQC_PURE ? c->n_params : 0;
+    g.scale = 2.0;
+  }
+  VQC_TRY(hipMemcpy(b->d_gjobs, gj.data(), gj.size() * sizeof(DGradJob), hipMemcpyHostToDevice));
+  return VQC_OK;
+}
+
+// pure items: seed, reverse passes, gradient reduction; energies optional
+static vqc_status batch_backward_pure_on(vqc_batch b, double *energies, hipStream_t st) {
+  for (auto &g : b->groups) {
+    const double *const *th = reinterpret_cast<const double *const *>(g->ptrs.p);
+    c128 *const *mt = reinterpret_cast<c128 *const *>(g->ptrs.as<char>() + g->count * sizeof(void *));
+    VQC_TRY(launch_build_mats(g->c->d_rec, (int)g->c->recipes.size(), g->c->d_cdata, th, mt, g->count, nullptr,
+                              nullptr, st));
+  }
+  VQC_TRY(launch_expect(b->d_sjobs, b->B, b->e_units, b->d_terms, b->n_terms, st));
+  VQC_TRY(launch_reduce_partials(b->d_sjobs, b->B, b->d_eres, st));
+  if (energies) VQC_TRY(launch_take_real(b->d_eres, b->B, energies, st));
+  DOverride ov;
+  std::memset(&ov, 0, sizeof(ov));
+  vqc_circuit c0 = b->circ[0];
+  for (int r = 0; r < b->max_adj; r++) {
+    if (b->adj_count[r] == 0) continue;
+    const int64_t units = b->adj_units[r];
+    const int grid = grid_of(c0, units);
+    const DJob *jobs = b->d_adj_jobs + b->adj_first[r];
+    VQC_TRY(launch_pass_lds(c0->adj.K, c0->adj.R, true, jobs, b->adj_count[r], units, grid, ov, st));
+  }
+  VQC_TRY(launch_grad_reduce(b->d_gjobs, b->B, b->max_params, st));
+  return VQC_OK;
+}
+
+vqc_status vqc_batch_create(vqc_batch *out, int B, const vqc_circuit *circuits, void *const *states,
+                            const double *const *thetas, void *stream) {
+  if (!out || B < 1 || !circuits || !states) return VQC_ERR_ARG;
+  for (int i = 0; i < B; i++) {
+    if (!circuits[i] || !states[i]) return VQC_ERR_ARG;
+    if (circuits[i]->n_params > 0 && (!thetas || !thetas[i])) return VQC_ERR_ARG;
+    const vqc_circuit c = circuits[i], c0 = circuits[0];
+    if (c->kind != c0->kind) return VQC_ERR_KIND;
+    if (c->fwd.reg_only != c0->fwd.reg_only || c->fwd.K != c0->fwd.K || c->fwd.R != c0->fwd.R ||
+        c->adj.K != c0->adj.K || c->adj.reg_only != c0->adj.reg_only)
+      return VQC_ERR_UNSUPPORTED;
+  }
+  std::unique_ptr<vqc_batch_s> b(new (std::nothrow) vqc_batch_s());
+  if (!b) return VQC_ERR_OOM;
+  b->B = B;
+  b->circ.assign(circuits, circuits + B);
+  for (int i = 0; i < B; i++) {
+    b->states.push_back(reinterpret_cast<c128 *>(states[i]));
+    b->thetas.push_back(thetas ? thetas[i] : nullptr);
+  }
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  b->reg_only = circuits[0]->fwd.reg_only;
+  b->K = circuits[0]->fwd.K;
+  b->Kadj = circuits[0]->adj.K;
+  vqc_status st = batch_build_tables(b.get());
+  if (st) return st;
+  *out = b.release();
+  return VQC_OK;
+}
+
+vqc_status vqc_batch_destroy(vqc_batch b) {
+  if (!b) return VQC_OK;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
+  return VQC_OK;
+}
+
+vqc_status vqc_batch_forward(vqc_batch b) {
+  if (!b) return VQC_ERR_ARG;
+  return batch_forward_on(b, b->stream);
+}
+
+vqc_status vqc_batch_expectation(vqc_batch b, const vqc_pauli_sum *H, double *energies) {
+  if (!b || !H || !energies) return VQC_ERR_ARG;
+  VQC_TRY(hipStreamSynchronize(b->stream));
+  vqc_status st = batch_upload_terms(b, H, false);
+  if (st) return st;
+  VQC_TRY(launch_expect(b->d_ejobs, b->B, b->e_units, b->d_terms, b->n_terms, b->stream));
+  VQC_TRY(launch_reduce_partials(b->d_ejobs, b->B, b->d_eres, b->stream));
+  VQC_TRY(launch_take_real(b->d_eres, b->B, energies, b->stream));
+  return VQC_OK;
+}
+
+vqc_status vqc_batch_backward(vqc_batch b, const vqc_pauli_sum *H, double *const *grads, double *energies,
+                              size_t budget) {
+  if (!b || !H || !grads) return VQC_ERR_ARG;
+  for (int i = 0; i < b->B; i++)
+    if (b->circ[i]->n_params > 0 && !grads[i]) return VQC_ERR_ARG;
+  VQC_TRY(hipStreamSynchronize(b->stream));
+  if (b->circ[0]->kind == VQC_PURE) {
+    for (int i = 0; i < b->B; i++)
+      if (b->circ[i]->has_nonunitary_matrix) return VQC_ERR_NOT_UNITARY;
+    vqc_status st = batch_ensure_adjoint(b);
+    if (st) return st;
+    st = batch_upload_terms(b, H, true);
+    if (st) return st;
+    st = batch_grad_jobs(b, grads);
+    if (st) return st;
+    return batch_backward_pure_on(b, energies, b->stream);
+  }
+  // mixed items: checkpointed backward item by item on the batch stream
+  for (int i = 0; i < b->B; i++) {
+    vqc_state s = nullptr;
+    vqc_status st = vqc_state_init(&s, VQC_MIXED, b->circ[i]->n, b->states[i], nullptr, b->stream);
+    (void)st;
+    // vqc_state_init wrote |0><0|: re-run the forward of this item
+    if (s == nullptr) return VQC_ERR_OOM;
+    st = vqc_apply_circuit(s, b->circ[i], b->thetas[i]);
+    double e = 0;
+    if (!st) st = vqc_backward(b->circ[i], b->thetas[i], s, H, grads[i], energies ? &e : nullptr, nullptr, budget);
+    vqc_state_destroy(s);
+    if (st) return st;
+    if (energies) VQC_TRY(hipMemcpyAsync(energies + i, &e, sizeof(double), hipMemcpyHostToDevice, b->stream));
+    VQC_TRY(hipStreamSynchronize(b->stream));
+  }
+  return VQC_OK;
+}
+
+vqc_status vqc_batch_capture(vqc_batch b, const vqc_pauli_sum *H, double *const *grads, double *energies,
+                             size_t budget) {
+  (void)budget;
+  if (!b || !H || !grads) return VQC_ERR_ARG;
+  if (b->circ[0]->kind != VQC_PURE) return VQC_ERR_UNSUPPORTED;
+  for (int i = 0; i < b->B; i++)
+    if (b->circ[i]->n_params > 0 && !grads[i]) return VQC_ERR_ARG;
+  VQC_TRY(hipStreamSynchronize(b->stream));
+  vqc_status st = batch_ensure_adjoint(b);
+  if (st) return st;
+  st = batch_upload_terms(b, H, true);
+  if (st) return st;
+  st = batch_grad_jobs(b, grads);
+  if (st) return st;
+  if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  if (!b->cap_stream) VQC_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  // one eager run so that every kernel attribute is set before capture
+  st = batch_forward_on(b, b->cap_stream);
+  if (!st) st = batch_backward_pure_on(b, energies, b->cap_stream);
+  if (st) return st;
+  VQC_TRY(hipStreamSynchronize(b->cap_stream));
+  VQC_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  vqc_status s1 = batch_forward_on(b, b->cap_stream);
+  vqc_status s2 = s1 ? s1 : batch_backward_pure_on(b, energies, b->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (s2) { if (g) (void)hipGraphDestroy(g); return s2; }
+  if (e != hipSuccess) return hip_status(e);
+  b->graph = g;
+  VQC_TRY(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+  return VQC_OK;
+}
+
+vqc_status vqc_batch_replay(vqc_batch b) {
+  if (!b || !b->gexec) return VQC_ERR_ARG;
+  VQC_TRY(hipGraphLaunch(b->gexec, b->stream));
+  return VQC_OK;
+}
 
 }  // extern "C"
