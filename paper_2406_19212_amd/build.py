@@ -22,9 +22,13 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 def units():
     out = []
-    for K in range(5, 14):
-        for A in (0, 1):
-            out.append(("inst_lds.hip", ["-DVQC_K=%d" % K, "-DVQC_ADJ=%d" % A], "lds_%d_%d" % (K, A)))
+    for R, Ks in ((4, range(5, 14)), (3, range(8, 14))):
+        for K in Ks:
+            for A in (0, 1):
+                if R == 3 and A == 1 and K > 12:
+                    continue
+                out.append(("inst_lds.hip", ["-DVQC_K=%d" % K, "-DVQC_R=%d" % R, "-DVQC_ADJ=%d" % A],
+                            "lds_%d_%d_%d" % (K, R, A)))
     for R in (1, 2, 3, 4):
         for M in (0, 1, 2):
             out.append(("inst_reg.hip", ["-DVQC_R=%d" % R, "-DVQC_MODE=%d" % M], "reg_%d_%d" % (R, M)))

@@ -20,7 +20,7 @@ using namespace vqc;
 
 namespace {
 
-constexpr int kDefaultTile = 12;
+constexpr int kDefaultTile = 11;
 constexpr int kDefaultAdjTile = 11;
 constexpr int kDefaultLow = 4;
 constexpr int kR = 4;
@@ -83,19 +83,37 @@ bool valid_type(int t) {
          (t >= VQC_AMPLITUDE_DAMPING && t <= VQC_KRAUS);
 }
 
-// register kind of a gate matrix (pure path)
-int gate_kind(int type, int m) {
+// register kind of a gate matrix.  Structured kinds touch fewer FP64
+// operations: real matrices (H, X, Ry), real-diagonal/imaginary-off-diagonal
+// ones (Rx, Y), diagonal ones (Rz; Z, S, T change only the |1> half), fSim
+// with Delta = 0.  sqrt(X), sqrt(Y), sqrt(W) are real/structured up to the
+// global phase e^{i pi/4}; `factored` selects that form (pure states only).
+int gate_kind(const vqc_op &op, bool factored) {
+  const int type = op.type, m = op.n_qubits;
   switch (type) {
-    case VQC_Z: case VQC_S: case VQC_T: case VQC_RZ: return GK_DIAG1;
+    case VQC_Z: case VQC_S: case VQC_T: return GK_PHASE1;
+    case VQC_RZ: return GK_DIAG1;
+    case VQC_H: case VQC_X: case VQC_RY: return GK_REAL1;
+    case VQC_Y: case VQC_RX: return GK_XROT1;
+    case VQC_SX: return factored ? GK_XROT1 : GK_DENSE1;
+    case VQC_SY: return factored ? GK_REAL1 : GK_DENSE1;
+    case VQC_SW: return factored ? GK_RDIAG1 : GK_DENSE1;
     case VQC_ID: return GK_NONE;
     case VQC_CZ: case VQC_CRZ: return GK_DIAG2;
     case VQC_CNOT: return GK_CX;
-    case VQC_SWAP: case VQC_ISWAP: case VQC_FSIM: return GK_FSIM;
+    case VQC_FSIM: {
+      bool plain = true;
+      for (int k = 2; k < 5; k++) plain &= op.params[k] == 0.0 && op.param_index[k] < 0;
+      return plain ? GK_FSIMX : GK_FSIM;
+    }
+    case VQC_SWAP: case VQC_ISWAP: return GK_FSIM;
     case VQC_CRX: case VQC_CRY: case VQC_CONTROL: return GK_DENSE2;
     case VQC_MATRIX: return m == 1 ? GK_DENSE1 : GK_DENSE2;
     default: return GK_DENSE1;
   }
 }
+
+bool phase_factored(int type) { return type == VQC_SX || type == VQC_SY || type == VQC_SW; }
 
 // row-major copy of a column-major ABI matrix
 void to_row_major(const vqc_c128 *cm, int d, std::vector<c128> &out) {
@@ -272,49 +290,88 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
       if ((tile >> b) & 1) ph.tq.push_back(b);
     int loc[64];
     for (int i = 0; i < (int)ph.tq.size(); i++) loc[ph.tq[i]] = i;
-    // stages over tile-local bits
-    std::vector<int> srem = chosen;
-    while (!srem.empty()) {
-      uint64_t reg = 0, sblk = 0;
-      int order4[4] = {-1, -1, -1, -1};
-      std::vector<int> st, sleft;
-      for (int i : srem) {
-        uint64_t lm = 0;
-        for (int t = 0; t < E[i].nq; t++) lm |= 1ull << loc[E[i].q[t]];
-        bool ok = !(lm & sblk) && popc(reg | lm) <= R;
-        if (ok && E[i].kind == GK_DENSE4) {
-          if (order4[0] >= 0) {
-            for (int t = 0; t < 4; t++)
-              if (order4[t] != loc[E[i].q[t]]) ok = false;
-          } else if (reg & ~lm) {
-            ok = false;
+    // stages over tile-local bits: plain first fit, and a variant whose first
+    // stage defers ops on the low c bits so it can read HBM directly; keep
+    // the one with fewer LDS round trips
+    const uint64_t lowloc = reg_only ? 0 : ((1ull << c) - 1);
+    auto cost = [&](const std::vector<PassH::Stage> &st) {
+      if (st.empty()) return 0;
+      auto mask = [&](const PassH::Stage &S) {
+        uint64_t m = 0;
+        for (int i = 0; i < R; i++) m |= 1ull << S.rbit[i];
+        return m;
+      };
+      return 2 * (int)st.size() + ((mask(st.front()) & lowloc) ? 1 : 0) + ((mask(st.back()) & lowloc) ? 1 : 0);
+    };
+    std::vector<PassH::Stage> best;
+    std::vector<int> best_rest;
+    for (int attempt = 0; attempt < (reg_only ? 1 : 2); attempt++) {
+      std::vector<PassH::Stage> stages;
+      std::vector<int> srem = chosen, rest;
+      while (!srem.empty()) {
+        uint64_t reg = 0, sblk = 0;
+        if (attempt == 1 && stages.empty()) sblk = lowloc;  // first stage: defer low bits
+        int order4[4] = {-1, -1, -1, -1};
+        std::vector<int> st, sleft;
+        for (int i : srem) {
+          uint64_t lm = 0;
+          for (int t = 0; t < E[i].nq; t++) lm |= 1ull << loc[E[i].q[t]];
+          bool ok = !(lm & sblk) && popc(reg | lm) <= R;
+          if (ok && E[i].kind == GK_DENSE4) {
+            if (order4[0] >= 0) {
+              for (int t = 0; t < 4; t++)
+                if (order4[t] != loc[E[i].q[t]]) ok = false;
+            } else if (reg & ~lm) {
+              ok = false;
+            }
           }
+          if (ok && order4[0] >= 0 && (lm & ~reg)) ok = false;
+          if (!ok) { sblk |= lm; sleft.push_back(i); continue; }
+          reg |= lm;
+          st.push_back(i);
+          if (E[i].kind == GK_DENSE4 && order4[0] < 0)
+            for (int t = 0; t < 4; t++) order4[t] = loc[E[i].q[t]];
         }
-        if (ok && order4[0] >= 0 && (lm & ~reg)) ok = false;
-        if (!ok) { sblk |= lm; sleft.push_back(i); continue; }
-        reg |= lm;
-        st.push_back(i);
-        if (E[i].kind == GK_DENSE4 && order4[0] < 0)
-          for (int t = 0; t < 4; t++) order4[t] = loc[E[i].q[t]];
+        if (st.empty()) {
+          // nothing fitted (possible only when the first stage deferred the
+          // low bits): drop the deferral for this stage
+          if (attempt == 1 && stages.empty()) { attempt = 2; break; }
+          // an op wider than the register set cannot be planned; take it
+          // alone so the loop always progresses (lowering never emits one)
+          st.push_back(sleft.front());
+          sleft.erase(sleft.begin());
+        }
+        srem.swap(sleft);
+        PassH::Stage S;
+        if (order4[0] >= 0) {
+          for (int t = 0; t < 4; t++) S.rbit[t] = order4[t];
+        } else {
+          // pad with bits outside the low range first, so a stage stays low-free
+          for (int b = TK - 1; b >= 0 && popc(reg) < R; b--)
+            if (!((lowloc >> b) & 1) && !((reg >> b) & 1)) reg |= 1ull << b;
+          for (int b = 0; b < TK && popc(reg) < R; b++) reg |= 1ull << b;
+          int k = 0;
+          for (int b = 0; b < TK; b++)
+            if ((reg >> b) & 1) S.rbit[k++] = b;
+        }
+        S.elems = st;
+        stages.push_back(S);
+        if (reg_only && !srem.empty()) {
+          rest = srem;
+          break;
+        }
       }
-      srem.swap(sleft);
-      PassH::Stage S;
-      if (order4[0] >= 0) {
-        for (int t = 0; t < 4; t++) S.rbit[t] = order4[t];
-      } else {
-        for (int b = 0; b < TK && popc(reg) < R; b++) reg |= 1ull << b;
-        int k = 0;
-        for (int b = 0; b < TK; b++)
-          if ((reg >> b) & 1) S.rbit[k++] = b;
+      if (attempt == 2) continue;
+      if (best.empty() || cost(stages) < cost(best)) {
+        best = stages;
+        best_rest = rest;
       }
-      S.elems = st;
-      ph.stages.push_back(S);
-      if (reg_only && !srem.empty()) {
-        // register-only passes hold exactly one stage: push the rest back
-        for (int i : srem) rem.push_back(i);
-        std::sort(rem.begin(), rem.end());
-        break;
-      }
+    }
+    ph.stages = best;
+    if (reg_only && !best_rest.empty()) {
+      // register-only passes hold exactly one stage: push the rest back
+      for (int i : best_rest) rem.push_back(i);
+      std::sort(rem.begin(), rem.end());
     }
     P.passes.push_back(ph);
   }
@@ -430,16 +487,18 @@ int add_recipe(vqc_circuit c, int type, int form, int k, int nq, const vqc_op &o
 vqc_status lower(vqc_circuit c) {
   const int n = c->n;
   const bool mixed = c->kind == VQC_MIXED;
+  int n_factored = 0;
   for (size_t j = 0; j < c->ops.size(); j++) {
     const vqc_op &op = c->ops[j];
     const int m = op.n_qubits, d = 1 << m;
     int data_off = -1, n_data = 0;
     if (op.data && op.n_data > 0) {
       data_off = (int)c->cdata.size();
-      const int blocks = op.n_data / (d * d);
-      for (int s = 0; s < blocks; s++) {
-        if (op.type == VQC_CONTROL) to_row_major(op.data, 2, c->cdata);
-        else to_row_major(op.data + (size_t)s * d * d, d, c->cdata);
+      if (op.type == VQC_CONTROL) {
+        to_row_major(op.data, 2, c->cdata);  // the 2x2 target block
+      } else {
+        const int blocks = op.n_data / (d * d);
+        for (int s = 0; s < blocks; s++) to_row_major(op.data + (size_t)s * d * d, d, c->cdata);
       }
       n_data = op.n_data;
     }
@@ -466,13 +525,17 @@ vqc_status lower(vqc_circuit c) {
       c->elems.push_back(e);
       continue;
     }
-    const int gk = gate_kind(op.type, m);
+    const int gk = gate_kind(op, !mixed);
     if (!mixed) {
       Elem e;
       e.nq = m;
       e.kind = gk;
       for (int t = 0; t < m; t++) e.q[t] = op.qubits[t];
-      e.mat = (gk == GK_CX || gk == GK_NONE) ? -1 : add_recipe(c, op.type, RF_GATE, 0, m, op, data_off, n_data, d * d);
+      const bool fac = phase_factored(op.type);
+      n_factored += fac;
+      e.mat = (gk == GK_CX || gk == GK_NONE)
+                  ? -1
+                  : add_recipe(c, op.type, fac ? RF_GATE_F : RF_GATE, 0, m, op, data_off, n_data, d * d);
       for (int k = 0; k < 5; k++)
         if (op.param_index[k] >= 0) {
           const int dk = (m == 1) ? (gk == GK_DIAG1 ? GK_DIAG1 : GK_DENSE1) : GK_DENSE2;
@@ -504,6 +567,18 @@ vqc_status lower(vqc_circuit c) {
         }
       c->elems.push_back(e);
     }
+  }
+  if ((n_factored & 7) != 0) {
+    // the product of the factored phases, e^{i pi n/4}, as one diagonal op
+    vqc_op ph;
+    std::memset(&ph, 0, sizeof(ph));
+    for (int k = 0; k < 5; k++) ph.param_index[k] = -1;
+    Elem e;
+    e.nq = 1;
+    e.kind = GK_DIAG1;
+    e.q[0] = 0;
+    e.mat = add_recipe(c, VQC_ID, RF_GPHASE, n_factored & 7, 1, ph, -1, 0, 4);
+    c->elems.push_back(e);
   }
   return VQC_OK;
 }
@@ -567,6 +642,14 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
     dp.K = ph.K;
     dp.nst = (int)ph.stages.size();
     dp.nvar = nvar;
+    if (!P.reg_only && !ph.stages.empty()) {
+      auto lowfree = [&](const PassH::Stage &S) {
+        for (int i = 0; i < P.R; i++)
+          if (S.rbit[i] < P.c) return false;
+        return true;
+      };
+      dp.lowfree = (lowfree(ph.stages.front()) ? 1 : 0) | (lowfree(ph.stages.back()) ? 2 : 0);
+    }
     for (int i = 0; i < ph.K; i++) dp.tq[i] = (int8_t)ph.tq[i];
   }
   P.n_stages = (int)stages.size();
@@ -616,7 +699,12 @@ vqc_status make_plans(vqc_circuit c) {
   int low = c->tune.low_bits > 0 ? c->tune.low_bits : kDefaultLow;
   if (K > kMaxTile) K = kMaxTile;
   const bool reg_only = mixed || nb < 5;
-  const int R = std::min(kR, nb);
+  int R = std::min(kR, nb);
+  int Radj = R;
+  if (!reg_only && c->tune.reg_bits == 3) {
+    R = 3;
+    Radj = 3;
+  }
   if (reg_only) {
     plan_passes(c->elems, nb, R, 0, R, true, c->fwd, kMaxVarPerPass);
     vqc_status st = upload_plan(c, c->fwd, false);
@@ -625,13 +713,15 @@ vqc_status make_plans(vqc_circuit c) {
     st = upload_plan(c, c->adj, true);
     if (st) return st;
   } else {
-    K = std::max(5, std::min(K, nb));
+    const int kmin = R == 3 ? 8 : 5;
+    if (nb < kmin) { R = Radj = 4; }
+    K = std::max(R == 3 ? 8 : 5, std::min(K, nb));
     low = std::min(low, K - 1);
-    int Ka = std::max(5, std::min(std::min(K, kDefaultAdjTile), nb));
+    int Ka = std::max(Radj == 3 ? 8 : 5, std::min(std::min(K, kDefaultAdjTile), nb));
     plan_passes(c->elems, nb, K, low, R, false, c->fwd, 0);
     vqc_status st = upload_plan(c, c->fwd, false);
     if (st) return st;
-    plan_passes(c->elems, nb, Ka, std::min(low, Ka - 1), R, false, c->adj, kMaxVarPerPass);
+    plan_passes(c->elems, nb, Ka, std::min(low, Ka - 1), Radj, false, c->adj, kMaxVarPerPass);
     st = upload_plan(c, c->adj, true);
     if (st) return st;
   }
@@ -1062,7 +1152,7 @@ vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops,
   if (kind != VQC_PURE && kind != VQC_MIXED) return VQC_ERR_ARG;
   if (n < 1 || (kind == VQC_PURE && n > 33) || (kind == VQC_MIXED && n > 16)) return VQC_ERR_ARG;
   if (tune && (tune->tile_bits < 0 || tune->tile_bits > kMaxTile || tune->low_bits < 0 || tune->grid_blocks < 0 ||
-               (tune->reg_bits != 0 && tune->reg_bits != kR)))
+               (tune->reg_bits != 0 && tune->reg_bits != 3 && tune->reg_bits != 4)))
     return VQC_ERR_ARG;
   for (int j = 0; j < n_ops; j++) {
     vqc_status st = validate_op(ops[j], n, kind, n_params);

@@ -14,6 +14,15 @@ __device__ __forceinline__ c128 C(double re, double im) { return make_double2(re
 // the derivative is identically zero, -1 on an unknown type.
 __device__ int dev_gate(int type, const double *p, int k, const c128 *data, int n_data, c128 *G) {
   const double r2 = 0.70710678118654752440;
+  // k == -2: sqrt(X), sqrt(Y), sqrt(W) without their global phase e^{i pi/4}
+  if (k == -2) {
+    switch (type) {
+      case VQC_SX: G[0] = C(r2, 0); G[1] = C(0, -r2); G[2] = C(0, -r2); G[3] = C(r2, 0); return 2;
+      case VQC_SY: G[0] = C(r2, 0); G[1] = C(-r2, 0); G[2] = C(r2, 0); G[3] = C(r2, 0); return 2;
+      case VQC_SW: G[0] = C(r2, 0); G[1] = C(-0.5, -0.5); G[2] = C(0.5, -0.5); G[3] = C(r2, 0); return 2;
+      default: k = -1; break;
+    }
+  }
   int d = (type >= VQC_CZ) ? 4 : 2;
   if (type == VQC_MATRIX) d = (n_data == 16) ? 4 : 2;
   for (int i = 0; i < d * d; i++) G[i] = C(0, 0);
@@ -149,6 +158,17 @@ __device__ void build_recipe(const DRecipe &R, const c128 *__restrict__ cdata, c
   const c128 *data = R.data >= 0 ? cdata + R.data : nullptr;
   c128 G[16], dG[16];
   switch (R.form) {
+    case RF_GATE_F: {
+      const int d = dev_gate(R.type, p, -2, data, R.n_data, G);
+      for (int e = 0; e < d * d; e++) out[e] = G[e];
+      break;
+    }
+    case RF_GPHASE: {
+      double sn, cs;
+      sincospi(0.25 * (R.k & 7), &sn, &cs);
+      out[0] = C(cs, sn); out[1] = C(0, 0); out[2] = C(0, 0); out[3] = C(cs, sn);
+      break;
+    }
     case RF_GATE: case RF_GATE_CONJ: case RF_DGATE: case RF_DGATE_CONJ: {
       int d = dev_gate(R.type, p, (R.form == RF_DGATE || R.form == RF_DGATE_CONJ) ? R.k : -1, data, R.n_data, G);
       if (d <= 0) d = (R.nq == 2) ? 4 : 2;
@@ -473,8 +493,8 @@ static int grid_for(uint64_t work, int block) {
 }
 
 // per-instantiation launchers live in inst_*.hip (compiled in parallel)
-#define VQC_DECL_LDS(KK, AA) \
-  hipError_t launch_lds_##KK##_##AA(const DJob *, int, int64_t, int, const DOverride &, hipStream_t);
+#define VQC_DECL_LDS(KK, RR, AA) \
+  hipError_t launch_lds_##KK##_##RR##_##AA(const DJob *, int, int64_t, int, const DOverride &, hipStream_t);
 #define VQC_DECL_REG(RR, MM) \
   hipError_t launch_reg_##RR##_##MM(const DJob *, int, int64_t, int, const DOverride &, hipStream_t);
 #include "inst_list.h"
@@ -483,9 +503,8 @@ static int grid_for(uint64_t work, int block) {
 
 hipError_t launch_pass_lds(int K, int R, bool adj, const DJob *jobs, int n_jobs, int64_t total, int grid,
                            const DOverride &ov, hipStream_t st) {
-  if (R != 4) return hipErrorInvalidValue;
-#define VQC_DECL_LDS(KK, AA) \
-  if (K == KK && (int)adj == AA) return launch_lds_##KK##_##AA(jobs, n_jobs, total, grid, ov, st);
+#define VQC_DECL_LDS(KK, RR, AA) \
+  if (K == KK && R == RR && (int)adj == AA) return launch_lds_##KK##_##RR##_##AA(jobs, n_jobs, total, grid, ov, st);
 #define VQC_DECL_REG(RR, MM)
 #include "inst_list.h"
 #undef VQC_DECL_LDS
@@ -495,7 +514,7 @@ hipError_t launch_pass_lds(int K, int R, bool adj, const DJob *jobs, int n_jobs,
 
 hipError_t launch_pass_reg(int R, int mode, const DJob *jobs, int n_jobs, int64_t total, int grid,
                            const DOverride &ov, hipStream_t st) {
-#define VQC_DECL_LDS(KK, AA)
+#define VQC_DECL_LDS(KK, RR, AA)
 #define VQC_DECL_REG(RR, MM) \
   if (R == RR && mode == MM) return launch_reg_##RR##_##MM(jobs, n_jobs, total, grid, ov, st);
 #include "inst_list.h"

@@ -29,6 +29,34 @@
 
 namespace vqc {
 
+// --------------------------------------------------------- address spaces
+// Descriptors and gate matrices are written before a pass kernel starts and
+// only read during it: reading them through the constant address space lets
+// the compiler use scalar (uniform) loads instead of per-lane loads that
+// serialise on memory latency.  The state goes through the global address
+// space (global_load/store rather than flat, which would also hold LDS waits).
+#define VQC_AS_CONST __attribute__((address_space(4)))
+#define VQC_AS_GLOBAL __attribute__((address_space(1)))
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef const VQC_AS_CONST v2d cmat;  // matrix element, scalar-loaded
+typedef VQC_AS_GLOBAL v2d gc128;      // state amplitude in HBM
+
+// whole-dword scalar loads (scalar loads have no byte/short forms); the
+// fields are then extracted in registers
+template <typename T>
+__device__ __forceinline__ T ldc(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "descriptor size must be a multiple of 4 bytes");
+  constexpr int W = sizeof(T) / 4;
+  union {
+    T t;
+    uint32_t w[W];
+  } u;
+  const VQC_AS_CONST uint32_t *q = (const VQC_AS_CONST uint32_t *)p;
+#pragma unroll
+  for (int i = 0; i < W; i++) u.w[i] = q[i];
+  return u.t;
+}
+
 // ------------------------------------------------------------ complex math
 
 __device__ __forceinline__ c128 cmul(c128 a, c128 b) {
@@ -44,11 +72,19 @@ __device__ __forceinline__ c128 cscale(double s, c128 a) { return make_double2(s
 // Re(conj(a) * b)
 __device__ __forceinline__ double redot(c128 a, c128 b) { return fma(a.x, b.x, a.y * b.y); }
 
+__device__ __forceinline__ c128 tc(v2d v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ v2d tv(c128 c) {
+  v2d v;
+  v.x = c.x;
+  v.y = c.y;
+  return v;
+}
+
 // element (r, c) of M (row-major D x D) or of M^dagger
 template <bool ADJ, int D>
-__device__ __forceinline__ c128 mel(const c128 *__restrict__ M, int r, int c) {
-  if (ADJ) return cconj(M[c * D + r]);
-  return M[r * D + c];
+__device__ __forceinline__ c128 mel(cmat *M, int r, int c) {
+  if (ADJ) return cconj(tc(M[c * D + r]));
+  return tc(M[r * D + c]);
 }
 
 // insert a zero bit at position p
@@ -66,7 +102,7 @@ __device__ __forceinline__ int swz(int l) { return l ^ (((l >> 4) ^ (l >> 8)) & 
 // ------------------------------------------------- register-level op kernels
 
 template <int NR, int B, bool ADJ>
-__device__ __forceinline__ void rg_dense1(c128 (&a)[NR], const c128 *__restrict__ M) {
+__device__ __forceinline__ void rg_dense1(c128 (&a)[NR], cmat *M) {
   const c128 m00 = mel<ADJ, 2>(M, 0, 0), m01 = mel<ADJ, 2>(M, 0, 1);
   const c128 m10 = mel<ADJ, 2>(M, 1, 0), m11 = mel<ADJ, 2>(M, 1, 1);
 #pragma unroll
@@ -80,14 +116,69 @@ __device__ __forceinline__ void rg_dense1(c128 (&a)[NR], const c128 *__restrict_
 }
 
 template <int NR, int B, bool ADJ>
-__device__ __forceinline__ void rg_diag1(c128 (&a)[NR], const c128 *__restrict__ M) {
+__device__ __forceinline__ void rg_diag1(c128 (&a)[NR], cmat *M) {
   const c128 d0 = mel<ADJ, 2>(M, 0, 0), d1 = mel<ADJ, 2>(M, 1, 1);
 #pragma unroll
   for (int j = 0; j < NR; j++) a[j] = cmul((j >> B) & 1 ? d1 : d0, a[j]);
 }
 
+// [[a, i b], [i c, d]] with real a, b, c, d: 4 FP64 ops per output
+template <int NR, int B, bool ADJ>
+__device__ __forceinline__ void rg_xrot1(c128 (&a)[NR], cmat *M) {
+  const double m00 = M[0].x, m11 = M[3].x;
+  // adjoint: [[a, -i c], [-i b, d]]
+  const double b = ADJ ? -M[2].y : M[1].y, c = ADJ ? -M[1].y : M[2].y;
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    const c128 x = a[j], y = a[k];
+    a[j] = make_double2(fma(m00, x.x, -b * y.y), fma(m00, x.y, b * y.x));
+    a[k] = make_double2(fma(m11, y.x, -c * x.y), fma(m11, y.y, c * x.x));
+  }
+}
+
+// real 2x2: 4 FP64 ops per output
+template <int NR, int B, bool ADJ>
+__device__ __forceinline__ void rg_real1(c128 (&a)[NR], cmat *M) {
+  const double m00 = M[0].x, m11 = M[3].x;
+  const double m01 = ADJ ? M[2].x : M[1].x, m10 = ADJ ? M[1].x : M[2].x;
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    const c128 x = a[j], y = a[k];
+    a[j] = make_double2(fma(m00, x.x, m01 * y.x), fma(m00, x.y, m01 * y.y));
+    a[k] = make_double2(fma(m10, x.x, m11 * y.x), fma(m10, x.y, m11 * y.y));
+  }
+}
+
+// real diagonal, complex off-diagonal: 6 FP64 ops per output
+template <int NR, int B, bool ADJ>
+__device__ __forceinline__ void rg_rdiag1(c128 (&a)[NR], cmat *M) {
+  const double m00 = M[0].x, m11 = M[3].x;
+  const c128 m01 = ADJ ? cconj(tc(M[2])) : tc(M[1]), m10 = ADJ ? cconj(tc(M[1])) : tc(M[2]);
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    const c128 x = a[j], y = a[k];
+    a[j] = make_double2(fma(m00, x.x, fma(m01.x, y.x, -m01.y * y.y)), fma(m00, x.y, fma(m01.x, y.y, m01.y * y.x)));
+    a[k] = make_double2(fma(m11, y.x, fma(m10.x, x.x, -m10.y * x.y)), fma(m11, y.y, fma(m10.x, x.y, m10.y * x.x)));
+  }
+}
+
+// diag(1, m11): only the |1> half changes
+template <int NR, int B, bool ADJ>
+__device__ __forceinline__ void rg_phase1(c128 (&a)[NR], cmat *M) {
+  const c128 d1 = mel<ADJ, 2>(M, 1, 1);
+#pragma unroll
+  for (int j = 0; j < NR; j++)
+    if ((j >> B) & 1) a[j] = cmul(d1, a[j]);
+}
+
 template <int NR, int B0, int B1, bool ADJ>
-__device__ __forceinline__ void rg_dense2(c128 (&a)[NR], const c128 *__restrict__ M) {
+__device__ __forceinline__ void rg_dense2(c128 (&a)[NR], cmat *M) {
   c128 m[16];
 #pragma unroll
   for (int r = 0; r < 4; r++)
@@ -114,7 +205,7 @@ __device__ __forceinline__ void rg_dense2(c128 (&a)[NR], const c128 *__restrict_
 }
 
 template <int NR, int B0, int B1, bool ADJ>
-__device__ __forceinline__ void rg_diag2(c128 (&a)[NR], const c128 *__restrict__ M) {
+__device__ __forceinline__ void rg_diag2(c128 (&a)[NR], cmat *M) {
   c128 d[4];
 #pragma unroll
   for (int l = 0; l < 4; l++) d[l] = mel<ADJ, 4>(M, l, l);
@@ -123,7 +214,7 @@ __device__ __forceinline__ void rg_diag2(c128 (&a)[NR], const c128 *__restrict__
 }
 
 template <int NR, int B0, int B1, bool ADJ>
-__device__ __forceinline__ void rg_fsim(c128 (&a)[NR], const c128 *__restrict__ M) {
+__device__ __forceinline__ void rg_fsim(c128 (&a)[NR], cmat *M) {
   const c128 m00 = mel<ADJ, 4>(M, 0, 0), m11 = mel<ADJ, 4>(M, 1, 1), m12 = mel<ADJ, 4>(M, 1, 2);
   const c128 m21 = mel<ADJ, 4>(M, 2, 1), m22 = mel<ADJ, 4>(M, 2, 2), m33 = mel<ADJ, 4>(M, 3, 3);
 #pragma unroll
@@ -134,6 +225,23 @@ __device__ __forceinline__ void rg_fsim(c128 (&a)[NR], const c128 *__restrict__ 
     a[j] = cmul(m00, a[j]);
     a[i1] = cfma(m11, x1, cmul(m12, x2));
     a[i2] = cfma(m21, x1, cmul(m22, x2));
+    a[i3] = cmul(m33, a[i3]);
+  }
+}
+
+// fSim with Delta = 0: |00> unchanged, XROT block on |01>,|10>, phase on |11>
+template <int NR, int B0, int B1, bool ADJ>
+__device__ __forceinline__ void rg_fsimx(c128 (&a)[NR], cmat *M) {
+  const double c1 = M[5].x, c2 = M[10].x;
+  const double s12 = ADJ ? -M[9].y : M[6].y, s21 = ADJ ? -M[6].y : M[9].y;
+  const c128 m33 = mel<ADJ, 4>(M, 3, 3);
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & ((1 << B0) | (1 << B1))) continue;
+    const int i1 = j | (1 << B0), i2 = j | (1 << B1), i3 = i1 | i2;
+    const c128 x = a[i1], y = a[i2];
+    a[i1] = make_double2(fma(c1, x.x, -s12 * y.y), fma(c1, x.y, s12 * y.x));
+    a[i2] = make_double2(fma(c2, y.x, -s21 * x.y), fma(c2, y.y, s21 * x.x));
     a[i3] = cmul(m33, a[i3]);
   }
 }
@@ -151,7 +259,7 @@ __device__ __forceinline__ void rg_cx(c128 (&a)[NR]) {
 }
 
 template <int NR, bool ADJ>
-__device__ __forceinline__ void rg_dense4(c128 (&a)[NR], const c128 *__restrict__ M) {
+__device__ __forceinline__ void rg_dense4(c128 (&a)[NR], cmat *M) {
   if constexpr (NR == 16) {
     c128 x[16];
 #pragma unroll
@@ -168,8 +276,8 @@ __device__ __forceinline__ void rg_dense4(c128 (&a)[NR], const c128 *__restrict_
 
 // Re sum conj(b) (D a) over the groups of an op (gradient inner products)
 template <int NR, int B>
-__device__ __forceinline__ double gr_dense1(const c128 (&a)[NR], const c128 (&b)[NR], const c128 *__restrict__ D) {
-  const c128 d00 = D[0], d01 = D[1], d10 = D[2], d11 = D[3];
+__device__ __forceinline__ double gr_dense1(const c128 (&a)[NR], const c128 (&b)[NR], cmat *D) {
+  const c128 d00 = tc(D[0]), d01 = tc(D[1]), d10 = tc(D[2]), d11 = tc(D[3]);
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < NR; j++) {
@@ -182,8 +290,8 @@ __device__ __forceinline__ double gr_dense1(const c128 (&a)[NR], const c128 (&b)
 }
 
 template <int NR, int B>
-__device__ __forceinline__ double gr_diag1(const c128 (&a)[NR], const c128 (&b)[NR], const c128 *__restrict__ D) {
-  const c128 d0 = D[0], d1 = D[3];
+__device__ __forceinline__ double gr_diag1(const c128 (&a)[NR], const c128 (&b)[NR], cmat *D) {
+  const c128 d0 = tc(D[0]), d1 = tc(D[3]);
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < NR; j++) acc += redot(b[j], cmul((j >> B) & 1 ? d1 : d0, a[j]));
@@ -191,7 +299,7 @@ __device__ __forceinline__ double gr_diag1(const c128 (&a)[NR], const c128 (&b)[
 }
 
 template <int NR, int B0, int B1>
-__device__ __forceinline__ double gr_dense2(const c128 (&a)[NR], const c128 (&b)[NR], const c128 *__restrict__ D) {
+__device__ __forceinline__ double gr_dense2(const c128 (&a)[NR], const c128 (&b)[NR], cmat *D) {
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < NR; j++) {
@@ -201,10 +309,10 @@ __device__ __forceinline__ double gr_dense2(const c128 (&a)[NR], const c128 (&b)
     for (int l = 0; l < 4; l++) idx[l] = j | ((l & 1) << B0) | ((l >> 1) << B1);
 #pragma unroll
     for (int r = 0; r < 4; r++) {
-      c128 w = cmul(D[r * 4 + 0], a[idx[0]]);
-      w = cfma(D[r * 4 + 1], a[idx[1]], w);
-      w = cfma(D[r * 4 + 2], a[idx[2]], w);
-      w = cfma(D[r * 4 + 3], a[idx[3]], w);
+      c128 w = cmul(tc(D[r * 4 + 0]), a[idx[0]]);
+      w = cfma(tc(D[r * 4 + 1]), a[idx[1]], w);
+      w = cfma(tc(D[r * 4 + 2]), a[idx[2]], w);
+      w = cfma(tc(D[r * 4 + 3]), a[idx[3]], w);
       acc += redot(b[idx[r]], w);
     }
   }
@@ -212,14 +320,14 @@ __device__ __forceinline__ double gr_dense2(const c128 (&a)[NR], const c128 (&b)
 }
 
 template <int NR>
-__device__ __forceinline__ double gr_dense4(const c128 (&a)[NR], const c128 (&b)[NR], const c128 *__restrict__ D) {
+__device__ __forceinline__ double gr_dense4(const c128 (&a)[NR], const c128 (&b)[NR], cmat *D) {
   double acc = 0.0;
   if constexpr (NR == 16) {
 #pragma unroll
     for (int r = 0; r < 16; r++) {
-      c128 w = cmul(D[r * 16], a[0]);
+      c128 w = cmul(tc(D[r * 16]), a[0]);
 #pragma unroll
-      for (int c = 1; c < 16; c++) w = cfma(D[r * 16 + c], a[c], w);
+      for (int c = 1; c < 16; c++) w = cfma(tc(D[r * 16 + c]), a[c], w);
       acc += redot(b[r], w);
     }
   }
@@ -245,10 +353,12 @@ __device__ __forceinline__ double gr_dense4(const c128 (&a)[NR], const c128 (&b)
     default: break;                                                            \
   }
 
-template <int R, bool ADJ>
-__device__ __forceinline__ void rg_apply(c128 (&a)[1 << R], const DGate &g, const c128 *__restrict__ mats) {
+// D4: whether 16x16 superoperators can occur (vectorised density matrices);
+// the pure-state LDS kernels leave them out, which frees registers
+template <int R, bool ADJ, bool D4 = true>
+__device__ __forceinline__ void rg_apply(c128 (&a)[1 << R], const DGate &g, cmat *mats) {
   constexpr int NR = 1 << R;
-  const c128 *__restrict__ M = mats + g.mat;
+  cmat *M = mats + g.mat;
   switch (g.kind) {
     case GK_DENSE1:
       switch (g.r[0]) { VQC_CASE1(rg_dense1, 0) VQC_CASE1(rg_dense1, 1) VQC_CASE1(rg_dense1, 2) VQC_CASE1(rg_dense1, 3) default: break; }
@@ -256,6 +366,19 @@ __device__ __forceinline__ void rg_apply(c128 (&a)[1 << R], const DGate &g, cons
     case GK_DIAG1:
       switch (g.r[0]) { VQC_CASE1(rg_diag1, 0) VQC_CASE1(rg_diag1, 1) VQC_CASE1(rg_diag1, 2) VQC_CASE1(rg_diag1, 3) default: break; }
       break;
+    case GK_XROT1:
+      switch (g.r[0]) { VQC_CASE1(rg_xrot1, 0) VQC_CASE1(rg_xrot1, 1) VQC_CASE1(rg_xrot1, 2) VQC_CASE1(rg_xrot1, 3) default: break; }
+      break;
+    case GK_REAL1:
+      switch (g.r[0]) { VQC_CASE1(rg_real1, 0) VQC_CASE1(rg_real1, 1) VQC_CASE1(rg_real1, 2) VQC_CASE1(rg_real1, 3) default: break; }
+      break;
+    case GK_RDIAG1:
+      switch (g.r[0]) { VQC_CASE1(rg_rdiag1, 0) VQC_CASE1(rg_rdiag1, 1) VQC_CASE1(rg_rdiag1, 2) VQC_CASE1(rg_rdiag1, 3) default: break; }
+      break;
+    case GK_PHASE1:
+      switch (g.r[0]) { VQC_CASE1(rg_phase1, 0) VQC_CASE1(rg_phase1, 1) VQC_CASE1(rg_phase1, 2) VQC_CASE1(rg_phase1, 3) default: break; }
+      break;
+    case GK_FSIMX: VQC_SWITCH2(rg_fsimx) break;
     case GK_DENSE2: VQC_SWITCH2(rg_dense2) break;
     case GK_DIAG2: VQC_SWITCH2(rg_diag2) break;
     case GK_FSIM: VQC_SWITCH2(rg_fsim) break;
@@ -272,7 +395,9 @@ __device__ __forceinline__ void rg_apply(c128 (&a)[1 << R], const DGate &g, cons
         default: break;
       }
       break;
-    case GK_DENSE4: rg_dense4<NR, ADJ>(a, M); break;
+    case GK_DENSE4:
+      if constexpr (D4) rg_dense4<NR, ADJ>(a, M);
+      break;
     default: break;
   }
 }
@@ -287,11 +412,11 @@ __device__ __forceinline__ void rg_apply(c128 (&a)[1 << R], const DGate &g, cons
     break;
 
 // derivative records reuse the register bits of their op
-template <int R>
+template <int R, bool D4 = true>
 __device__ __forceinline__ double rg_grad(const c128 (&a)[1 << R], const c128 (&b)[1 << R], const DGate &g,
-                                          const DDeriv &d, const c128 *__restrict__ mats) {
+                                          const DDeriv &d, cmat *mats) {
   constexpr int NR = 1 << R;
-  const c128 *__restrict__ D = mats + d.mat;
+  cmat *D = mats + d.mat;
   double v = 0.0;
   switch (d.kind) {
     case GK_DENSE1:
@@ -307,7 +432,9 @@ __device__ __forceinline__ double rg_grad(const c128 (&a)[1 << R], const c128 (&
         default: break;
       }
       break;
-    case GK_DENSE4: v = gr_dense4<NR>(a, b, D); break;
+    case GK_DENSE4:
+      if constexpr (D4) v = gr_dense4<NR>(a, b, D);
+      break;
     default: break;
   }
   return v;
@@ -320,12 +447,20 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// tile-local bit -> global qubit for a runtime (uniform) local bit: one
+// scalar dword load from the pass table instead of indexing a local copy,
+// which would force the copy into scratch memory
+__device__ __forceinline__ int tq_at(const DPass *gp, int idx) {
+  const uint32_t w = *((const VQC_AS_CONST uint32_t *)gp->tq + (idx >> 2));
+  return (w >> (8 * (idx & 3))) & 0xff;
+}
+
 template <typename JT>
 __device__ __forceinline__ int find_job(const JT *__restrict__ jobs, int n_jobs, int64_t u) {
   int lo = 0, hi = n_jobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].unit0 <= u) lo = mid; else hi = mid - 1;
+    if (ldc(&jobs[mid].unit0) <= u) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
@@ -346,13 +481,50 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
 
+  // forward passes run persistent blocks that prefetch the next tile into
+  // registers while the current tile is in its register stages, so HBM
+  // traffic overlaps the FP64 work
+  [[maybe_unused]] c128 pf[NR];
+  [[maybe_unused]] bool have_pf = false;
+  auto tile_addr = [&](int64_t uu, const DJob &JJ, const DPass &PQ, uint64_t &gb0, uint64_t &st0) {
+    uint64_t g0 = (uint64_t)(uu - JJ.unit0);
+#pragma unroll
+    for (int i = 0; i < K; i++) g0 = ins0<uint64_t>(g0, PQ.tq[i]);
+    uint64_t s0 = 0;
+#pragma unroll
+    for (int i = 0; i < K - R; i++) s0 |= (uint64_t)((t >> i) & 1) << PQ.tq[i];
+    gb0 = g0;
+    st0 = s0;
+  };
+  auto prefetch = [&](int64_t uu) {
+    const DJob JN = ldc(&jobs[find_job(jobs, n_jobs, uu)]);
+    const DPass PN = ldc(JN.pass);
+    const gc128 *srcn = (const gc128 *)(ov.use ? ov.a : JN.a);
+    uint64_t g0, s0;
+    tile_addr(uu, JN, PN, g0, s0);
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+      uint64_t oj = 0;
+#pragma unroll
+      for (int i = 0; i < R; i++)
+        if ((j >> i) & 1) oj |= 1ull << PN.tq[K - R + i];
+      pf[j] = tc(srcn[g0 | s0 | oj]);
+    }
+  };
+  if constexpr (!ADJ) {
+    if ((int64_t)blockIdx.x < total_units) {
+      prefetch(blockIdx.x);
+      have_pf = true;
+    }
+  }
   for (int64_t u = blockIdx.x; u < total_units; u += gridDim.x) {
-    const DJob &J = jobs[find_job(jobs, n_jobs, u)];
-    const DPass *__restrict__ P = J.pass;
+    const DJob J = ldc(&jobs[find_job(jobs, n_jobs, u)]);
+    const DPass PP = ldc(J.pass);
+    const DPass *P = &PP;
     const int64_t tile = u - J.unit0;
-    c128 *A = ov.use ? ov.a : J.a;
-    c128 *Bv = ov.use ? ov.b : J.b;
-    const c128 *__restrict__ MT = ov.use ? ov.mats : J.mats;
+    gc128 *A = (gc128 *)(ov.use ? ov.a : J.a);
+    gc128 *Bv = (gc128 *)(ov.use ? ov.b : J.b);
+    cmat *MT = (cmat *)(ov.use ? ov.mats : J.mats);
     double *PT = ov.use ? ov.partials : J.partials;
     const int mode = ov.use ? ov.mode : J.mode;
     uint64_t gbase = (uint64_t)tile;
@@ -361,72 +533,121 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
     uint64_t st = 0;
 #pragma unroll
     for (int i = 0; i < K - R; i++) st |= (uint64_t)((t >> i) & 1) << P->tq[i];
-    const c128 *__restrict__ src = A;
-    c128 *dst = (mode == 1) ? Bv : A;
-    // HBM -> LDS, coalesced over the low tile bits
-#pragma unroll
-    for (int j = 0; j < NR; j++) {
-      uint64_t oj = 0;
-#pragma unroll
-      for (int i = 0; i < R; i++)
-        if ((j >> i) & 1) oj |= 1ull << P->tq[K - R + i];
-      const uint64_t gi = gbase | st | oj;
-      la[swz(j * T + t)] = src[gi];
-      if constexpr (ADJ) lb[swz(j * T + t)] = Bv[gi];
-    }
-    __syncthreads();
+    const gc128 *src = A;
+    gc128 *dst = (mode == 1) ? Bv : A;
     const int nst = P->nst;
+    // direct HBM access for the first / last stage in execution order
+    const bool din = ADJ ? (P->lowfree >> 1) & 1 : false;
+    const bool dout = ADJ ? P->lowfree & 1 : (P->lowfree >> 1) & 1;
+    if constexpr (!ADJ) {
+      // the tile was prefetched by the previous iteration (or before the loop)
+#pragma unroll
+      for (int j = 0; j < NR; j++) la[swz(j * T + t)] = pf[j];
+      const int64_t un = u + gridDim.x;
+      if (un < total_units) prefetch(un);
+      __syncthreads();
+    } else if (!din) {
+      // HBM -> LDS, coalesced over the low tile bits
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        uint64_t oj = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) oj |= 1ull << P->tq[K - R + i];
+        const uint64_t gi = gbase | st | oj;
+        la[swz(j * T + t)] = tc(src[gi]);
+        if constexpr (ADJ) lb[swz(j * T + t)] = tc(Bv[gi]);
+      }
+      __syncthreads();
+    }
     for (int si = 0; si < nst; si++) {
       const int s = ADJ ? nst - 1 - si : si;
-      const DStage S = P->stages[s];
+      const DStage S = ldc(&P->stages[s]);
       int base = t;
 #pragma unroll
       for (int i = 0; i < R; i++) base = ins0<int>(base, S.srt[i]);
-      int off[NR];
+      int lo[NR];
 #pragma unroll
       for (int j = 0; j < NR; j++) {
         int o = 0;
 #pragma unroll
         for (int i = 0; i < R; i++)
           if ((j >> i) & 1) o |= 1 << S.rbit[i];
-        off[j] = swz(base | o);
+        lo[j] = o;
+      }
+      const bool first = (si == 0) && din, last = (si == nst - 1) && dout;
+      uint64_t gb = 0;
+      if (first || last) {
+        // HBM address of local index base | lo[j]: gbase + scatter(base) + scatter(lo[j])
+        gb = gbase;
+#pragma unroll
+        for (int i = 0; i < K; i++)
+          if ((base >> i) & 1) gb |= 1ull << P->tq[i];
       }
       c128 a[NR];
+      [[maybe_unused]] c128 b[NR];
+      if (first) {
 #pragma unroll
-      for (int j = 0; j < NR; j++) a[j] = la[off[j]];
-      if constexpr (!ADJ) {
-        for (int g = S.g0; g < S.g1; g++) rg_apply<R, false>(a, P->gates[g], MT);
+        for (int j = 0; j < NR; j++) {
+          uint64_t go = 0;
+#pragma unroll
+          for (int i = 0; i < R; i++)
+            if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
+          a[j] = tc(src[gb | go]);
+          if constexpr (ADJ) b[j] = tc(Bv[gb | go]);
+        }
       } else {
-        c128 b[NR];
 #pragma unroll
-        for (int j = 0; j < NR; j++) b[j] = lb[off[j]];
+        for (int j = 0; j < NR; j++) {
+          a[j] = la[swz(base | lo[j])];
+          if constexpr (ADJ) b[j] = lb[swz(base | lo[j])];
+        }
+      }
+      if constexpr (!ADJ) {
+        for (int g = S.g0; g < S.g1; g++) rg_apply<R, false, false>(a, ldc(&P->gates[g]), MT);
+      } else {
         for (int g = S.g1 - 1; g >= S.g0; g--) {
-          const DGate G = P->gates[g];
-          rg_apply<R, true>(a, G, MT);  // Phi <- Q^dagger Phi
+          const DGate G = ldc(&P->gates[g]);
+          rg_apply<R, true, false>(a, G, MT);  // Phi <- Q^dagger Phi
           for (int d = 0; d < G.nd; d++) {  // <Psi| dQ |Phi>
-            const DDeriv Dd = P->derivs[G.d0 + d];
-            double v = wave_sum<WS>(rg_grad<R>(a, b, G, Dd, MT));
+            const DDeriv Dd = ldc(&P->derivs[G.d0 + d]);
+            double v = wave_sum<WS>(rg_grad<R, false>(a, b, G, Dd, MT));
             if (lane == 0) red[Dd.local][wave] = v;
           }
-          rg_apply<R, true>(b, G, MT);  // Psi <- Q^dagger Psi
+          rg_apply<R, true, false>(b, G, MT);  // Psi <- Q^dagger Psi
         }
-#pragma unroll
-        for (int j = 0; j < NR; j++) lb[off[j]] = b[j];
       }
+      if (last) {
 #pragma unroll
-      for (int j = 0; j < NR; j++) la[off[j]] = a[j];
-      __syncthreads();
+        for (int j = 0; j < NR; j++) {
+          uint64_t go = 0;
+#pragma unroll
+          for (int i = 0; i < R; i++)
+            if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
+          dst[gb | go] = tv(a[j]);
+          if constexpr (ADJ) Bv[gb | go] = tv(b[j]);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < NR; j++) {
+          la[swz(base | lo[j])] = a[j];
+          if constexpr (ADJ) lb[swz(base | lo[j])] = b[j];
+        }
+        __syncthreads();
+      }
     }
-    // LDS -> HBM
+    if (!dout) {
+      // LDS -> HBM
 #pragma unroll
-    for (int j = 0; j < NR; j++) {
-      uint64_t oj = 0;
+      for (int j = 0; j < NR; j++) {
+        uint64_t oj = 0;
 #pragma unroll
-      for (int i = 0; i < R; i++)
-        if ((j >> i) & 1) oj |= 1ull << P->tq[K - R + i];
-      const uint64_t gi = gbase | st | oj;
-      dst[gi] = la[swz(j * T + t)];
-      if constexpr (ADJ) Bv[gi] = lb[swz(j * T + t)];
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) oj |= 1ull << P->tq[K - R + i];
+        const uint64_t gi = gbase | st | oj;
+        dst[gi] = tv(la[swz(j * T + t)]);
+        if constexpr (ADJ) Bv[gi] = tv(lb[swz(j * T + t)]);
+      }
     }
     if constexpr (ADJ) {
       const int nv = P->nvar;
@@ -434,7 +655,7 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; w++) s += red[v][w];
-        PT[(int64_t)P->vslot[v] * J.n_units + tile] = s;
+        PT[(int64_t)ldc(&P->vslot[v]) * J.n_units + tile] = s;
       }
     }
     __syncthreads();
@@ -456,18 +677,19 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   for (int64_t u = blockIdx.x; u < total_units; u += gridDim.x) {
-    const DJob &J = jobs[find_job(jobs, n_jobs, u)];
-    const DPass *__restrict__ P = J.pass;
+    const DJob J = ldc(&jobs[find_job(jobs, n_jobs, u)]);
+    const DPass PP = ldc(J.pass);
+    const DPass *P = &PP;
     const int64_t ublk = u - J.unit0;
-    c128 *A = ov.use ? ov.a : J.a;
-    c128 *Bv = ov.use ? ov.b : J.b;
-    const c128 *__restrict__ MT = ov.use ? ov.mats : J.mats;
+    gc128 *A = (gc128 *)(ov.use ? ov.a : J.a);
+    gc128 *Bv = (gc128 *)(ov.use ? ov.b : J.b);
+    cmat *MT = (cmat *)(ov.use ? ov.mats : J.mats);
     double *PT = ov.use ? ov.partials : J.partials;
     const int mode = ov.use ? ov.mode : J.mode;
     const int64_t tiles = (int64_t)1 << (J.nbits - R);
     const int64_t tile = ublk * 256 + t;
     const bool act = tile < tiles;
-    const DStage S = P->stages[0];
+    const DStage S = ldc(&P->stages[0]);
     uint64_t base = act ? (uint64_t)tile : 0;
 #pragma unroll
     for (int i = 0; i < R; i++) base = ins0<uint64_t>(base, P->tq[i]);
@@ -477,29 +699,29 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
       uint64_t o = 0;
 #pragma unroll
       for (int i = 0; i < R; i++)
-        if ((j >> i) & 1) o |= 1ull << P->tq[S.rbit[i]];
+        if ((j >> i) & 1) o |= 1ull << tq_at(J.pass, S.rbit[i]);
       off[j] = base | o;
     }
     c128 a[NR];
 #pragma unroll
-    for (int j = 0; j < NR; j++) a[j] = act ? A[off[j]] : make_double2(0.0, 0.0);
+    for (int j = 0; j < NR; j++) a[j] = act ? tc(A[off[j]]) : make_double2(0.0, 0.0);
     if constexpr (MODE == 0) {
-      for (int g = S.g0; g < S.g1; g++) rg_apply<R, false>(a, P->gates[g], MT);
-      c128 *dst = (mode == 1) ? Bv : A;
+      for (int g = S.g0; g < S.g1; g++) rg_apply<R, false>(a, ldc(&P->gates[g]), MT);
+      gc128 *dst = (mode == 1) ? Bv : A;
       if (act) {
 #pragma unroll
-        for (int j = 0; j < NR; j++) dst[off[j]] = a[j];
+        for (int j = 0; j < NR; j++) dst[off[j]] = tv(a[j]);
       }
     } else {
       c128 b[NR];
 #pragma unroll
-      for (int j = 0; j < NR; j++) b[j] = act ? Bv[off[j]] : make_double2(0.0, 0.0);
+      for (int j = 0; j < NR; j++) b[j] = act ? tc(Bv[off[j]]) : make_double2(0.0, 0.0);
       for (int g = S.g1 - 1; g >= S.g0; g--) {
-        const DGate G = P->gates[g];
+        const DGate G = ldc(&P->gates[g]);
         if constexpr (MODE == 1) {
           rg_apply<R, true>(a, G, MT);
           for (int d = 0; d < G.nd; d++) {
-            const DDeriv Dd = P->derivs[G.d0 + d];
+            const DDeriv Dd = ldc(&P->derivs[G.d0 + d]);
             const double v = wave_sum<64>(rg_grad<R>(a, b, G, Dd, MT));
             if (lane == 0) red[Dd.local][wave] = v;
           }
@@ -508,9 +730,9 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
             c128 c[NR];
 #pragma unroll
             for (int j = 0; j < NR; j++) c[j] = a[j];
-            for (int g2 = S.g0; g2 < g; g2++) rg_apply<R, false>(c, P->gates[g2], MT);
+            for (int g2 = S.g0; g2 < g; g2++) rg_apply<R, false>(c, ldc(&P->gates[g2]), MT);
             for (int d = 0; d < G.nd; d++) {
-              const DDeriv Dd = P->derivs[G.d0 + d];
+              const DDeriv Dd = ldc(&P->derivs[G.d0 + d]);
               const double v = wave_sum<64>(rg_grad<R>(c, b, G, Dd, MT));
               if (lane == 0) red[Dd.local][wave] = v;
             }
@@ -521,14 +743,14 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
       if (act) {
 #pragma unroll
         for (int j = 0; j < NR; j++) {
-          if constexpr (MODE == 1) A[off[j]] = a[j];
-          Bv[off[j]] = b[j];
+          if constexpr (MODE == 1) A[off[j]] = tv(a[j]);
+          Bv[off[j]] = tv(b[j]);
         }
       }
       __syncthreads();
       const int nv = P->nvar;
       for (int v = t; v < nv; v += 256)
-        PT[(int64_t)P->vslot[v] * J.n_units + ublk] = (red[v][0] + red[v][1]) + (red[v][2] + red[v][3]);
+        PT[(int64_t)ldc(&P->vslot[v]) * J.n_units + ublk] = (red[v][0] + red[v][1]) + (red[v][2] + red[v][3]);
     }
     __syncthreads();
   }
@@ -546,7 +768,20 @@ hipError_t launch_lds_t(const DJob *jobs, int n_jobs, int64_t total, int grid, c
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  const int g = grid > 0 ? grid : (int)(total < (1 << 30) ? total : (1 << 30));
+  int g = grid;
+  if (g <= 0) {
+    // persistent grid: as many resident blocks as the chip holds
+    static int resident = 0;
+    if (!resident) {
+      int per_cu = 0, dev = 0, cus = 0;
+      (void)hipGetDevice(&dev);
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_pass_lds<K, R, ADJ>, 1 << (K - R),
+                                                         shmem);
+      resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 256);
+    }
+    g = (int)(total < resident ? total : resident);
+  }
   hipLaunchKernelGGL((k_pass_lds<K, R, ADJ>), dim3(g), dim3(1 << (K - R)), shmem, st, jobs, n_jobs, total, ov);
   return hipGetLastError();
 }

@@ -18,7 +18,12 @@ enum GateKind : int8_t {
   GK_FSIM = 4,    // m00 | [[m11 m12][m21 m22]] | m33 (fSim / iSWAP pattern)
   GK_CX = 5,      // controlled X: control bit 0, target bit 1 (no matrix)
   GK_DENSE4 = 6,  // 16x16 on four bits, register bits 0..3 in order
-  GK_NONE = 7     // identity (no-op)
+  GK_NONE = 7,    // identity (no-op)
+  GK_XROT1 = 8,   // [[a, i b], [i c, d]], a..d real (Rx, phase-free sqrt(X), Y)
+  GK_REAL1 = 9,   // real 2x2 (Ry, H, X, phase-free sqrt(Y))
+  GK_RDIAG1 = 10, // real diagonal, complex off-diagonal (phase-free sqrt(W))
+  GK_FSIMX = 11,  // fSim with Delta = 0: 1 | [[c, -i s], [-i s, c]] | e^{-i phi}
+  GK_PHASE1 = 12  // diag(1, m11) (Z, S, T)
 };
 
 constexpr int kMaxTile = 13;      // K <= 13: 2^13 * 16 B = 128 KiB of LDS
@@ -52,7 +57,8 @@ struct DPass {
   int32_t K;        // tile bits (= R for register-only passes)
   int32_t nst;      // stages
   int32_t nvar;     // derivative slots reduced in this pass
-  int32_t pad;
+  int32_t lowfree;  // bit 0: stage 0 holds none of the low c bits; bit 1: the last stage
+                    // holds none (that stage can then load/store HBM directly, coalesced)
   int8_t tq[16];    // global qubit of tile-local bit i, ascending
   const DStage *stages;   // absolute device pointers
   const DGate *gates;
@@ -92,7 +98,9 @@ enum RecipeForm : int32_t {
   RF_DGATE_CONJ = 3,
   RF_SUPER_GATE = 4,  // conj(U) (x) U  (ket bits low, bra bits high)
   RF_DSUPER_GATE = 5, // conj(dU) (x) U + conj(U) (x) dU
-  RF_SUPER_KRAUS = 6  // sum_s conj(K_s) (x) K_s
+  RF_SUPER_KRAUS = 6,  // sum_s conj(K_s) (x) K_s
+  RF_GATE_F = 7,       // gate matrix with the global phase e^{i pi/4} of sqrt(X/Y/W) removed
+  RF_GPHASE = 8        // diag(w, w), w = e^{i pi k / 4}
 };
 
 struct DRecipe {

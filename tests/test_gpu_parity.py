@@ -119,15 +119,26 @@ def test_random_grid_circuit(rows, cols, cycles):
     assert abs(st.norm() - 1) < 1e-12
 
 
-@pytest.mark.parametrize("tile,low", [(5, 2), (8, 3), (10, 4), (11, 5), (13, 4)])
-def test_tile_shapes_agree(tile, low):
+@pytest.mark.parametrize("tile,low,reg", [(5, 2, 4), (8, 3, 4), (10, 4, 4), (11, 5, 4), (13, 4, 4),
+                                          (8, 3, 3), (11, 4, 3), (13, 5, 3)])
+def test_tile_shapes_agree(tile, low, reg):
     n = 14
     ops = W.rqc_grid(2, 7, 10, 99)
     ref = oracle.run(n, ops)
-    c = Circuit(n, ops, tune={"tile_bits": tile, "low_bits": low})
+    c = Circuit(n, ops, tune={"tile_bits": tile, "low_bits": low, "reg_bits": reg})
     st = State(n)
     c.apply(st)
     assert maxdiff(st.numpy(), ref) < AMP_TOL
+    # the adjoint kernels of the same register width
+    ops2 = W.hea(n, 2)
+    th = W.theta_uniform(3, 1, W.count_params(ops2))[0]
+    c2 = Circuit(n, ops2, tune={"tile_bits": tile, "low_bits": low, "reg_bits": reg})
+    st2 = State(n)
+    tht = torch.tensor(th, device="cuda")
+    c2.apply(st2, tht)
+    g, e = c2.backward(tht, st2, W.tfim(n))
+    e_ref, g_ref, _ = oracle.grad_pure(n, ops2, th, W.tfim(n))
+    assert maxdiff(g.cpu().numpy(), g_ref) < GRAD_TOL
 
 
 def test_expectation_pure_and_mixed():
@@ -238,3 +249,56 @@ def test_noisy_gradient(n, layers):
     # a small checkpoint budget (more recomputation) gives the same gradient
     g2, _ = c.backward(tht, st, terms, budget=12 * 16 * (4 ** n))
     assert maxdiff(g2.cpu().numpy(), g_ref) < GRAD_TOL
+
+
+def _mixed_gate_circuit(n, seed, n_sqrt):
+    """Every gate type at seeded positions; `n_sqrt` phase-factored sqrt gates
+    (a count that is not a multiple of 8 exercises the global-phase op)."""
+    rng = np.random.default_rng(seed)
+    ops, k = [], 0
+    names1 = ["x", "y", "z", "h", "s", "t"]
+    for i in range(6 * n):
+        q = int(rng.integers(n))
+        r = i % 9
+        if r < 3:
+            ops.append(Op(["rx", "ry", "rz"][r], (q,), (0.0,), (k,)))
+            k += 1
+        elif r < 5:
+            ops.append(Op(names1[int(rng.integers(6))], (q,)))
+        else:
+            a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+            two = ["cz", "cnot", "swap", "iswap", "crx", "fsim", "fsimd", "control"][int(rng.integers(8))]
+            if two == "crx":
+                ops.append(Op("crx", (a, b), (0.0,), (k,)))
+                k += 1
+            elif two == "fsim":
+                ops.append(Op("fsim", (a, b), (0.0, 0.3, 0, 0, 0), (k, -1, -1, -1, -1)))
+                k += 1
+            elif two == "fsimd":
+                ops.append(Op("fsim", (a, b), (0.7, 0.3, 0.1, -0.2, 0.05)))
+            elif two == "control":
+                ops.append(Op("control", (a, b), (), (), W.random_unitary(2, i)))
+            else:
+                ops.append(Op(two, (a, b)))
+    for i in range(n_sqrt):
+        ops.insert(int(rng.integers(len(ops))), Op(["sx", "sy", "sw"][i % 3], (int(rng.integers(n)),)))
+    th = rng.uniform(-3, 3, k)
+    return ops, th
+
+
+@pytest.mark.parametrize("n,n_sqrt,tile,reg", [(12, 13, 11, 3), (13, 8, 10, 4), (9, 3, 8, 4)])
+def test_every_kind_fused_forward_and_adjoint(n, n_sqrt, tile, reg):
+    ops, th = _mixed_gate_circuit(n, 100 + n, n_sqrt)
+    c = Circuit(n, ops, tune={"tile_bits": tile, "low_bits": 3, "reg_bits": reg})
+    st = State(n)
+    tht = torch.tensor(th, device="cuda")
+    c.apply(st, tht)
+    ref = oracle.run(n, ops, th)
+    assert maxdiff(st.numpy(), ref) < AMP_TOL
+    terms = W.heisenberg_1d(n, 0.3, 1.0)
+    g, e = c.backward(tht, st, terms)
+    e_ref, g_ref, _ = oracle.grad_pure(n, ops, th, terms)
+    assert abs(e - e_ref) < AMP_TOL
+    assert maxdiff(g.cpu().numpy(), g_ref) < GRAD_TOL
+    phi = st.numpy()
+    assert abs(phi[0] - 1) < 1e-11 and np.max(np.abs(phi[1:])) < 1e-11
