@@ -257,6 +257,50 @@ vqc_status vqc_batch_capture(vqc_batch b, const vqc_pauli_sum *H, double *const 
                              double *energies_dev, size_t checkpoint_budget_bytes);
 vqc_status vqc_batch_replay(vqc_batch b);
 
+/* --------------------------------------------------- surrogate network
+ * A small MLP model of the variational energy landscape (not part of the
+ * paper): E_hat(theta) = w3 . gelu(W2 gelu(W1 theta + b1) + b2) + b3, with
+ * gelu(x) = x Phi(x) (exact erf).  Parameters and activations are FP32;
+ * every matrix product rounds its FP32 inputs to BF16 (nearest-even) and
+ * accumulates in FP32 on MFMA.  Parameter buffer layout (FP32, device):
+ * W1[h1][n_in], b1[h1], W2[h2][h1], b2[h2], w3[h2], b3[1].  Activations are
+ * row-major [batch][features]. */
+typedef struct vqc_mlp_s *vqc_mlp;
+
+/* C[M x N] = alpha op(A) op(B) + beta C, FP32 in/out, BF16 products with FP32
+ * accumulation.  op(A)[m][k] = A[m*lda + k] (ta = 0) or A[k*lda + m] (ta = 1);
+ * op(B)[k][n] = B[k*ldb + n] (tb = 0) or B[n*ldb + k] (tb = 1).  Device
+ * pointers; stream as in vqc_state_init. */
+vqc_status vqc_gemm_bf16(int M, int N, int K, const float *A, int lda, int ta, const float *B, int ldb, int tb,
+                         float *C, int ldc, float alpha, float beta, void *stream);
+
+/* Network n_in -> h1 -> h2 -> 1 for batches up to max_batch; allocates the
+ * parameters (uninitialised: write them through vqc_mlp_buffers), gradient,
+ * Adam moments and activation workspace. */
+vqc_status vqc_mlp_create(vqc_mlp *out, int n_in, int h1, int h2, int max_batch, void *stream);
+vqc_status vqc_mlp_destroy(vqc_mlp m);
+/* Device pointers to the parameter and gradient buffers and their length. */
+vqc_status vqc_mlp_buffers(vqc_mlp m, float **params, float **grads, size_t *count);
+
+/* y[b] = E_hat(x[b]) for x [batch][n_in]; when dydx is non-NULL also the
+ * input gradient dE_hat/dx [batch][n_in] (backpropagation to the input). */
+vqc_status vqc_mlp_forward(vqc_mlp m, int batch, const float *x, float *y, float *dydx);
+
+/* Parameter gradient (into the gradient buffer) of the loss
+ *   L = mean_b (E_hat(x_b) - e_b)^2 + lambda / (batch n_in) sum_b |dE_hat/dx(x_b) - g_b|^2
+ * where g may be NULL (then lambda is ignored).  The gradient term needs the
+ * second derivatives of the network (double backpropagation).  y and dydx
+ * (optional, device) receive the forward outputs. */
+vqc_status vqc_mlp_backward(vqc_mlp m, int batch, const float *x, const float *e, const float *g, float lambda,
+                            float *y, float *dydx);
+
+/* One Adam step on the parameters with the current gradient (step >= 1). */
+vqc_status vqc_mlp_adam(vqc_mlp m, float lr, float beta1, float beta2, float eps, int step);
+
+/* `steps` plain gradient-descent steps on the inputs: x <- x - lr dE_hat/dx
+ * (the surrogate's proposal for each row of x). */
+vqc_status vqc_mlp_descend_inputs(vqc_mlp m, int batch, float *x, float lr, int steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -104,6 +104,17 @@ _SIGS = {
     "vqc_batch_backward": (c_int, [c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p, c_void_p, c_size_t]),
     "vqc_batch_capture": (c_int, [c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p, c_void_p, c_size_t]),
     "vqc_batch_replay": (c_int, [c_void_p]),
+    "vqc_gemm_bf16": (c_int, [c_int, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_int,
+                              ctypes.c_float, ctypes.c_float, c_void_p]),
+    "vqc_mlp_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_int, c_int, c_void_p]),
+    "vqc_mlp_destroy": (c_int, [c_void_p]),
+    "vqc_mlp_buffers": (c_int, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                ctypes.POINTER(c_size_t)]),
+    "vqc_mlp_forward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "vqc_mlp_backward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_void_p,
+                                 c_void_p]),
+    "vqc_mlp_adam": (c_int, [c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_int]),
+    "vqc_mlp_descend_inputs": (c_int, [c_void_p, c_int, c_void_p, ctypes.c_float, c_int]),
 }
 
 

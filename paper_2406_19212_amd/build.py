@@ -34,6 +34,7 @@ def units():
             out.append(("inst_reg.hip", ["-DVQC_R=%d" % R, "-DVQC_MODE=%d" % M], "reg_%d_%d" % (R, M)))
     out.append(("kernels.hip", [], "kernels"))
     out.append(("api.cpp", ["-x", "hip"], "api"))
+    out.append(("mlp.hip", [], "mlp"))
     return out
 
 
@@ -42,6 +43,7 @@ _DEPS = {
     "kernels.hip": ["pass_kernels.h", "vqc_internal.h", "inst_list.h"],
     "inst_lds.hip": ["pass_kernels.h", "vqc_internal.h"],
     "inst_reg.hip": ["pass_kernels.h", "vqc_internal.h"],
+    "mlp.hip": [],
 }
 
 
