@@ -1,0 +1,253 @@
+"""Surrogate-assisted variational optimisation (not part of the paper).
+
+An MLP E_hat(theta) of the ansatz energy is trained on (theta, E, dE/dtheta)
+produced by the batched adjoint simulator, then used to propose optimiser
+steps that the exact simulator verifies:
+
+    repeat: theta' = theta after K gradient steps on E_hat
+            E(theta'), dE(theta') from the simulator (one exact evaluation)
+            accept theta' if E(theta') < E(theta), else take one exact Adam step
+            fine-tune E_hat on the verified points seen so far
+
+The plain baseline is exact-gradient Adam from the same theta_0; both are
+compared per exact evaluation and per wall-clock second.  All arithmetic runs
+in the library's kernels (simulator and network); this module schedules them.
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import workloads as W
+from .api import Batch, Circuit, State
+from .mlp import MLP
+
+
+class Simulator:
+    """Energy and adjoint gradient of the ansatz for one theta or a batch."""
+
+    def __init__(self, n, layers, h=1.0, batch=256):
+        self.n, self.layers = n, layers
+        self.ops = W.hea(n, layers)
+        self.P = W.count_params(self.ops)
+        self.terms = W.tfim(n, h)
+        self.circ = Circuit(n, self.ops, n_params=self.P)
+        self.state = State(n)
+        self.B = batch
+        self.theta_b = torch.zeros(batch, self.P, dtype=torch.float64, device="cuda")
+        self.states_b = [torch.empty(1 << n, dtype=torch.complex128, device="cuda") for _ in range(batch)]
+        self.grads_b = torch.zeros(batch, self.P, dtype=torch.float64, device="cuda")
+        self.en_b = torch.zeros(batch, dtype=torch.float64, device="cuda")
+        self.batch = Batch([self.circ] * batch, self.states_b, [self.theta_b[i] for i in range(batch)])
+        self.batch.capture(self.terms, [self.grads_b[i] for i in range(batch)], self.en_b)
+        self.evals = 0
+
+    def energy_grad(self, theta):
+        """(E, dE/dtheta) of one parameter vector (float64 CUDA tensor)."""
+        self.state.reset()
+        self.circ.apply(self.state, theta)
+        g, e = self.circ.backward(theta, self.state, self.terms)
+        self.evals += 1
+        return e, g.clone()
+
+    def batch_energy_grad(self, thetas):
+        """Rows of thetas (count x P, float64 CUDA) -> energies, gradients."""
+        E, G = [], []
+        for s in range(0, thetas.shape[0], self.B):
+            k = min(self.B, thetas.shape[0] - s)
+            self.theta_b[:k].copy_(thetas[s:s + k])
+            self.batch.replay()
+            E.append(self.en_b[:k].clone())
+            G.append(self.grads_b[:k].clone())
+        return torch.cat(E), torch.cat(G)
+
+
+def generate(sim: Simulator, count: int, seed: int):
+    theta = torch.tensor(W.theta_uniform(seed, count, sim.P), device="cuda")
+    E, G = sim.batch_energy_grad(theta)
+    return theta, E, G
+
+
+def init_params(net: MLP, seed: int):
+    n_in, h1, h2 = net.dims
+    r = W.SplitMix64(seed)
+    parts = [r.normal(h1 * n_in) * math.sqrt(2.0 / n_in), np.zeros(h1), r.normal(h2 * h1) * math.sqrt(2.0 / h1),
+             np.zeros(h2), r.normal(h2) * math.sqrt(1.0 / h2), np.zeros(1)]
+    net.set_params(np.concatenate(parts))
+
+
+def train(net: MLP, theta, E, G, epochs, lam=1.0, lr=1e-3, batch=512, seed=0, scale=None):
+    """Adam on mean (E_hat - E)^2 + lam/(B P) sum |dE_hat - G|^2 with inputs
+    theta (float32) and labels scaled by `scale` (mean, std of E)."""
+    n = theta.shape[0]
+    x = theta.float().contiguous()
+    mu, sd = scale
+    e = ((E - mu) / sd).float().contiguous()
+    g = (G / sd).float().contiguous()
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    for _ in range(epochs):
+        perm = torch.randperm(n, generator=gen).to(x.device)
+        for s in range(0, n - batch + 1, batch):
+            idx = perm[s:s + batch]
+            net.backward(x[idx], e[idx], g[idx] if lam else None, lam)
+            net.adam(lr)
+
+
+def predict(net: MLP, theta, scale):
+    mu, sd = scale
+    x = theta.float().contiguous().view(1, -1) if theta.dim() == 1 else theta.float().contiguous()
+    ys, gs = [], []
+    for s in range(0, x.shape[0], net.max_batch):
+        y, gx = net.forward(x[s:s + net.max_batch], want_grad=True)
+        ys.append(y)
+        gs.append(gx)
+    return torch.cat(ys).double() * sd + mu, torch.cat(gs).double() * sd
+
+
+class Adam:
+    """Optimiser state for theta (float64): the library's Adam is for the
+    network's FP32 parameters, so theta's update is kept here as the same
+    recurrence on a torch tensor."""
+
+    def __init__(self, theta, lr, b1=0.9, b2=0.999, eps=1e-8):
+        self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
+        self.m = torch.zeros_like(theta)
+        self.v = torch.zeros_like(theta)
+        self.t = 0
+
+    def step(self, theta, g):
+        self.t += 1
+        self.m.mul_(self.b1).add_(g, alpha=1 - self.b1)
+        self.v.mul_(self.b2).addcmul_(g, g, value=1 - self.b2)
+        mh = self.m / (1 - self.b1 ** self.t)
+        vh = self.v / (1 - self.b2 ** self.t)
+        theta.sub_(self.lr * mh / (vh.sqrt() + self.eps))
+
+
+def optimize_plain(sim: Simulator, theta0, steps, lr, target=None):
+    theta = theta0.clone()
+    opt = Adam(theta, lr)
+    t0 = time.perf_counter()
+    hist = []
+    for _ in range(steps):
+        e, g = sim.energy_grad(theta)
+        hist.append((time.perf_counter() - t0, sim.evals, e))
+        if target is not None and e <= target:
+            break
+        opt.step(theta, g)
+    return theta, hist
+
+
+def optimize_surrogate(sim: Simulator, net: MLP, scale, theta0, steps, lr, K=10, eta=0.02, finetune=20,
+                       ft_lr=2e-3, buffer=128, radius=0.5, margin=1e-6, target=None):
+    """Surrogate proposals verified by the simulator.
+
+    Each outer step fine-tunes the network on the most recent verified points
+    (energy + gradient matching), descends the surrogate K steps from theta
+    (total move clipped to a trust radius), and evaluates the proposal
+    exactly.  A proposal that lowers the energy by more than `margin` is
+    accepted (its exact gradient serves the next step, the radius grows);
+    otherwise theta takes one exact Adam step with the gradient already known
+    and the radius shrinks."""
+    theta = theta0.clone()
+    opt = Adam(theta, lr)
+    t0 = time.perf_counter()
+    e, g = sim.energy_grad(theta)
+    hist = [(time.perf_counter() - t0, sim.evals, e)]
+    seen_x, seen_e, seen_g = [theta.clone()], [e], [g]
+    log = {"accepted": 0, "fallback": 0, "abs_err": [], "cos": []}
+    for _ in range(steps):
+        if target is not None and e <= target:
+            break
+        if finetune:
+            X = torch.stack(seen_x[-buffer:])
+            Ev = torch.tensor(seen_e[-buffer:], dtype=torch.float64, device=X.device)
+            Gv = torch.stack(seen_g[-buffer:])
+            train(net, X, Ev, Gv, epochs=finetune, batch=min(len(X), 32), scale=scale, lr=ft_lr)
+        x = theta.float().clone().view(1, -1)
+        net.descend_inputs(x, eta * scale[1], K)
+        prop = x.view(-1).double()
+        d = prop - theta
+        dn = float(d.norm())
+        if dn > radius:
+            prop = theta + d * (radius / dn)
+        e_hat, g_hat = predict(net, prop, scale)
+        e2, g2 = sim.energy_grad(prop)
+        log["abs_err"].append(abs(float(e_hat[0]) - e2))
+        log["cos"].append(float(torch.dot(g_hat.view(-1), g2) / (g_hat.norm() * g2.norm() + 1e-30)))
+        seen_x.append(prop.clone())
+        seen_e.append(e2)
+        seen_g.append(g2)
+        if e2 < e - margin:
+            theta.copy_(prop)
+            e, g = e2, g2
+            radius *= 1.5
+            log["accepted"] += 1
+        else:
+            opt.step(theta, g)
+            e, g = sim.energy_grad(theta)
+            seen_x.append(theta.clone())
+            seen_e.append(e)
+            seen_g.append(g)
+            radius = max(radius * 0.5, 1e-3)
+            log["fallback"] += 1
+        hist.append((time.perf_counter() - t0, sim.evals, e))
+    return theta, hist, log
+
+
+def run(n=16, layers=10, h=1.0, samples=50000, epochs=30, steps=200, lr=0.05, seed=240619216, target=None,
+        hidden=512, out=None, **kw):
+    """The full experiment; returns a JSON-able record."""
+    rec = {"n": n, "layers": layers, "h": h, "samples": samples, "epochs": epochs, "steps": steps}
+    sim = Simulator(n, layers, h)
+    rec["params"] = sim.P
+    t = time.perf_counter()
+    theta, E, G = generate(sim, samples, seed)
+    torch.cuda.synchronize()
+    rec["data_s"] = time.perf_counter() - t
+    rec["label_grads_per_s"] = samples / rec["data_s"]
+    scale = (float(E.mean()), float(E.std()) + 1e-12)
+    net = MLP(sim.P, hidden, hidden, max_batch=512)
+    init_params(net, seed + 1)
+    ntr = int(0.9 * samples)
+    t = time.perf_counter()
+    train(net, theta[:ntr], E[:ntr], G[:ntr], epochs=epochs, scale=scale)
+    torch.cuda.synchronize()
+    rec["train_s"] = time.perf_counter() - t
+    e_hat, g_hat = predict(net, theta[ntr:], scale)
+    rec["holdout_rmse"] = float((e_hat - E[ntr:]).pow(2).mean().sqrt())
+    rec["holdout_label_std"] = float(E[ntr:].std())
+    rec["holdout_grad_cos"] = float(torch.nn.functional.cosine_similarity(g_hat, G[ntr:], dim=1).mean())
+    theta0 = torch.tensor(W.theta_uniform(seed + 2, 1, sim.P)[0], device="cuda")
+    sim.evals = 0
+    _, hp = optimize_plain(sim, theta0, steps, lr, target)
+    sim.evals = 0
+    _, hs, log = optimize_surrogate(sim, net, scale, theta0, steps, lr, target=target, **kw)
+    rec["plain"] = {"final_E": hp[-1][2], "evals": hp[-1][1], "seconds": hp[-1][0], "trace": hp[::10]}
+    rec["surrogate"] = {"final_E": hs[-1][2], "evals": hs[-1][1], "seconds": hs[-1][0], "trace": hs[::10],
+                        "accepted": log["accepted"], "fallback": log["fallback"],
+                        "mean_abs_err": float(np.mean(log["abs_err"])) if log["abs_err"] else None,
+                        "mean_grad_cos": float(np.mean(log["cos"])) if log["cos"] else None}
+    if out:
+        with open(out, "w") as f:
+            json.dump(rec, f)
+    return rec
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=16)
+    ap.add_argument("--layers", type=int, default=10)
+    ap.add_argument("--samples", type=int, default=50000)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--target", type=float, default=None)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    print(json.dumps(run(a.n, a.layers, samples=a.samples, epochs=a.epochs, steps=a.steps, target=a.target,
+                         out=a.out)))
