@@ -18,6 +18,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (known wrong results on this part)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Control flow on wave-uniform values (the per-op dispatch of the pass
+# kernels) stays as plain scalar branches instead of being rewritten into
+# predicated flow regions; otherwise every amplitude register is live across
+# all dispatch arms and each op ends in register copies.
+UNIFORM_CF = ["-mllvm", "-structurizecfg-skip-uniform-regions"]
 
 
 def units():
@@ -27,12 +32,12 @@ def units():
             for A in (0, 1):
                 if R == 3 and A == 1 and K > 12:
                     continue
-                out.append(("inst_lds.hip", ["-DVQC_K=%d" % K, "-DVQC_R=%d" % R, "-DVQC_ADJ=%d" % A],
+                out.append(("inst_lds.hip", UNIFORM_CF + ["-DVQC_K=%d" % K, "-DVQC_R=%d" % R, "-DVQC_ADJ=%d" % A],
                             "lds_%d_%d_%d" % (K, R, A)))
     for R in (1, 2, 3, 4):
         for M in (0, 1, 2):
-            out.append(("inst_reg.hip", ["-DVQC_R=%d" % R, "-DVQC_MODE=%d" % M], "reg_%d_%d" % (R, M)))
-    out.append(("kernels.hip", [], "kernels"))
+            out.append(("inst_reg.hip", UNIFORM_CF + ["-DVQC_R=%d" % R, "-DVQC_MODE=%d" % M], "reg_%d_%d" % (R, M)))
+    out.append(("kernels.hip", UNIFORM_CF, "kernels"))
     out.append(("api.cpp", ["-x", "hip"], "api"))
     out.append(("mlp.hip", [], "mlp"))
     return out

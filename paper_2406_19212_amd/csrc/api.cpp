@@ -91,20 +91,22 @@ bool valid_type(int t) {
 int gate_kind(const vqc_op &op, bool factored) {
   const int type = op.type, m = op.n_qubits;
   switch (type) {
-    case VQC_Z: case VQC_S: case VQC_T: return GK_PHASE1;
-    case VQC_RZ: return GK_DIAG1;
-    case VQC_H: case VQC_X: case VQC_RY: return GK_REAL1;
-    case VQC_Y: case VQC_RX: return GK_XROT1;
-    case VQC_SX: return factored ? GK_XROT1 : GK_DENSE1;
-    case VQC_SY: return factored ? GK_REAL1 : GK_DENSE1;
-    case VQC_SW: return factored ? GK_RDIAG1 : GK_DENSE1;
+    case VQC_Z: case VQC_S: case VQC_T: return GK_SPH1;
+    case VQC_RZ: return GK_SDG1;
+    case VQC_H: case VQC_X: return GK_REAL1;
+    case VQC_RY: return GK_SRR1;
+    case VQC_Y: return GK_XROT1;
+    case VQC_RX: return GK_SXR1;
+    case VQC_SX: return factored ? GK_SXR1 : GK_DENSE1;
+    case VQC_SY: return factored ? GK_SRR1 : GK_DENSE1;
+    case VQC_SW: return factored ? GK_SRD1 : GK_DENSE1;
     case VQC_ID: return GK_NONE;
     case VQC_CZ: case VQC_CRZ: return GK_DIAG2;
     case VQC_CNOT: return GK_CX;
     case VQC_FSIM: {
       bool plain = true;
       for (int k = 2; k < 5; k++) plain &= op.params[k] == 0.0 && op.param_index[k] < 0;
-      return plain ? GK_FSIMX : GK_FSIM;
+      return plain ? GK_SFX : GK_FSIM;
     }
     case VQC_SWAP: case VQC_ISWAP: return GK_FSIM;
     case VQC_CRX: case VQC_CRY: case VQC_CONTROL: return GK_DENSE2;
@@ -112,6 +114,9 @@ int gate_kind(const vqc_op &op, bool factored) {
     default: return GK_DENSE1;
   }
 }
+
+// kinds applied from a shear record that follows the op's matrix
+bool shear_kind(int gk) { return gk >= GK_SXR1 && gk <= GK_SFX; }
 
 bool phase_factored(int type) { return type == VQC_SX || type == VQC_SY || type == VQC_SW; }
 
@@ -465,7 +470,7 @@ namespace {
 // ---------------------------------------------------------- circuit build
 
 int add_recipe(vqc_circuit c, int type, int form, int k, int nq, const vqc_op &op, int data_off, int n_data,
-               int out_size) {
+               int out_size, int shear = 0) {
   DRecipe r;
   std::memset(&r, 0, sizeof(r));
   r.type = type;
@@ -475,13 +480,23 @@ int add_recipe(vqc_circuit c, int type, int form, int k, int nq, const vqc_op &o
   r.out = c->mat_size;
   r.data = data_off;
   r.n_data = n_data;
+  r.shear = shear;
   for (int i = 0; i < 5; i++) {
     r.pidx[i] = op.param_index[i];
     r.pval[i] = op.params[i];
   }
   c->recipes.push_back(r);
-  c->mat_size += out_size;
+  c->mat_size += out_size + (shear ? kSRecSlots : 0);
   return r.out;
+}
+
+// matrix of a gate op for the pass kernels: the offset the kernels read,
+// i.e. the shear record for rotation kinds, the matrix otherwise
+int add_gate_recipe(vqc_circuit c, int gk, int type, int form, int nq, const vqc_op &op, int data_off, int n_data) {
+  const int d = 1 << nq;
+  if (gk == GK_CX || gk == GK_NONE) return -1;
+  if (shear_kind(gk)) return add_recipe(c, type, form, 0, nq, op, data_off, n_data, d * d, gk) + d * d;
+  return add_recipe(c, type, form, 0, nq, op, data_off, n_data, d * d);
 }
 
 vqc_status lower(vqc_circuit c) {
@@ -533,12 +548,10 @@ vqc_status lower(vqc_circuit c) {
       for (int t = 0; t < m; t++) e.q[t] = op.qubits[t];
       const bool fac = phase_factored(op.type);
       n_factored += fac;
-      e.mat = (gk == GK_CX || gk == GK_NONE)
-                  ? -1
-                  : add_recipe(c, op.type, fac ? RF_GATE_F : RF_GATE, 0, m, op, data_off, n_data, d * d);
+      e.mat = add_gate_recipe(c, gk, op.type, fac ? RF_GATE_F : RF_GATE, m, op, data_off, n_data);
       for (int k = 0; k < 5; k++)
         if (op.param_index[k] >= 0) {
-          const int dk = (m == 1) ? (gk == GK_DIAG1 ? GK_DIAG1 : GK_DENSE1) : GK_DENSE2;
+          const int dk = (m == 1) ? (gk == GK_SDG1 ? GK_DIAG1 : GK_DENSE1) : GK_DENSE2;
           const int mat = add_recipe(c, op.type, RF_DGATE, k, m, op, data_off, n_data, d * d);
           e.d.push_back(new_deriv(dk, mat, k));
         }
@@ -548,11 +561,10 @@ vqc_status lower(vqc_circuit c) {
       e.nq = m;
       e.kind = gk;
       for (int t = 0; t < m; t++) e.q[t] = op.qubits[t];
-      e.mat = (gk == GK_CX || gk == GK_NONE) ? -1 : add_recipe(c, op.type, RF_GATE, 0, m, op, data_off, n_data, d * d);
+      e.mat = add_gate_recipe(c, gk, op.type, RF_GATE, m, op, data_off, n_data);
       c->elems.push_back(e);
       for (int t = 0; t < m; t++) e.q[t] = op.qubits[t] + n;
-      e.mat = (gk == GK_CX || gk == GK_NONE) ? -1
-                                             : add_recipe(c, op.type, RF_GATE_CONJ, 0, m, op, data_off, n_data, d * d);
+      e.mat = add_gate_recipe(c, gk, op.type, RF_GATE_CONJ, m, op, data_off, n_data);
       c->elems.push_back(e);
     } else {
       Elem e;
@@ -575,9 +587,9 @@ vqc_status lower(vqc_circuit c) {
     for (int k = 0; k < 5; k++) ph.param_index[k] = -1;
     Elem e;
     e.nq = 1;
-    e.kind = GK_DIAG1;
+    e.kind = GK_SDG1;
     e.q[0] = 0;
-    e.mat = add_recipe(c, VQC_ID, RF_GPHASE, n_factored & 7, 1, ph, -1, 0, 4);
+    e.mat = add_recipe(c, VQC_ID, RF_GPHASE, n_factored & 7, 1, ph, -1, 0, 4, GK_SDG1) + 4;
     c->elems.push_back(e);
   }
   return VQC_OK;
@@ -757,7 +769,7 @@ vqc_status upload_const(vqc_circuit c) {
   c->d_cdata = reinterpret_cast<c128 *>(base + o_c);
   c->d_csr_ptr = reinterpret_cast<int32_t *>(base + o_p);
   c->d_csr_slot = reinterpret_cast<int32_t *>(base + o_s);
-  VQC_TRY(c->mats1.ensure(std::max(1, c->mat_size) * sizeof(c128)));
+  VQC_TRY(c->mats1.ensure(std::max(kSRecSlots, c->mat_size) * sizeof(c128)));
   return VQC_OK;
 }
 
@@ -1421,7 +1433,7 @@ static vqc_status batch_build_tables(vqc_batch b) {
   for (int i = 0; i < B; i++) {
     vqc_circuit c = b->circ[i];
     b->mat_off[i] = mtot;
-    mtot += al(std::max(1, c->mat_size) * sizeof(c128));
+    mtot += al(std::max(kSRecSlots, c->mat_size) * sizeof(c128));
     b->psi_off[i] = ptot;
     if (c->kind == VQC_PURE) ptot += al(state_len(c->kind, c->n) * sizeof(c128));
     b->part_off[i] = qtot;

@@ -151,6 +151,57 @@ __device__ c128 dev_kraus(int type, double g, const c128 *data, int d, int s, in
   }
 }
 
+// rotation i of a shear record from (C, S) = (cos p, sin p)
+__device__ __forceinline__ void srec_rot(SRec &r, int i, double C, double S) {
+  if (C < 0.0) {
+    C = -C;
+    S = -S;
+    r.neg |= 1u << i;
+  }
+  r.ab[2 * i] = -S / (1.0 + C);
+  r.ab[2 * i + 1] = S;
+}
+
+// shear record of a rotation kind from its (row-major) matrix M
+__device__ void derive_srec(int kind, const c128 *M, c128 *out) {
+  SRec r;
+  r.neg = 0;
+  r.pad = 0;
+  for (int i = 0; i < 7; i++) r.ab[i] = 0.0;
+  switch (kind) {
+    case GK_SXR1: srec_rot(r, 0, M[0].x, M[2].y); break;  // [[C, -iS], [-iS, C]]: S = Im m10
+    case GK_SRR1: srec_rot(r, 0, M[0].x, M[2].x); break;  // [[C, -S], [S, C]]
+    case GK_SPH1: srec_rot(r, 0, M[3].x, M[3].y); break;
+    case GK_SDG1:
+      srec_rot(r, 0, M[0].x, M[0].y);
+      srec_rot(r, 1, M[3].x, M[3].y);
+      break;
+    case GK_SRD1: {
+      // m10 = B e^{-i chi}; D^dagger R D is unchanged by chi -> chi + pi,
+      // B -> -B, which keeps cos chi >= 0
+      double B = hypot(M[2].x, M[2].y), cc = 1.0, sc = 0.0;
+      if (B > 0.0) {
+        cc = M[2].x / B;
+        sc = -M[2].y / B;
+      }
+      if (cc < 0.0) {
+        cc = -cc;
+        sc = -sc;
+        B = -B;
+      }
+      srec_rot(r, 0, cc, sc);
+      srec_rot(r, 1, M[0].x, B);
+      break;
+    }
+    case GK_SFX:
+      srec_rot(r, 0, M[5].x, M[9].y);
+      srec_rot(r, 1, M[15].x, M[15].y);
+      break;
+    default: break;
+  }
+  *reinterpret_cast<SRec *>(out) = r;  // kSRecSlots c128 slots, 16 B aligned
+}
+
 __device__ void build_recipe(const DRecipe &R, const c128 *__restrict__ cdata, const double *th, c128 *out_base) {
   double p[5];
   for (int k = 0; k < 5; k++) p[k] = (R.pidx[k] >= 0 && th) ? th[R.pidx[k]] : R.pval[k];
@@ -211,6 +262,10 @@ __device__ void build_recipe(const DRecipe &R, const c128 *__restrict__ cdata, c
             }
       break;
     }
+  }
+  if (R.shear) {
+    const int d = R.nq == 2 ? 4 : 2;
+    derive_srec(R.shear, out, out + d * d);
   }
 }
 

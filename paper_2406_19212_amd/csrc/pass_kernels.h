@@ -274,6 +274,107 @@ __device__ __forceinline__ void rg_dense4(c128 (&a)[NR], cmat *M) {
   }
 }
 
+// ------------------------------------------- in-place rotation (shear) forms
+// A plane rotation [[C, -S], [S, C]] of (u, v) is three shears
+// u += a v; v += b u; u += a v with a = -tan(p/2) = -S/(1+C), b = S, each a
+// fused multiply-add accumulated into the coordinate's own register, so a
+// run of these ops keeps every amplitude in place (no register copies
+// between ops) and costs 3 FP64 FMAs per rotated pair of reals instead of 4.
+// The record keeps C >= 0 (|a| <= 1, no cancellation); a rotation with
+// C < 0 is stored as the rotation by p - pi followed by a negation, folded
+// into the last two FMAs.
+template <bool NEG>
+__device__ __forceinline__ void shr(double &u, double &v, double a, double b) {
+  u = fma(a, v, u);
+  if (!NEG) {
+    v = fma(b, u, v);
+    u = fma(a, v, u);
+  } else {
+    v = fma(-b, u, -v);
+    u = fma(a, v, -u);
+  }
+}
+
+// Rx-type [[C, -iS], [-iS, C]]: (Re x, Im y) rotate by p, (Im x, Re y) by -p
+template <int NR, int B, bool ADJ, bool N0>
+__device__ __forceinline__ void rg_sxr1(c128 (&a)[NR], const SRec &r) {
+  const double al = ADJ ? -r.ab[0] : r.ab[0], be = ADJ ? -r.ab[1] : r.ab[1];
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    shr<N0>(a[j].x, a[k].y, al, be);
+    shr<N0>(a[j].y, a[k].x, -al, -be);
+  }
+}
+
+// Ry-type real rotation of (x, y), real and imaginary parts alike
+template <int NR, int B, bool ADJ, bool N0>
+__device__ __forceinline__ void rg_srr1(c128 (&a)[NR], const SRec &r) {
+  const double al = ADJ ? -r.ab[0] : r.ab[0], be = ADJ ? -r.ab[1] : r.ab[1];
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    shr<N0>(a[j].x, a[k].x, al, be);
+    shr<N0>(a[j].y, a[k].y, al, be);
+  }
+}
+
+// diag(1, e^{ip}): the |1> amplitudes rotate in the complex plane
+template <int NR, int B, bool ADJ, bool N0>
+__device__ __forceinline__ void rg_sph1(c128 (&a)[NR], const SRec &r) {
+  const double al = ADJ ? -r.ab[0] : r.ab[0], be = ADJ ? -r.ab[1] : r.ab[1];
+#pragma unroll
+  for (int j = 0; j < NR; j++)
+    if ((j >> B) & 1) shr<N0>(a[j].x, a[j].y, al, be);
+}
+
+// diag(e^{ip0}, e^{ip1})
+template <int NR, int B, bool ADJ, bool N0, bool N1>
+__device__ __forceinline__ void rg_sdg1(c128 (&a)[NR], const SRec &r) {
+  const double a0 = ADJ ? -r.ab[0] : r.ab[0], b0 = ADJ ? -r.ab[1] : r.ab[1];
+  const double a1 = ADJ ? -r.ab[2] : r.ab[2], b1 = ADJ ? -r.ab[3] : r.ab[3];
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if ((j >> B) & 1) shr<N1>(a[j].x, a[j].y, a1, b1);
+    else shr<N0>(a[j].x, a[j].y, a0, b0);
+  }
+}
+
+// D^dagger R(p) D with D = diag(1, e^{i chi}): rotation 0 is chi (stored
+// with C >= 0, never negated), rotation 1 is p; the adjoint negates p only
+template <int NR, int B, bool ADJ, bool N1>
+__device__ __forceinline__ void rg_srd1(c128 (&a)[NR], const SRec &r) {
+  const double ac = r.ab[0], bc = r.ab[1];
+  const double al = ADJ ? -r.ab[2] : r.ab[2], be = ADJ ? -r.ab[3] : r.ab[3];
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    shr<false>(a[k].x, a[k].y, ac, bc);
+    shr<N1>(a[j].x, a[k].x, al, be);
+    shr<N1>(a[j].y, a[k].y, al, be);
+    shr<false>(a[k].x, a[k].y, -ac, -bc);
+  }
+}
+
+// fSim with Delta = 0: |01>,|10> block as an Rx-type rotation (rotation 0),
+// e^{-i phi} on |11> (rotation 1)
+template <int NR, int B0, int B1, bool ADJ, bool N0, bool N1>
+__device__ __forceinline__ void rg_sfx(c128 (&a)[NR], const SRec &r) {
+  const double a0 = ADJ ? -r.ab[0] : r.ab[0], b0 = ADJ ? -r.ab[1] : r.ab[1];
+  const double a1 = ADJ ? -r.ab[2] : r.ab[2], b1 = ADJ ? -r.ab[3] : r.ab[3];
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & ((1 << B0) | (1 << B1))) continue;
+    const int i1 = j | (1 << B0), i2 = j | (1 << B1), i3 = i1 | i2;
+    shr<N0>(a[i1].x, a[i2].y, a0, b0);
+    shr<N0>(a[i1].y, a[i2].x, -a0, -b0);
+    shr<N1>(a[i3].x, a[i3].y, a1, b1);
+  }
+}
+
 // Re sum conj(b) (D a) over the groups of an op (gradient inner products)
 template <int NR, int B>
 __device__ __forceinline__ double gr_dense1(const c128 (&a)[NR], const c128 (&b)[NR], cmat *D) {
@@ -353,12 +454,83 @@ __device__ __forceinline__ double gr_dense4(const c128 (&a)[NR], const c128 (&b)
     default: break;                                                            \
   }
 
+// rotation kinds on one register bit B: kind x bit x negation bits
+template <int R, bool ADJ, int B>
+__device__ __forceinline__ void rg_s1_at(c128 (&a)[1 << R], int kind, const SRec &r) {
+  constexpr int NR = 1 << R;
+  if constexpr (B < R) {
+    const uint32_t n = r.neg;
+    switch (kind) {
+      case GK_SXR1:
+        if (n & 1) rg_sxr1<NR, B, ADJ, true>(a, r); else rg_sxr1<NR, B, ADJ, false>(a, r);
+        break;
+      case GK_SRR1:
+        if (n & 1) rg_srr1<NR, B, ADJ, true>(a, r); else rg_srr1<NR, B, ADJ, false>(a, r);
+        break;
+      case GK_SPH1:
+        if (n & 1) rg_sph1<NR, B, ADJ, true>(a, r); else rg_sph1<NR, B, ADJ, false>(a, r);
+        break;
+      case GK_SDG1:
+        switch (n & 3) {
+          case 0: rg_sdg1<NR, B, ADJ, false, false>(a, r); break;
+          case 1: rg_sdg1<NR, B, ADJ, true, false>(a, r); break;
+          case 2: rg_sdg1<NR, B, ADJ, false, true>(a, r); break;
+          default: rg_sdg1<NR, B, ADJ, true, true>(a, r); break;
+        }
+        break;
+      default:  // GK_SRD1
+        if (n & 2) rg_srd1<NR, B, ADJ, true>(a, r); else rg_srd1<NR, B, ADJ, false>(a, r);
+        break;
+    }
+  }
+}
+
+template <int R, bool ADJ>
+__device__ __forceinline__ void rg_apply_s1(c128 (&a)[1 << R], const DGate &g, const SRec &r) {
+  switch (g.r[0]) {
+    case 0: rg_s1_at<R, ADJ, 0>(a, g.kind, r); break;
+    case 1: rg_s1_at<R, ADJ, 1>(a, g.kind, r); break;
+    case 2: rg_s1_at<R, ADJ, 2>(a, g.kind, r); break;
+    default: rg_s1_at<R, ADJ, 3>(a, g.kind, r); break;
+  }
+}
+
+template <int R, bool ADJ, int B0, int B1>
+__device__ __forceinline__ void rg_sfx_at(c128 (&a)[1 << R], const SRec &r) {
+  constexpr int NR = 1 << R;
+  if constexpr (B0 < R && B1 < R && B0 != B1) {
+    switch (r.neg & 3) {
+      case 0: rg_sfx<NR, B0, B1, ADJ, false, false>(a, r); break;
+      case 1: rg_sfx<NR, B0, B1, ADJ, true, false>(a, r); break;
+      case 2: rg_sfx<NR, B0, B1, ADJ, false, true>(a, r); break;
+      default: rg_sfx<NR, B0, B1, ADJ, true, true>(a, r); break;
+    }
+  }
+}
+
+template <int R, bool ADJ>
+__device__ __forceinline__ void rg_apply_sfx(c128 (&a)[1 << R], const DGate &g, const SRec &r) {
+  switch (g.r[0] * 4 + g.r[1]) {
+    case 1: rg_sfx_at<R, ADJ, 0, 1>(a, r); break;
+    case 2: rg_sfx_at<R, ADJ, 0, 2>(a, r); break;
+    case 3: rg_sfx_at<R, ADJ, 0, 3>(a, r); break;
+    case 4: rg_sfx_at<R, ADJ, 1, 0>(a, r); break;
+    case 6: rg_sfx_at<R, ADJ, 1, 2>(a, r); break;
+    case 7: rg_sfx_at<R, ADJ, 1, 3>(a, r); break;
+    case 8: rg_sfx_at<R, ADJ, 2, 0>(a, r); break;
+    case 9: rg_sfx_at<R, ADJ, 2, 1>(a, r); break;
+    case 11: rg_sfx_at<R, ADJ, 2, 3>(a, r); break;
+    case 12: rg_sfx_at<R, ADJ, 3, 0>(a, r); break;
+    case 13: rg_sfx_at<R, ADJ, 3, 1>(a, r); break;
+    default: rg_sfx_at<R, ADJ, 3, 2>(a, r); break;
+  }
+}
+
 // D4: whether 16x16 superoperators can occur (vectorised density matrices);
 // the pure-state LDS kernels leave them out, which frees registers
-template <int R, bool ADJ, bool D4 = true>
-__device__ __forceinline__ void rg_apply(c128 (&a)[1 << R], const DGate &g, cmat *mats) {
+template <int R, bool ADJ, bool D4>
+__device__ __forceinline__ void rg_apply_generic(c128 (&a)[1 << R], const DGate &g, cmat *M) {
   constexpr int NR = 1 << R;
-  cmat *M = mats + g.mat;
   switch (g.kind) {
     case GK_DENSE1:
       switch (g.r[0]) { VQC_CASE1(rg_dense1, 0) VQC_CASE1(rg_dense1, 1) VQC_CASE1(rg_dense1, 2) VQC_CASE1(rg_dense1, 3) default: break; }
@@ -399,6 +571,68 @@ __device__ __forceinline__ void rg_apply(c128 (&a)[1 << R], const DGate &g, cmat
       if constexpr (D4) rg_dense4<NR, ADJ>(a, M);
       break;
     default: break;
+  }
+}
+
+// move t[j] into the register that holds a[j] (the asm ties the result to
+// a[j]'s register)
+__device__ __forceinline__ void tied_set(double &d, double s) { asm("v_mov_b64 %0, %1" : "+v"(d) : "v"(s)); }
+
+// Apply one op to the lane's amplitudes.  The op loop keeps the amplitudes
+// in fixed registers: rotation kinds update them in place; every other kind
+// works on a copy whose results are moved back with register-tied moves, so
+// no dispatch arm leaves a value in another register (which would make the
+// register allocator copy all amplitudes after every op).
+// record of op g for the rotation kinds; for other kinds the first 64 B of
+// the matrix (or of the buffer, for ops without one), unused but in bounds
+__device__ __forceinline__ const SRec *srec_at(cmat *mats, const DGate &g) {
+  return (const SRec *)(mats + (g.mat > 0 ? g.mat : 0));
+}
+
+template <int R, bool ADJ, bool D4 = true>
+__device__ __forceinline__ void rg_apply_pre(c128 (&a)[1 << R], const DGate &g, const SRec &rec, cmat *mats) {
+  constexpr int NR = 1 << R;
+  cmat *M = mats + g.mat;
+  const int kind = g.kind;
+  if (kind >= GK_SXR1) {
+    if (kind == GK_SFX) rg_apply_sfx<R, ADJ>(a, g, rec);
+    else rg_apply_s1<R, ADJ>(a, g, rec);
+    return;
+  }
+  if (kind == GK_NONE) return;
+  c128 t[NR];
+#pragma unroll
+  for (int j = 0; j < NR; j++) t[j] = a[j];
+  rg_apply_generic<R, ADJ, D4>(t, g, M);
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    tied_set(a[j].x, t[j].x);
+    tied_set(a[j].y, t[j].y);
+  }
+}
+
+template <int R, bool ADJ, bool D4 = true>
+__device__ __forceinline__ void rg_apply(c128 (&a)[1 << R], const DGate &g, cmat *mats) {
+  rg_apply_pre<R, ADJ, D4>(a, g, ldc(srec_at(mats, g)), mats);
+}
+
+// Ops g0 .. g1-1 in order.  Descriptors are loaded two ops ahead and records
+// one op ahead, so the scalar-load latency overlaps the previous op's FP64
+// work instead of stalling every op (the clamped indices re-read the last
+// op near the end, always in bounds).
+template <int R, bool D4 = true>
+__device__ __forceinline__ void rg_run(c128 (&a)[1 << R], const DGate *gates, int g0, int g1, cmat *mats) {
+  if (g0 >= g1) return;
+  DGate G = ldc(&gates[g0]);
+  DGate Gn = ldc(&gates[g0 + 1 < g1 ? g0 + 1 : g0]);
+  SRec Rc = ldc(srec_at(mats, G));
+  for (int g = g0; g < g1; g++) {
+    const DGate Gnn = ldc(&gates[g + 2 < g1 ? g + 2 : g1 - 1]);
+    const SRec Rn = ldc(srec_at(mats, Gn));
+    rg_apply_pre<R, false, D4>(a, G, Rc, mats);
+    G = Gn;
+    Gn = Gnn;
+    Rc = Rn;
   }
 }
 
@@ -604,7 +838,7 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
         }
       }
       if constexpr (!ADJ) {
-        for (int g = S.g0; g < S.g1; g++) rg_apply<R, false, false>(a, ldc(&P->gates[g]), MT);
+        rg_run<R, false>(a, P->gates, S.g0, S.g1, MT);
       } else {
         for (int g = S.g1 - 1; g >= S.g0; g--) {
           const DGate G = ldc(&P->gates[g]);
@@ -706,7 +940,7 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
 #pragma unroll
     for (int j = 0; j < NR; j++) a[j] = act ? tc(A[off[j]]) : make_double2(0.0, 0.0);
     if constexpr (MODE == 0) {
-      for (int g = S.g0; g < S.g1; g++) rg_apply<R, false>(a, ldc(&P->gates[g]), MT);
+      rg_run<R>(a, P->gates, S.g0, S.g1, MT);
       gc128 *dst = (mode == 1) ? Bv : A;
       if (act) {
 #pragma unroll
@@ -730,7 +964,7 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
             c128 c[NR];
 #pragma unroll
             for (int j = 0; j < NR; j++) c[j] = a[j];
-            for (int g2 = S.g0; g2 < g; g2++) rg_apply<R, false>(c, ldc(&P->gates[g2]), MT);
+            rg_run<R>(c, P->gates, S.g0, g, MT);
             for (int d = 0; d < G.nd; d++) {
               const DDeriv Dd = ldc(&P->derivs[G.d0 + d]);
               const double v = wave_sum<64>(rg_grad<R>(c, b, G, Dd, MT));

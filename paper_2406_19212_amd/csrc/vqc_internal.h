@@ -23,8 +23,30 @@ enum GateKind : int8_t {
   GK_REAL1 = 9,   // real 2x2 (Ry, H, X, phase-free sqrt(Y))
   GK_RDIAG1 = 10, // real diagonal, complex off-diagonal (phase-free sqrt(W))
   GK_FSIMX = 11,  // fSim with Delta = 0: 1 | [[c, -i s], [-i s, c]] | e^{-i phi}
-  GK_PHASE1 = 12  // diag(1, m11) (Z, S, T)
+  GK_PHASE1 = 12, // diag(1, m11)
+  // in-place rotation forms: the op's matrix is followed by an SRec whose
+  // plane rotations are applied as three shears each (u += a v; v += b u;
+  // u += a v), so every update is an accumulate into the amplitude's own
+  // register.  g.mat of these kinds points at the SRec.
+  GK_SXR1 = 13,   // [[c, -i s], [-i s, c]] (Rx, phase-free sqrt(X))
+  GK_SRR1 = 14,   // [[c, -s], [s, c]] (Ry, phase-free sqrt(Y))
+  GK_SPH1 = 15,   // diag(1, e^{i p}) (Z, S, T)
+  GK_SDG1 = 16,   // diag(e^{i p0}, e^{i p1}) (Rz, global phase)
+  GK_SRD1 = 17,   // D^dagger R D, D = diag(1, e^{i chi}) (phase-free sqrt(W))
+  GK_SFX = 18     // fSim with Delta = 0 as two rotations of the |01>,|10> block and one phase
 };
+
+// Shear record of a rotation kind.  Rotation i by angle p (cos p = C,
+// sin p = S) is stored as a = -S/(1+C), b = S with C >= 0; an angle with
+// C < 0 is stored as the rotation by p - pi and bit i of neg set (the
+// rotation then ends with both coordinates negated).
+struct SRec {
+  uint32_t neg;
+  uint32_t pad;
+  double ab[7];     // (a, b) of rotations 0..2, one spare
+};
+static_assert(sizeof(SRec) == 64, "SRec is four c128 slots");
+constexpr int kSRecSlots = 4;
 
 constexpr int kMaxTile = 13;      // K <= 13: 2^13 * 16 B = 128 KiB of LDS
 constexpr int kMaxVarPerPass = 256;  // derivative slots reduced inside one pass
@@ -112,6 +134,8 @@ struct DRecipe {
   int32_t data;     // offset into the circuit's constant data (c128 units), -1 none
   int32_t n_data;   // entries at data
   int32_t pidx[5];  // theta index of each parameter, -1 = fixed
+  int32_t shear;    // rotation kind whose SRec follows the matrix, 0 none
+  int32_t pad;
   double pval[5];
 };
 
