@@ -247,6 +247,9 @@ struct Plan {
   DJob *d_jobs1 = nullptr;  // single-item jobs, one per pass
   int n_stages = 0;
   int64_t units_per_item = 0;  // tiles (LDS) or blocks of 256 tiles (register-only)
+  int prog = 0;                // c128 offset of the op program in an item's matrix buffer
+  int n_gates = 0;
+  const DGate *d_gates = nullptr;
 };
 
 int popc(uint64_t v) { return __builtin_popcountll(v); }
@@ -405,7 +408,8 @@ struct vqc_circuit_s {
   std::vector<vqc_op> ops;
   std::vector<c128> cdata;
   std::vector<DRecipe> recipes;
-  int mat_size = 0;
+  int mat_size = 0;   // recipe outputs
+  int mat_total = 0;  // recipe outputs + op programs of both plans (c128 per item)
   std::vector<Elem> elems;
   int n_gslots = 0;
   std::vector<int> gslot_param;
@@ -654,6 +658,7 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
     dp.K = ph.K;
     dp.nst = (int)ph.stages.size();
     dp.nvar = nvar;
+    dp.prog = P.prog;
     if (!P.reg_only && !ph.stages.empty()) {
       auto lowfree = [&](const PassH::Stage &S) {
         for (int i = 0; i < P.R; i++)
@@ -701,6 +706,8 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
   VQC_TRY(hipMemcpy(base, blob.data(), total, hipMemcpyHostToDevice));
   P.d_pass = reinterpret_cast<DPass *>(base + o_pass);
   P.d_jobs1 = reinterpret_cast<DJob *>(base + o_jobs);
+  P.d_gates = reinterpret_cast<const DGate *>(base + o_g);
+  P.n_gates = (int)gates.size();
   return VQC_OK;
 }
 
@@ -717,10 +724,13 @@ vqc_status make_plans(vqc_circuit c) {
     R = 3;
     Radj = 3;
   }
+  // op programs follow the recipe outputs in each item's matrix buffer
+  c->fwd.prog = c->mat_size;
   if (reg_only) {
     plan_passes(c->elems, nb, R, 0, R, true, c->fwd, kMaxVarPerPass);
     vqc_status st = upload_plan(c, c->fwd, false);
     if (st) return st;
+    c->adj.prog = c->fwd.prog + (c->fwd.n_gates + 2) * kOpSlots;
     plan_passes(c->elems, nb, R, 0, R, true, c->adj, kMaxVarPerPass);
     st = upload_plan(c, c->adj, true);
     if (st) return st;
@@ -733,10 +743,13 @@ vqc_status make_plans(vqc_circuit c) {
     plan_passes(c->elems, nb, K, low, R, false, c->fwd, 0);
     vqc_status st = upload_plan(c, c->fwd, false);
     if (st) return st;
+    c->adj.prog = c->fwd.prog + (c->fwd.n_gates + 2) * kOpSlots;
     plan_passes(c->elems, nb, Ka, std::min(low, Ka - 1), Radj, false, c->adj, kMaxVarPerPass);
     st = upload_plan(c, c->adj, true);
     if (st) return st;
   }
+  c->mat_total = c->adj.prog + (c->adj.n_gates + 2) * kOpSlots;
+  if (c->mats1.ensure((size_t)c->mat_total * sizeof(c128)) != hipSuccess) return VQC_ERR_HIP;
   c->tune.tile_bits = c->fwd.K;
   c->tune.low_bits = c->fwd.c;
   c->tune.reg_bits = c->fwd.R;
@@ -769,7 +782,7 @@ vqc_status upload_const(vqc_circuit c) {
   c->d_cdata = reinterpret_cast<c128 *>(base + o_c);
   c->d_csr_ptr = reinterpret_cast<int32_t *>(base + o_p);
   c->d_csr_slot = reinterpret_cast<int32_t *>(base + o_s);
-  VQC_TRY(c->mats1.ensure(std::max(kSRecSlots, c->mat_size) * sizeof(c128)));
+  VQC_TRY(c->mats1.ensure((size_t)c->mat_total * sizeof(c128)));
   return VQC_OK;
 }
 
@@ -801,6 +814,17 @@ int grid_of(vqc_circuit c, int64_t units) {
   const int g = c->tune.grid_blocks;
   if (g > 0 && g < units) return g;
   return (int)std::min<int64_t>(units, int64_t(1) << 30);
+}
+
+// matrices, rotation records and the op programs of both plans for B items
+// (thetas / mats per item) or one item (theta0 / mats0)
+hipError_t build_mats(vqc_circuit c, const double *const *thetas, c128 *const *mats, int B, const double *theta0,
+                      c128 *mats0, hipStream_t st) {
+  hipError_t e = launch_build_mats(c->d_rec, (int)c->recipes.size(), c->d_cdata, thetas, mats, B, theta0, mats0, st);
+  if (e != hipSuccess) return e;
+  e = launch_assemble(c->fwd.d_gates, c->fwd.n_gates, c->fwd.prog, mats, B, mats0, st);
+  if (e != hipSuccess) return e;
+  return launch_assemble(c->adj.d_gates, c->adj.n_gates, c->adj.prog, mats, B, mats0, st);
 }
 
 // run passes [p0, p1) of a plan on one item (dir > 0: forward order)
@@ -1227,7 +1251,7 @@ vqc_status vqc_apply_circuit(vqc_state s, vqc_circuit c, const double *theta) {
   if (s->kind != c->kind || s->n != c->n) return VQC_ERR_KIND;
   if (c->n_params > 0 && !theta) return VQC_ERR_ARG;
   c128 *mats = c->mats1.as<c128>();
-  VQC_TRY(launch_build_mats(c->d_rec, (int)c->recipes.size(), c->d_cdata, nullptr, nullptr, 1, theta, mats, s->stream));
+  VQC_TRY(build_mats(c, nullptr, nullptr, 1, theta, mats, s->stream));
   VQC_TRY(run_passes(c, c->fwd, 0, s->buf, nullptr, mats, nullptr, 0, (int)c->fwd.passes.size(), 1, s->stream));
   return VQC_OK;
 }
@@ -1240,8 +1264,7 @@ vqc_status vqc_apply_circuit_timed(vqc_state s, vqc_circuit c, const double *the
   std::vector<hipEvent_t> ev(np + 1);
   for (auto &e : ev) VQC_TRY(hipEventCreate(&e));
   c128 *mats = c->mats1.as<c128>();
-  hipError_t err = launch_build_mats(c->d_rec, (int)c->recipes.size(), c->d_cdata, nullptr, nullptr, 1, theta, mats,
-                                     s->stream);
+  hipError_t err = build_mats(c, nullptr, nullptr, 1, theta, mats, s->stream);
   if (err == hipSuccess) err = hipEventRecord(ev[0], s->stream);
   for (int p = 0; p < np && err == hipSuccess; p++) {
     err = run_passes(c, c->fwd, 0, s->buf, nullptr, mats, nullptr, p, p + 1, 1, s->stream);
@@ -1302,7 +1325,7 @@ vqc_status vqc_backward(vqc_circuit c, const double *theta, vqc_state s, const v
     if (c->has_nonunitary_matrix) return VQC_ERR_NOT_UNITARY;
     VQC_TRY(c->psi1.ensure(N * sizeof(c128)));
     c128 *psi = c->psi1.as<c128>();
-    VQC_TRY(launch_build_mats(c->d_rec, (int)c->recipes.size(), c->d_cdata, nullptr, nullptr, 1, theta, mats, st));
+    VQC_TRY(build_mats(c, nullptr, nullptr, 1, theta, mats, st));
     vs = seed_and_energy(c, terms, s->buf, psi, st, &dres);
     if (vs) return vs;
     VQC_TRY(run_passes(c, P, 1, s->buf, psi, mats, c->part1.as<double>(), 0, np, -1, st));
@@ -1325,7 +1348,7 @@ vqc_status vqc_backward(vqc_circuit c, const double *theta, vqc_state s, const v
     c128 *psi = W + N;
     c128 *ck0 = psi + N;
     c128 *seg0 = ck0 + (size_t)nck * N;
-    VQC_TRY(launch_build_mats(c->d_rec, (int)c->recipes.size(), c->d_cdata, nullptr, nullptr, 1, theta, mats, st));
+    VQC_TRY(build_mats(c, nullptr, nullptr, 1, theta, mats, st));
     if (init_dev) VQC_TRY(launch_copy(W, reinterpret_cast<const c128 *>(init_dev), N, st));
     else VQC_TRY(launch_init_basis0(W, N, st));
     for (int p = 0; p < np; p++) {
@@ -1433,7 +1456,7 @@ static vqc_status batch_build_tables(vqc_batch b) {
   for (int i = 0; i < B; i++) {
     vqc_circuit c = b->circ[i];
     b->mat_off[i] = mtot;
-    mtot += al(std::max(kSRecSlots, c->mat_size) * sizeof(c128));
+    mtot += al((size_t)c->mat_total * sizeof(c128));
     b->psi_off[i] = ptot;
     if (c->kind == VQC_PURE) ptot += al(state_len(c->kind, c->n) * sizeof(c128));
     b->part_off[i] = qtot;
@@ -1570,8 +1593,7 @@ static vqc_status batch_forward_on(vqc_batch b, hipStream_t st) {
   for (auto &g : b->groups) {
     const double *const *th = reinterpret_cast<const double *const *>(g->ptrs.p);
     c128 *const *mt = reinterpret_cast<c128 *const *>(g->ptrs.as<char>() + g->count * sizeof(void *));
-    VQC_TRY(launch_build_mats(g->c->d_rec, (int)g->c->recipes.size(), g->c->d_cdata, th, mt, g->count, nullptr,
-                              nullptr, st));
+    VQC_TRY(build_mats(g->c, th, mt, g->count, nullptr, nullptr, st));
   }
   DOverride ov;
   std::memset(&ov, 0, sizeof(ov));
@@ -1645,8 +1667,7 @@ static vqc_status batch_backward_pure_on(vqc_batch b, double *energies, hipStrea
   for (auto &g : b->groups) {
     const double *const *th = reinterpret_cast<const double *const *>(g->ptrs.p);
     c128 *const *mt = reinterpret_cast<c128 *const *>(g->ptrs.as<char>() + g->count * sizeof(void *));
-    VQC_TRY(launch_build_mats(g->c->d_rec, (int)g->c->recipes.size(), g->c->d_cdata, th, mt, g->count, nullptr,
-                              nullptr, st));
+    VQC_TRY(build_mats(g->c, th, mt, g->count, nullptr, nullptr, st));
   }
   VQC_TRY(launch_expect(b->d_sjobs, b->B, b->e_units, b->d_terms, b->n_terms, st));
   VQC_TRY(launch_reduce_partials(b->d_sjobs, b->B, b->d_eres, st));

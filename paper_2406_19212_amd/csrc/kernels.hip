@@ -278,6 +278,35 @@ __global__ void k_build_mats(const DRecipe *__restrict__ rec, int n_rec, const c
   build_recipe(rec[i], cdata, thetas ? thetas[b] : theta0, mats ? mats[b] : mats0);
 }
 
+// op program of a plan for each item: entry i + 1 is op i with its rotation
+// record copied from where the recipe built it; entries 0 and n + 1 pad
+__global__ void k_assemble(const DGate *__restrict__ gates, int n, int prog, c128 *const *__restrict__ mats, int B,
+                           c128 *mats0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= n + 2 || b >= B) return;
+  c128 *M = mats ? mats[b] : mats0;
+  DOp e;
+  e.g.kind = GK_NONE;
+  e.g.nq = 0;
+  for (int t = 0; t < 4; t++) e.g.r[t] = 0;
+  e.g.nd = 0;
+  e.g.mat = 0;
+  e.g.d0 = 0;
+  e.neg = 0;
+  e.pad = 0;
+  for (int k = 0; k < 5; k++) e.ab[k] = 0.0;
+  if (i >= 1 && i <= n) {
+    e.g = gates[i - 1];
+    if (e.g.kind >= GK_SXR1 && e.g.kind <= GK_SFX) {
+      const SRec r = *reinterpret_cast<const SRec *>(M + e.g.mat);
+      e.neg = r.neg;
+      for (int k = 0; k < 4; k++) e.ab[k] = r.ab[k];
+    }
+  }
+  *reinterpret_cast<DOp *>(M + prog + (size_t)i * kOpSlots) = e;
+}
+
 __global__ void k_build_one(DRecipe r, const c128 *__restrict__ cdata, c128 *out) {
   if (threadIdx.x == 0) build_recipe(r, cdata, nullptr, out);
 }
@@ -641,6 +670,14 @@ hipError_t launch_gm(c128 *psi, int nbits, int m, const int *q, const c128 *M, h
 
 hipError_t launch_init_basis0(c128 *v, uint64_t N, hipStream_t st) {
   hipLaunchKernelGGL(k_init_basis0, dim3(grid_for(N, 256)), dim3(256), 0, st, v, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const DGate *gates, int n_gates, int prog, c128 *const *mats, int B, c128 *mats0,
+                           hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assemble, dim3((n_gates + 2 + 63) / 64, B), dim3(64), 0, st, gates, n_gates, prog, mats, B,
+                     mats0);
   return hipGetLastError();
 }
 

@@ -80,6 +80,11 @@ __device__ __forceinline__ v2d tv(c128 c) {
   return v;
 }
 
+// streaming state access: every amplitude is read and written once per
+// pass, so loads and stores carry the nontemporal hint
+__device__ __forceinline__ c128 ldg(const gc128 *p) { return tc(__builtin_nontemporal_load(p)); }
+__device__ __forceinline__ void stg(gc128 *p, c128 v) { __builtin_nontemporal_store(tv(v), p); }
+
 // element (r, c) of M (row-major D x D) or of M^dagger
 template <bool ADJ, int D>
 __device__ __forceinline__ c128 mel(cmat *M, int r, int c) {
@@ -616,23 +621,37 @@ __device__ __forceinline__ void rg_apply(c128 (&a)[1 << R], const DGate &g, cmat
   rg_apply_pre<R, ADJ, D4>(a, g, ldc(srec_at(mats, g)), mats);
 }
 
-// Ops g0 .. g1-1 in order.  Descriptors are loaded two ops ahead and records
-// one op ahead, so the scalar-load latency overlaps the previous op's FP64
-// work instead of stalling every op (the clamped indices re-read the last
-// op near the end, always in bounds).
+// one op from its program entry
+template <int R, bool ADJ, bool D4 = true>
+__device__ __forceinline__ void rg_apply_op(c128 (&a)[1 << R], const DOp &E, cmat *mats) {
+  SRec r;
+  r.neg = E.neg;
+  r.pad = 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) r.ab[i] = E.ab[i];
+#pragma unroll
+  for (int i = 4; i < 7; i++) r.ab[i] = 0.0;
+  rg_apply_pre<R, ADJ, D4>(a, E.g, r, mats);
+}
+
+// wait for all outstanding scalar (and LDS) loads.  Scalar loads may return
+// out of order, so a wait for one of them is a wait for all: the op loops
+// wait explicitly for the op about to run *before* issuing the load of the
+// next one, which then overlaps the current op's FP64 work.
+__device__ __forceinline__ void lgkm_wait() { __builtin_amdgcn_s_waitcnt(0xc07f); }
+
+// Ops g0 .. g1-1 of a program in order (prog[g] is op g; prog[g1] is
+// readable: the next stage's op or padding).  The entry of op g + 1 is in
+// flight while op g runs.
 template <int R, bool D4 = true>
-__device__ __forceinline__ void rg_run(c128 (&a)[1 << R], const DGate *gates, int g0, int g1, cmat *mats) {
+__device__ __forceinline__ void rg_run(c128 (&a)[1 << R], const DOp *prog, int g0, int g1, cmat *mats) {
   if (g0 >= g1) return;
-  DGate G = ldc(&gates[g0]);
-  DGate Gn = ldc(&gates[g0 + 1 < g1 ? g0 + 1 : g0]);
-  SRec Rc = ldc(srec_at(mats, G));
+  DOp A = ldc(&prog[g0]);
   for (int g = g0; g < g1; g++) {
-    const DGate Gnn = ldc(&gates[g + 2 < g1 ? g + 2 : g1 - 1]);
-    const SRec Rn = ldc(srec_at(mats, Gn));
-    rg_apply_pre<R, false, D4>(a, G, Rc, mats);
-    G = Gn;
-    Gn = Gnn;
-    Rc = Rn;
+    lgkm_wait();
+    const DOp B = ldc(&prog[g + 1]);
+    rg_apply_op<R, false, D4>(a, A, mats);
+    A = B;
   }
 }
 
@@ -742,7 +761,7 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
 #pragma unroll
       for (int i = 0; i < R; i++)
         if ((j >> i) & 1) oj |= 1ull << PN.tq[K - R + i];
-      pf[j] = tc(srcn[g0 | s0 | oj]);
+      pf[j] = ldg(&srcn[g0 | s0 | oj]);
     }
   };
   if constexpr (!ADJ) {
@@ -759,6 +778,7 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
     gc128 *A = (gc128 *)(ov.use ? ov.a : J.a);
     gc128 *Bv = (gc128 *)(ov.use ? ov.b : J.b);
     cmat *MT = (cmat *)(ov.use ? ov.mats : J.mats);
+    const DOp *prog = (const DOp *)(MT + P->prog) + 1;
     double *PT = ov.use ? ov.partials : J.partials;
     const int mode = ov.use ? ov.mode : J.mode;
     uint64_t gbase = (uint64_t)tile;
@@ -789,8 +809,8 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
         for (int i = 0; i < R; i++)
           if ((j >> i) & 1) oj |= 1ull << P->tq[K - R + i];
         const uint64_t gi = gbase | st | oj;
-        la[swz(j * T + t)] = tc(src[gi]);
-        if constexpr (ADJ) lb[swz(j * T + t)] = tc(Bv[gi]);
+        la[swz(j * T + t)] = ldg(&src[gi]);
+        if constexpr (ADJ) lb[swz(j * T + t)] = ldg(&Bv[gi]);
       }
       __syncthreads();
     }
@@ -827,8 +847,8 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
 #pragma unroll
           for (int i = 0; i < R; i++)
             if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
-          a[j] = tc(src[gb | go]);
-          if constexpr (ADJ) b[j] = tc(Bv[gb | go]);
+          a[j] = ldg(&src[gb | go]);
+          if constexpr (ADJ) b[j] = ldg(&Bv[gb | go]);
         }
       } else {
 #pragma unroll
@@ -838,17 +858,20 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
         }
       }
       if constexpr (!ADJ) {
-        rg_run<R, false>(a, P->gates, S.g0, S.g1, MT);
+        rg_run<R, false>(a, prog, S.g0, S.g1, MT);
       } else {
+        DOp E = ldc(&prog[S.g1 - 1]);
         for (int g = S.g1 - 1; g >= S.g0; g--) {
-          const DGate G = ldc(&P->gates[g]);
-          rg_apply<R, true, false>(a, G, MT);  // Phi <- Q^dagger Phi
-          for (int d = 0; d < G.nd; d++) {  // <Psi| dQ |Phi>
-            const DDeriv Dd = ldc(&P->derivs[G.d0 + d]);
-            double v = wave_sum<WS>(rg_grad<R, false>(a, b, G, Dd, MT));
+          lgkm_wait();
+          const DOp En = ldc(&prog[g - 1]);  // prog[g0 - 1] is readable
+          rg_apply_op<R, true, false>(a, E, MT);  // Phi <- Q^dagger Phi
+          for (int d = 0; d < E.g.nd; d++) {  // <Psi| dQ |Phi>
+            const DDeriv Dd = ldc(&P->derivs[E.g.d0 + d]);
+            double v = wave_sum<WS>(rg_grad<R, false>(a, b, E.g, Dd, MT));
             if (lane == 0) red[Dd.local][wave] = v;
           }
-          rg_apply<R, true, false>(b, G, MT);  // Psi <- Q^dagger Psi
+          rg_apply_op<R, true, false>(b, E, MT);  // Psi <- Q^dagger Psi
+          E = En;
         }
       }
       if (last) {
@@ -858,8 +881,8 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
 #pragma unroll
           for (int i = 0; i < R; i++)
             if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
-          dst[gb | go] = tv(a[j]);
-          if constexpr (ADJ) Bv[gb | go] = tv(b[j]);
+          stg(&dst[gb | go], a[j]);
+          if constexpr (ADJ) stg(&Bv[gb | go], b[j]);
         }
       } else {
 #pragma unroll
@@ -879,8 +902,8 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
         for (int i = 0; i < R; i++)
           if ((j >> i) & 1) oj |= 1ull << P->tq[K - R + i];
         const uint64_t gi = gbase | st | oj;
-        dst[gi] = tv(la[swz(j * T + t)]);
-        if constexpr (ADJ) Bv[gi] = tv(lb[swz(j * T + t)]);
+        stg(&dst[gi], la[swz(j * T + t)]);
+        if constexpr (ADJ) stg(&Bv[gi], lb[swz(j * T + t)]);
       }
     }
     if constexpr (ADJ) {
@@ -918,6 +941,7 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
     gc128 *A = (gc128 *)(ov.use ? ov.a : J.a);
     gc128 *Bv = (gc128 *)(ov.use ? ov.b : J.b);
     cmat *MT = (cmat *)(ov.use ? ov.mats : J.mats);
+    const DOp *prog = (const DOp *)(MT + P->prog) + 1;
     double *PT = ov.use ? ov.partials : J.partials;
     const int mode = ov.use ? ov.mode : J.mode;
     const int64_t tiles = (int64_t)1 << (J.nbits - R);
@@ -938,22 +962,24 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
     }
     c128 a[NR];
 #pragma unroll
-    for (int j = 0; j < NR; j++) a[j] = act ? tc(A[off[j]]) : make_double2(0.0, 0.0);
+    for (int j = 0; j < NR; j++) a[j] = act ? ldg(&A[off[j]]) : make_double2(0.0, 0.0);
     if constexpr (MODE == 0) {
-      rg_run<R>(a, P->gates, S.g0, S.g1, MT);
+      rg_run<R>(a, prog, S.g0, S.g1, MT);
       gc128 *dst = (mode == 1) ? Bv : A;
       if (act) {
 #pragma unroll
-        for (int j = 0; j < NR; j++) dst[off[j]] = tv(a[j]);
+        for (int j = 0; j < NR; j++) stg(&dst[off[j]], a[j]);
       }
     } else {
       c128 b[NR];
 #pragma unroll
-      for (int j = 0; j < NR; j++) b[j] = act ? tc(Bv[off[j]]) : make_double2(0.0, 0.0);
+      for (int j = 0; j < NR; j++) b[j] = act ? ldg(&Bv[off[j]]) : make_double2(0.0, 0.0);
       for (int g = S.g1 - 1; g >= S.g0; g--) {
-        const DGate G = ldc(&P->gates[g]);
+        lgkm_wait();
+        const DOp E = ldc(&prog[g]);
+        const DGate &G = E.g;
         if constexpr (MODE == 1) {
-          rg_apply<R, true>(a, G, MT);
+          rg_apply_op<R, true>(a, E, MT);
           for (int d = 0; d < G.nd; d++) {
             const DDeriv Dd = ldc(&P->derivs[G.d0 + d]);
             const double v = wave_sum<64>(rg_grad<R>(a, b, G, Dd, MT));
@@ -964,7 +990,7 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
             c128 c[NR];
 #pragma unroll
             for (int j = 0; j < NR; j++) c[j] = a[j];
-            rg_run<R>(c, P->gates, S.g0, g, MT);
+            rg_run<R>(c, prog, S.g0, g, MT);
             for (int d = 0; d < G.nd; d++) {
               const DDeriv Dd = ldc(&P->derivs[G.d0 + d]);
               const double v = wave_sum<64>(rg_grad<R>(c, b, G, Dd, MT));
@@ -972,13 +998,13 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
             }
           }
         }
-        rg_apply<R, true>(b, G, MT);
+        rg_apply_op<R, true>(b, E, MT);
       }
       if (act) {
 #pragma unroll
         for (int j = 0; j < NR; j++) {
-          if constexpr (MODE == 1) A[off[j]] = tv(a[j]);
-          Bv[off[j]] = tv(b[j]);
+          if constexpr (MODE == 1) stg(&A[off[j]], a[j]);
+          stg(&Bv[off[j]], b[j]);
         }
       }
       __syncthreads();

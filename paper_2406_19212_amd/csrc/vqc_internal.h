@@ -61,6 +61,21 @@ struct DGate {
   int32_t d0;       // first derivative record
 };
 
+// Op g of a plan as the pass kernels read it: the static descriptor plus the
+// item's rotation record, stored in execution order inside the item's matrix
+// buffer so that each op is one 64 B scalar load at an address known without
+// reading anything else first.  Entry 0 and entry n+1 of a plan's program
+// are padding (kind GK_NONE) so the kernels may read one op past either end
+// of a stage.
+struct DOp {
+  DGate g;
+  uint32_t neg;
+  uint32_t pad;
+  double ab[5];     // rotation parameters (GK_S* kinds), as in SRec
+};
+static_assert(sizeof(DOp) == 64, "DOp is four c128 slots");
+constexpr int kOpSlots = 4;
+
 struct DDeriv {
   int8_t kind;      // register kind of the derivative matrix
   int8_t pad[3];
@@ -82,6 +97,8 @@ struct DPass {
   int32_t lowfree;  // bit 0: stage 0 holds none of the low c bits; bit 1: the last stage
                     // holds none (that stage can then load/store HBM directly, coalesced)
   int8_t tq[16];    // global qubit of tile-local bit i, ascending
+  int32_t prog;     // c128 offset of the plan's op program in the item's matrix buffer
+  int32_t pad;
   const DStage *stages;   // absolute device pointers
   const DGate *gates;
   const DDeriv *derivs;
@@ -171,6 +188,8 @@ hipError_t launch_pass_reg(int R, int mode, const DJob *jobs, int n_jobs, int64_
 hipError_t launch_build_mats(const DRecipe *rec, int n_rec, const c128 *cdata, const double *const *thetas,
                              c128 *const *mats, int B, const double *theta0, c128 *mats0, hipStream_t st);
 hipError_t launch_build_one(const DRecipe &r, const c128 *cdata, c128 *out, hipStream_t st);
+hipError_t launch_assemble(const DGate *gates, int n_gates, int prog, c128 *const *mats, int B, c128 *mats0,
+                           hipStream_t st);
 hipError_t launch_init_batched(c128 *const *ptrs, const uint64_t *sizes, int B, uint64_t max_n, hipStream_t st);
 int64_t expect_units(int nbits_iter);
 hipError_t launch_expect(const DEJob *jobs, int n_jobs, int64_t total, const DTerm *terms, int nt, hipStream_t st);
