@@ -302,3 +302,62 @@ def test_every_kind_fused_forward_and_adjoint(n, n_sqrt, tile, reg):
     assert maxdiff(g.cpu().numpy(), g_ref) < GRAD_TOL
     phi = st.numpy()
     assert abs(phi[0] - 1) < 1e-11 and np.max(np.abs(phi[1:])) < 1e-11
+
+
+EDGE_ANGLES = [0.0, math.pi / 2, math.pi, 1.5 * math.pi, 2 * math.pi, -math.pi, -math.pi / 2, 1e-9,
+               math.pi - 1e-9, math.pi + 1e-9, 4 * math.pi - 1e-3, 3 * math.pi]
+
+
+def _edge_circuit(n, seed):
+    """Rotation-type ops (the kinds applied as in-place plane rotations) at
+    angles where the cosine is 0, +-1 or changes sign, mixed with random ones."""
+    rng = np.random.default_rng(seed)
+    ops, th = [], []
+    for i in range(5 * n):
+        q = int(rng.integers(n))
+        r = i % 5
+        if r < 3:
+            ops.append(Op(["rx", "ry", "rz"][r], (q,), (0.0,), (len(th),)))
+            th.append(EDGE_ANGLES[i % len(EDGE_ANGLES)] if i % 2 == 0 else float(rng.uniform(0, 2 * math.pi)))
+        elif r == 3:
+            ops.append(Op(["s", "t", "z", "sx", "sy", "sw"][int(rng.integers(6))], (q,)))
+        else:
+            a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+            ops.append(Op("fsim", (a, b), (0.0, 0.0, 0, 0, 0), (len(th), len(th) + 1, -1, -1, -1)))
+            th.append(EDGE_ANGLES[i % len(EDGE_ANGLES)])
+            th.append(EDGE_ANGLES[(3 * i + 1) % len(EDGE_ANGLES)])
+    return ops, np.array(th)
+
+
+@pytest.mark.parametrize("n,tile,reg", [(9, 8, 4), (10, 9, 3)])
+def test_rotation_kinds_at_edge_angles(n, tile, reg):
+    ops, th = _edge_circuit(n, 7 + n)
+    c = Circuit(n, ops, n_params=len(th), tune={"tile_bits": tile, "low_bits": 3, "reg_bits": reg})
+    psi0 = W.random_state(n, 11 + n)
+    st = State(n, init=psi0)
+    tht = torch.tensor(th, device="cuda")
+    c.apply(st, tht)
+    assert maxdiff(st.numpy(), oracle.run(n, ops, th, init=psi0)) < AMP_TOL
+    st = State(n)
+    c.apply(st, tht)
+    terms = W.tfim(n, 0.7)
+    g, e = c.backward(tht, st, terms)
+    e_ref, g_ref, _ = oracle.grad_pure(n, ops, th, terms)
+    assert abs(e - e_ref) < AMP_TOL
+    assert maxdiff(g.cpu().numpy(), g_ref) < GRAD_TOL
+
+
+def test_rotation_kinds_at_edge_angles_mixed():
+    n = 4
+    rng = np.random.default_rng(5)
+    ops = []
+    for i, a in enumerate(EDGE_ANGLES):
+        q = int(rng.integers(n))
+        ops.append(Op(["rx", "ry", "rz"][i % 3], (q,), (a,)))
+        ops.append(Op(["s", "t", "z"][i % 3], (int(rng.integers(n)),)))
+        p, r = (int(v) for v in rng.choice(n, 2, replace=False))
+        ops.append(Op("fsim", (p, r), (a, EDGE_ANGLES[-1 - i], 0, 0, 0)))
+    v = W.random_density(n, 3).reshape(-1, order="F")
+    st = State(n, mixed=True, init=v)
+    Circuit(n, ops, mixed=True).apply(st)
+    assert maxdiff(st.numpy(), oracle.run(n, ops, mixed=True, init=v)) < AMP_TOL
