@@ -250,6 +250,7 @@ struct Plan {
   int prog = 0;                // c128 offset of the op program in an item's matrix buffer
   int n_gates = 0;
   const DGate *d_gates = nullptr;
+  const DDeriv *d_derivs = nullptr;
 };
 
 int popc(uint64_t v) { return __builtin_popcountll(v); }
@@ -553,8 +554,14 @@ vqc_status lower(vqc_circuit c) {
       const bool fac = phase_factored(op.type);
       n_factored += fac;
       e.mat = add_gate_recipe(c, gk, op.type, fac ? RF_GATE_F : RF_GATE, m, op, data_off, n_data);
+      // Pauli rotations exp(-i theta G / 2): derivative from the generator
+      const int gen = op.type == VQC_RX ? GK_GENX : op.type == VQC_RY ? GK_GENY : op.type == VQC_RZ ? GK_GENZ : 0;
       for (int k = 0; k < 5; k++)
         if (op.param_index[k] >= 0) {
+          if (gen) {
+            e.d.push_back(new_deriv(gen, -1, k));
+            continue;
+          }
           const int dk = (m == 1) ? (gk == GK_SDG1 ? GK_DIAG1 : GK_DENSE1) : GK_DENSE2;
           const int mat = add_recipe(c, op.type, RF_DGATE, k, m, op, data_off, n_data, d * d);
           e.d.push_back(new_deriv(dk, mat, k));
@@ -636,6 +643,7 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
         g.mat = e.mat;
         g.d0 = (int)derivs.size();
         g.nd = adjoint ? (int16_t)e.d.size() : 0;
+        if (adjoint && !e.d.empty() && e.d[0].kind >= GK_GENX && e.d[0].kind <= GK_GENZ) g.nd |= kGenFlag;
         if (adjoint)
           for (const Deriv &dv : e.d) {
             DDeriv dd;
@@ -707,6 +715,7 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
   P.d_pass = reinterpret_cast<DPass *>(base + o_pass);
   P.d_jobs1 = reinterpret_cast<DJob *>(base + o_jobs);
   P.d_gates = reinterpret_cast<const DGate *>(base + o_g);
+  P.d_derivs = reinterpret_cast<const DDeriv *>(base + o_d);
   P.n_gates = (int)gates.size();
   return VQC_OK;
 }
@@ -719,7 +728,11 @@ vqc_status make_plans(vqc_circuit c) {
   if (K > kMaxTile) K = kMaxTile;
   const bool reg_only = mixed || nb < 5;
   int R = std::min(kR, nb);
-  int Radj = R;
+  // the adjoint step keeps two states and runs derivative reductions: three
+  // register bits (more waves per SIMD) beat four there, while four are best
+  // for the forward pass (measured on the 20-qubit gradient and the
+  // 28-qubit circuit)
+  int Radj = (!reg_only && nb >= 8) ? 3 : R;
   if (!reg_only && c->tune.reg_bits == 3) {
     R = 3;
     Radj = 3;
@@ -822,9 +835,9 @@ hipError_t build_mats(vqc_circuit c, const double *const *thetas, c128 *const *m
                       c128 *mats0, hipStream_t st) {
   hipError_t e = launch_build_mats(c->d_rec, (int)c->recipes.size(), c->d_cdata, thetas, mats, B, theta0, mats0, st);
   if (e != hipSuccess) return e;
-  e = launch_assemble(c->fwd.d_gates, c->fwd.n_gates, c->fwd.prog, mats, B, mats0, st);
+  e = launch_assemble(c->fwd.d_gates, c->fwd.d_derivs, c->fwd.n_gates, c->fwd.prog, mats, B, mats0, st);
   if (e != hipSuccess) return e;
-  return launch_assemble(c->adj.d_gates, c->adj.n_gates, c->adj.prog, mats, B, mats0, st);
+  return launch_assemble(c->adj.d_gates, c->adj.d_derivs, c->adj.n_gates, c->adj.prog, mats, B, mats0, st);
 }
 
 // run passes [p0, p1) of a plan on one item (dir > 0: forward order)
@@ -1695,7 +1708,7 @@ vqc_status vqc_batch_create(vqc_batch *out, int B, const vqc_circuit *circuits, 
     const vqc_circuit c = circuits[i], c0 = circuits[0];
     if (c->kind != c0->kind) return VQC_ERR_KIND;
     if (c->fwd.reg_only != c0->fwd.reg_only || c->fwd.K != c0->fwd.K || c->fwd.R != c0->fwd.R ||
-        c->adj.K != c0->adj.K || c->adj.reg_only != c0->adj.reg_only)
+        c->adj.K != c0->adj.K || c->adj.R != c0->adj.R || c->adj.reg_only != c0->adj.reg_only)
       return VQC_ERR_UNSUPPORTED;
   }
   std::unique_ptr<vqc_batch_s> b(new (std::nothrow) vqc_batch_s());

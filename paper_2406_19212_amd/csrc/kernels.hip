@@ -280,8 +280,8 @@ __global__ void k_build_mats(const DRecipe *__restrict__ rec, int n_rec, const c
 
 // op program of a plan for each item: entry i + 1 is op i with its rotation
 // record copied from where the recipe built it; entries 0 and n + 1 pad
-__global__ void k_assemble(const DGate *__restrict__ gates, int n, int prog, c128 *const *__restrict__ mats, int B,
-                           c128 *mats0) {
+__global__ void k_assemble(const DGate *__restrict__ gates, const DDeriv *__restrict__ derivs, int n, int prog,
+                           c128 *const *__restrict__ mats, int B, c128 *mats0) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
   if (i >= n + 2 || b >= B) return;
@@ -302,6 +302,10 @@ __global__ void k_assemble(const DGate *__restrict__ gates, int n, int prog, c12
       const SRec r = *reinterpret_cast<const SRec *>(M + e.g.mat);
       e.neg = r.neg;
       for (int k = 0; k < 4; k++) e.ab[k] = r.ab[k];
+    }
+    if ((e.g.nd & kGenFlag) && (e.g.nd & 0xff) == 1) {
+      const DDeriv d = derivs[e.g.d0];
+      e.pad = (1u << 31) | ((uint32_t)(d.local & 0xffff) << 8) | (uint32_t)(d.kind & 0xff);
     }
   }
   *reinterpret_cast<DOp *>(M + prog + (size_t)i * kOpSlots) = e;
@@ -673,11 +677,11 @@ hipError_t launch_init_basis0(c128 *v, uint64_t N, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_assemble(const DGate *gates, int n_gates, int prog, c128 *const *mats, int B, c128 *mats0,
-                           hipStream_t st) {
+hipError_t launch_assemble(const DGate *gates, const DDeriv *derivs, int n_gates, int prog, c128 *const *mats,
+                           int B, c128 *mats0, hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_assemble, dim3((n_gates + 2 + 63) / 64, B), dim3(64), 0, st, gates, n_gates, prog, mats, B,
-                     mats0);
+  hipLaunchKernelGGL(k_assemble, dim3((n_gates + 2 + 63) / 64, B), dim3(64), 0, st, gates, derivs, n_gates, prog,
+                     mats, B, mats0);
   return hipGetLastError();
 }
 

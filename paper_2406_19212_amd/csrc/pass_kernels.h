@@ -440,6 +440,37 @@ __device__ __forceinline__ double gr_dense4(const c128 (&a)[NR], const c128 (&b)
   return acc;
 }
 
+// Im<b| G |a> / 2 for G = X, Y or Z on register bit B (a is Phi after the op)
+template <int NR, int B, int GEN>
+__device__ __forceinline__ double gr_gen(const c128 (&a)[NR], const c128 (&b)[NR]) {
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    if (GEN == GK_GENZ) {
+      // Im(conj(b_j) a_j) - Im(conj(b_k) a_k)
+      acc = fma(b[j].x, a[j].y, acc);
+      acc = fma(-b[j].y, a[j].x, acc);
+      acc = fma(-b[k].x, a[k].y, acc);
+      acc = fma(b[k].y, a[k].x, acc);
+    } else if (GEN == GK_GENX) {
+      // Im(conj(b_j) a_k) + Im(conj(b_k) a_j)
+      acc = fma(b[j].x, a[k].y, acc);
+      acc = fma(-b[j].y, a[k].x, acc);
+      acc = fma(b[k].x, a[j].y, acc);
+      acc = fma(-b[k].y, a[j].x, acc);
+    } else {
+      // (Y a)_j = -i a_k, (Y a)_k = i a_j: Re(conj(b_k) a_j) - Re(conj(b_j) a_k)
+      acc = fma(b[k].x, a[j].x, acc);
+      acc = fma(b[k].y, a[j].y, acc);
+      acc = fma(-b[j].x, a[k].x, acc);
+      acc = fma(-b[j].y, a[k].y, acc);
+    }
+  }
+  return 0.5 * acc;
+}
+
 // dispatch on kind and register bits (compile-time bit positions keep the
 // amplitude array in VGPRs)
 #define VQC_CASE1(FN, B) \
@@ -664,6 +695,26 @@ __device__ __forceinline__ void rg_run(c128 (&a)[1 << R], const DOp *prog, int g
     if constexpr (B0 < R && B1 < R) v = gr_dense2<NR, B0, B1>(a, b, D); \
     break;
 
+template <int R, int B>
+__device__ __forceinline__ double rg_grad_gen_at(const c128 (&a)[1 << R], const c128 (&b)[1 << R], int kind) {
+  if constexpr (B < R) {
+    if (kind == GK_GENZ) return gr_gen<1 << R, B, GK_GENZ>(a, b);
+    if (kind == GK_GENX) return gr_gen<1 << R, B, GK_GENX>(a, b);
+    return gr_gen<1 << R, B, GK_GENY>(a, b);
+  }
+  return 0.0;
+}
+
+template <int R>
+__device__ __forceinline__ double rg_grad_gen(const c128 (&a)[1 << R], const c128 (&b)[1 << R], int kind, int r0) {
+  switch (r0) {
+    case 0: return rg_grad_gen_at<R, 0>(a, b, kind);
+    case 1: return rg_grad_gen_at<R, 1>(a, b, kind);
+    case 2: return rg_grad_gen_at<R, 2>(a, b, kind);
+    default: return rg_grad_gen_at<R, 3>(a, b, kind);
+  }
+}
+
 // derivative records reuse the register bits of their op
 template <int R, bool D4 = true>
 __device__ __forceinline__ double rg_grad(const c128 (&a)[1 << R], const c128 (&b)[1 << R], const DGate &g,
@@ -688,16 +739,46 @@ __device__ __forceinline__ double rg_grad(const c128 (&a)[1 << R], const c128 (&
     case GK_DENSE4:
       if constexpr (D4) v = gr_dense4<NR>(a, b, D);
       break;
+    case GK_GENX: case GK_GENY: case GK_GENZ:
+      v = rg_grad_gen<R>(a, b, d.kind, g.r[0]);
+      break;
     default: break;
   }
   return v;
 }
 
+// one DPP move of a double (both halves) from the lane the control selects;
+// lanes in rows outside ROWMASK get 0
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int rlo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xf, false);
+  const int rhi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(rhi, rlo);
+}
+
+// Sum over the lanes of a wave (W lanes active, W a power of two).  A full
+// wave64 reduces with DPP moves (quad swaps, half-row and row mirrors, then
+// the row-15 and row-31 broadcasts), all in the VALU, and the total is read
+// from lane 63 into a scalar; narrower groups use lane shuffles.  The result
+// is the same in every lane.
 template <int W>
 __device__ __forceinline__ double wave_sum(double v) {
+  if constexpr (W == 64) {
+    v += dpp_d<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);       // row_half_mirror: sum of 8
+    v += dpp_d<0x140>(v);       // row_mirror: sum of 16
+    v += dpp_d<0x142, 0xA>(v);  // row_bcast15 into rows 1 and 3
+    v += dpp_d<0x143, 0xC>(v);  // row_bcast31 into rows 2 and 3: lane 63 = total
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+  } else {
 #pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
-  return v;
+    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+    return v;
+  }
 }
 
 // tile-local bit -> global qubit for a runtime (uniform) local bit: one
@@ -864,12 +945,22 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
         for (int g = S.g1 - 1; g >= S.g0; g--) {
           lgkm_wait();
           const DOp En = ldc(&prog[g - 1]);  // prog[g0 - 1] is readable
+          const int nd = E.g.nd & 0xff;
+          auto grads = [&]() {  // Re<Psi| dQ |Phi before Q>
+            if (E.pad >> 31) {  // one generator derivative, carried in the entry
+              const double v = wave_sum<WS>(rg_grad_gen<R>(a, b, E.pad & 0xff, E.g.r[0]));
+              if (lane == 0) red[(E.pad >> 8) & 0xffff][wave] = v;
+              return;
+            }
+            for (int d = 0; d < nd; d++) {
+              const DDeriv Dd = ldc(&P->derivs[E.g.d0 + d]);
+              double v = wave_sum<WS>(rg_grad<R, false>(a, b, E.g, Dd, MT));
+              if (lane == 0) red[Dd.local][wave] = v;
+            }
+          };
+          if (E.g.nd & kGenFlag) grads();         // generator form: Phi after Q
           rg_apply_op<R, true, false>(a, E, MT);  // Phi <- Q^dagger Phi
-          for (int d = 0; d < E.g.nd; d++) {  // <Psi| dQ |Phi>
-            const DDeriv Dd = ldc(&P->derivs[E.g.d0 + d]);
-            double v = wave_sum<WS>(rg_grad<R, false>(a, b, E.g, Dd, MT));
-            if (lane == 0) red[Dd.local][wave] = v;
-          }
+          if (!(E.g.nd & kGenFlag)) grads();
           rg_apply_op<R, true, false>(b, E, MT);  // Psi <- Q^dagger Psi
           E = En;
         }
@@ -978,20 +1069,33 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
         lgkm_wait();
         const DOp E = ldc(&prog[g]);
         const DGate &G = E.g;
+        const int nd = G.nd & 0xff;
+        const bool gen = G.nd & kGenFlag;
         if constexpr (MODE == 1) {
+          auto grads = [&]() {
+            if (E.pad >> 31) {  // one generator derivative, carried in the entry
+              const double v = wave_sum<64>(rg_grad_gen<R>(a, b, E.pad & 0xff, G.r[0]));
+              if (lane == 0) red[(E.pad >> 8) & 0xffff][wave] = v;
+              return;
+            }
+            for (int d = 0; d < nd; d++) {
+              const DDeriv Dd = ldc(&P->derivs[G.d0 + d]);
+              const double v = wave_sum<64>(rg_grad<R>(a, b, G, Dd, MT));
+              if (lane == 0) red[Dd.local][wave] = v;
+            }
+          };
+          if (gen) grads();  // generator form: Phi after the op
           rg_apply_op<R, true>(a, E, MT);
-          for (int d = 0; d < G.nd; d++) {
-            const DDeriv Dd = ldc(&P->derivs[G.d0 + d]);
-            const double v = wave_sum<64>(rg_grad<R>(a, b, G, Dd, MT));
-            if (lane == 0) red[Dd.local][wave] = v;
-          }
+          if (!gen) grads();
         } else {
-          if (G.nd > 0) {
+          if (nd > 0) {
+            // Phi before op g (after it, for generator derivatives),
+            // recomputed from the pass-start checkpoint
             c128 c[NR];
 #pragma unroll
             for (int j = 0; j < NR; j++) c[j] = a[j];
-            rg_run<R>(c, prog, S.g0, g, MT);
-            for (int d = 0; d < G.nd; d++) {
+            rg_run<R>(c, prog, S.g0, gen ? g + 1 : g, MT);
+            for (int d = 0; d < nd; d++) {
               const DDeriv Dd = ldc(&P->derivs[G.d0 + d]);
               const double v = wave_sum<64>(rg_grad<R>(c, b, G, Dd, MT));
               if (lane == 0) red[Dd.local][wave] = v;

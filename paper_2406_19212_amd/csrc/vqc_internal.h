@@ -33,8 +33,17 @@ enum GateKind : int8_t {
   GK_SPH1 = 15,   // diag(1, e^{i p}) (Z, S, T)
   GK_SDG1 = 16,   // diag(e^{i p0}, e^{i p1}) (Rz, global phase)
   GK_SRD1 = 17,   // D^dagger R D, D = diag(1, e^{i chi}) (phase-free sqrt(W))
-  GK_SFX = 18     // fSim with Delta = 0 as two rotations of the |01>,|10> block and one phase
+  GK_SFX = 18,    // fSim with Delta = 0 as two rotations of the |01>,|10> block and one phase
+  // derivative-only kinds of U = exp(-i theta G / 2), G = X, Y, Z on one bit:
+  // Re<Psi| dU |Phi_before> = Im<Psi| G |Phi_after> / 2, evaluated before
+  // Phi is uncomputed through U (no derivative matrix)
+  GK_GENX = 19,
+  GK_GENY = 20,
+  GK_GENZ = 21
 };
+// DGate.nd: derivative count in the low byte; this bit set when the op's
+// derivatives are generator kinds (taken on Phi before the op is undone)
+constexpr int kGenFlag = 0x100;
 
 // Shear record of a rotation kind.  Rotation i by angle p (cos p = C,
 // sin p = S) is stored as a = -S/(1+C), b = S with C >= 0; an angle with
@@ -70,7 +79,7 @@ struct DGate {
 struct DOp {
   DGate g;
   uint32_t neg;
-  uint32_t pad;
+  uint32_t pad;     // bit 31: one generator derivative, kind in bits 0-7, local slot in 8-23
   double ab[5];     // rotation parameters (GK_S* kinds), as in SRec
 };
 static_assert(sizeof(DOp) == 64, "DOp is four c128 slots");
@@ -188,8 +197,8 @@ hipError_t launch_pass_reg(int R, int mode, const DJob *jobs, int n_jobs, int64_
 hipError_t launch_build_mats(const DRecipe *rec, int n_rec, const c128 *cdata, const double *const *thetas,
                              c128 *const *mats, int B, const double *theta0, c128 *mats0, hipStream_t st);
 hipError_t launch_build_one(const DRecipe &r, const c128 *cdata, c128 *out, hipStream_t st);
-hipError_t launch_assemble(const DGate *gates, int n_gates, int prog, c128 *const *mats, int B, c128 *mats0,
-                           hipStream_t st);
+hipError_t launch_assemble(const DGate *gates, const DDeriv *derivs, int n_gates, int prog, c128 *const *mats,
+                           int B, c128 *mats0, hipStream_t st);
 hipError_t launch_init_batched(c128 *const *ptrs, const uint64_t *sizes, int B, uint64_t max_n, hipStream_t st);
 int64_t expect_units(int nbits_iter);
 hipError_t launch_expect(const DEJob *jobs, int n_jobs, int64_t total, const DTerm *terms, int nt, hipStream_t st);
