@@ -114,12 +114,17 @@ typedef struct {
  * tile_bits: qubits per LDS tile (K); low_bits: contiguous low qubits every
  * tile includes (c); reg_bits: qubits held per thread (R, 3 or 4);
  * grid_blocks: persistent grid size (0 = one block per tile).  Zero fields
- * take the library default. */
+ * take the library default.
+ * remap: forward passes may move qubits into the contiguous low block for
+ * the next pass (the state ends in the standard layout; the circuit then
+ * holds a second state buffer of the same size): 1 on, -1 off, 0 default
+ * (on from 22 qubits, pure states). */
 typedef struct {
   int tile_bits;
   int low_bits;
   int reg_bits;
   int grid_blocks;
+  int remap;
 } vqc_tune;
 
 typedef struct {

@@ -112,7 +112,8 @@ class Circuit:
         arr = B.OpArray(self.ops)
         t = None
         if tune is not None:
-            t = B.vqc_tune(*[int(tune.get(k, 0)) for k in ("tile_bits", "low_bits", "reg_bits", "grid_blocks")])
+            t = B.vqc_tune(*[int(tune.get(k, 0)) for k in ("tile_bits", "low_bits", "reg_bits", "grid_blocks",
+                                                           "remap")])
         h = ctypes.c_void_p()
         check(lib().vqc_circuit_create(ctypes.byref(h), self.n, B.VQC_MIXED if self.mixed else B.VQC_PURE,
                                        arr.n, arr.ptr(), self.n_params,
@@ -131,7 +132,7 @@ class Circuit:
         return {"n_ops": s.n_ops, "n_elementary": s.n_elementary, "n_passes": s.n_passes,
                 "n_stages": s.n_stages, "n_var": s.n_var, "n_params": s.n_params,
                 "tile_bits": s.tune.tile_bits, "low_bits": s.tune.low_bits, "reg_bits": s.tune.reg_bits,
-                "grid_blocks": s.tune.grid_blocks, "alg_bytes_per_amp": s.alg_bytes_per_amp}
+                "grid_blocks": s.tune.grid_blocks, "remap": s.tune.remap, "alg_bytes_per_amp": s.alg_bytes_per_amp}
 
     def _theta(self, theta):
         if self.n_params == 0:
@@ -171,7 +172,7 @@ class Circuit:
         t = B.vqc_tune()
         check(lib().vqc_circuit_autotune(self.h, state.h, _dptr(th), ctypes.byref(t)), "vqc_circuit_autotune")
         return {"tile_bits": t.tile_bits, "low_bits": t.low_bits, "reg_bits": t.reg_bits,
-                "grid_blocks": t.grid_blocks}
+                "grid_blocks": t.grid_blocks, "remap": t.remap}
 
 
 class Batch:

@@ -62,7 +62,8 @@ class vqc_pauli_sum(ctypes.Structure):
 
 
 class vqc_tune(ctypes.Structure):
-    _fields_ = [("tile_bits", c_int), ("low_bits", c_int), ("reg_bits", c_int), ("grid_blocks", c_int)]
+    _fields_ = [("tile_bits", c_int), ("low_bits", c_int), ("reg_bits", c_int), ("grid_blocks", c_int),
+                ("remap", c_int)]
 
 
 class vqc_circuit_stats(ctypes.Structure):

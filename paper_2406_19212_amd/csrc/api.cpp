@@ -23,6 +23,9 @@ namespace {
 constexpr int kDefaultTile = 11;
 constexpr int kDefaultAdjTile = 11;
 constexpr int kDefaultLow = 4;
+// forward plans of states with at least this many qubits move qubits into
+// the low block between passes (and keep a second state buffer for it)
+constexpr int kRemapMinBits = 22;
 constexpr int kR = 4;
 
 #define VQC_TRY(expr)                                         \
@@ -229,7 +232,11 @@ struct Elem {
 
 struct PassH {
   int K;
-  std::vector<int> tq;  // ascending global bits
+  std::vector<int> tq;      // physical bit (input layout) of tile-local bit i, ascending
+  std::vector<int> lq;      // logical qubit of tile-local bit i
+  std::vector<int> tq_out;  // physical bit of tile-local bit i in the output layout
+  bool moves = false;       // output layout differs from the input layout
+  int src = 0, dst = 0;     // 0: the state's buffer, 1: the circuit's scratch state
   struct Stage {
     int rbit[4];
     std::vector<int> elems;  // indices into elems
@@ -239,6 +246,8 @@ struct PassH {
 
 struct Plan {
   bool reg_only = false;
+  bool remap = false;          // passes move qubits between the low block and the rest
+  bool needs_scratch = false;  // some pass runs out of place
   int K = 0, R = kR, c = kDefaultLow;
   std::vector<PassH> passes;
   // device tables
@@ -255,15 +264,82 @@ struct Plan {
 
 int popc(uint64_t v) { return __builtin_popcountll(v); }
 
+// empty plan (keeps its device buffer for reuse)
+void reset_plan(Plan &P) {
+  P.passes.clear();
+  P.reg_only = false;
+  P.remap = false;
+  P.needs_scratch = false;
+  P.n_stages = 0;
+  P.units_per_item = 0;
+  P.prog = 0;
+  P.n_gates = 0;
+  P.d_pass = nullptr;
+  P.d_jobs1 = nullptr;
+  P.d_gates = nullptr;
+  P.d_derivs = nullptr;
+}
+
 // First-fit fusion: walk the remaining ops in order; an op joins the pass if
 // its qubits fit in the tile (<= K bits, the low c bits always included) and
 // no earlier skipped op shares a qubit with it (program order on every qubit
 // is kept, ops on disjoint qubits commute).  Then split each pass into
 // register stages of R bits the same way.
+// ops of `rem` (a prefix of at most `limit`) the first-fit rule takes into one
+// tile of TK bits that must hold `forced`
+int count_fit(const std::vector<Elem> &E, const std::vector<int> &rem, uint64_t forced, int TK, size_t limit) {
+  uint64_t tile = forced, blocked = 0;
+  int n = 0;
+  for (size_t k = 0; k < rem.size() && k < limit; k++) {
+    const uint64_t m = E[rem[k]].mask();
+    if (m & blocked) { blocked |= m; continue; }
+    if (popc(tile | m) <= TK) { tile |= m; n++; }
+    else blocked |= m;
+  }
+  return n;
+}
+
+// Layout "low set first": the c qubits of L at physical bits 0..c-1 in
+// ascending order, every other qubit after them in ascending order.
+void layout_of(uint64_t L, int nbits, std::vector<int> &pos) {
+  pos.assign(nbits, 0);
+  int k = 0;
+  for (int q = 0; q < nbits; q++)
+    if ((L >> q) & 1) pos[q] = k++;
+  for (int q = 0; q < nbits; q++)
+    if (!((L >> q) & 1)) pos[q] = k++;
+}
+
+// the c-subset of `tile` that lets the next pass take the most ops
+uint64_t choose_low(const std::vector<Elem> &E, const std::vector<int> &rem, uint64_t tile, int c, int TK) {
+  std::vector<int> q;
+  for (int b = 0; b < 64; b++)
+    if ((tile >> b) & 1) q.push_back(b);
+  const int t = (int)q.size();
+  uint64_t best = 0;
+  int best_n = -1;
+  std::vector<int> idx(c);
+  for (int i = 0; i < c; i++) idx[i] = i;
+  while (true) {
+    uint64_t L = 0;
+    for (int i = 0; i < c; i++) L |= 1ull << q[idx[i]];
+    const int n = count_fit(E, rem, L, TK, 256);
+    if (n > best_n) { best_n = n; best = L; }
+    int i = c - 1;
+    while (i >= 0 && idx[i] == t - c + i) i--;
+    if (i < 0) break;
+    idx[i]++;
+    for (int j = i + 1; j < c; j++) idx[j] = idx[j - 1] + 1;
+  }
+  return best;
+}
+
 void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, bool reg_only, Plan &P,
-                 int max_var) {
+                 int max_var, bool remap = false) {
   P.passes.clear();
   P.reg_only = reg_only;
+  P.remap = remap && !reg_only && c > 0;
+  P.needs_scratch = false;
   P.K = reg_only ? R : K;
   P.R = R;
   P.c = c;
@@ -271,8 +347,36 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
   for (size_t i = 0; i < E.size(); i++)
     if (E[i].kind != GK_NONE) rem.push_back((int)i);
   const int TK = reg_only ? R : K;
+  // current layout: logical qubit -> physical bit; the low set L sits at bits 0..c-1
+  const uint64_t home = reg_only ? 0 : ((1ull << c) - 1);
+  uint64_t L = home;
+  std::vector<int> pos, pos_next;
+  layout_of(L, nbits, pos);
+  auto finish_pass = [&](PassH &ph, uint64_t tile, const std::vector<int> &rest) {
+    // tile-local bits in ascending input position; output layout
+    std::vector<int> qs;
+    for (int b = 0; b < nbits; b++)
+      if ((tile >> b) & 1) qs.push_back(b);
+    std::sort(qs.begin(), qs.end(), [&](int x, int y) { return pos[x] < pos[y]; });
+    uint64_t Ln = L;
+    if (P.remap) {
+      if (rest.empty()) Ln = ((home & ~tile) == 0) ? home : L;
+      else Ln = choose_low(E, rest, tile, c, TK);
+    }
+    layout_of(Ln, nbits, pos_next);
+    ph.lq = qs;
+    ph.tq.clear();
+    ph.tq_out.clear();
+    for (int q : qs) {
+      ph.tq.push_back(pos[q]);
+      ph.tq_out.push_back(pos_next[q]);
+    }
+    ph.moves = pos_next != pos;
+    pos = pos_next;
+    L = Ln;
+  };
   while (!rem.empty()) {
-    uint64_t tile = reg_only ? 0 : ((1ull << c) - 1);
+    uint64_t tile = reg_only ? 0 : L;
     uint64_t blocked = 0;
     int nvar = 0;
     std::vector<int> chosen, left;
@@ -295,10 +399,9 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
     for (int b = 0; b < nbits && popc(tile) < TK; b++) tile |= 1ull << b;
     PassH ph;
     ph.K = TK;
-    for (int b = 0; b < nbits; b++)
-      if ((tile >> b) & 1) ph.tq.push_back(b);
+    finish_pass(ph, tile, rem);
     int loc[64];
-    for (int i = 0; i < (int)ph.tq.size(); i++) loc[ph.tq[i]] = i;
+    for (int i = 0; i < (int)ph.lq.size(); i++) loc[ph.lq[i]] = i;
     // stages over tile-local bits: plain first fit, and a variant whose first
     // stage defers ops on the low c bits so it can read HBM directly; keep
     // the one with fewer LDS round trips
@@ -384,6 +487,39 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
     }
     P.passes.push_back(ph);
   }
+  if (!P.remap) return;
+  auto empty_pass = [&]() {
+    // a pass without ops whose tile holds the low set and the home low bits
+    uint64_t tile = L | home;
+    for (int b = 0; b < nbits && popc(tile) < TK; b++) tile |= 1ull << b;
+    PassH ph;
+    ph.K = TK;
+    const std::vector<int> none;
+    finish_pass(ph, tile, none);
+    P.passes.push_back(ph);
+  };
+  if (L != home) empty_pass();  // bring the layout back to the identity
+  // A pass that changes the layout reads one buffer and writes the other;
+  // the others may run in place.  The last pass must leave the state in
+  // the caller's buffer, so the number of buffer switches must be even.
+  int moving = 0;
+  for (const PassH &ph : P.passes) moving += ph.moves;
+  if (moving & 1) {
+    bool fixed = false;
+    for (PassH &ph : P.passes)
+      if (!ph.moves) { ph.moves = true; fixed = true; break; }  // run one in-place pass out of place
+    if (!fixed) {
+      empty_pass();
+      P.passes.back().moves = true;
+    }
+  }
+  int cur = 0;
+  for (PassH &ph : P.passes) {
+    ph.src = cur;
+    ph.dst = ph.moves ? 1 - cur : cur;
+    cur = ph.dst;
+    P.needs_scratch |= ph.moves;
+  }
 }
 
 }  // namespace
@@ -416,6 +552,8 @@ struct vqc_circuit_s {
   std::vector<int> gslot_param;
   bool has_nonunitary_matrix = false;
   Plan fwd, adj;   // pure: LDS forward + LDS adjoint; mixed: register-only, shared
+  Plan fwd_nr;     // forward plan without qubit moves (batches), when fwd moves qubits
+  DevBuf scratch;  // second state buffer for forward passes that move qubits
   DevBuf dconst;   // recipes, constant data, csr
   DRecipe *d_rec = nullptr;
   c128 *d_cdata = nullptr;
@@ -618,7 +756,7 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
   for (size_t p = 0; p < P.passes.size(); p++) {
     const PassH &ph = P.passes[p];
     int loc[64];
-    for (int i = 0; i < (int)ph.tq.size(); i++) loc[ph.tq[i]] = i;
+    for (int i = 0; i < (int)ph.lq.size(); i++) loc[ph.lq[i]] = i;
     pass_stage0.push_back((int)stages.size());
     pass_deriv0.push_back((int)derivs.size());
     pass_vslot0.push_back((int)vslot.size());
@@ -673,9 +811,19 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
           if (S.rbit[i] < P.c) return false;
         return true;
       };
-      dp.lowfree = (lowfree(ph.stages.front()) ? 1 : 0) | (lowfree(ph.stages.back()) ? 2 : 0);
+      // a pass that changes the layout stores through LDS (the output's low
+      // bits are other tile bits than the input's)
+      dp.lowfree = (lowfree(ph.stages.front()) ? 1 : 0) | ((lowfree(ph.stages.back()) && !ph.moves) ? 2 : 0);
     }
     for (int i = 0; i < ph.K; i++) dp.tq[i] = (int8_t)ph.tq[i];
+    // output order: tile-local bits by ascending output position
+    std::vector<int> ord(ph.K);
+    for (int i = 0; i < ph.K; i++) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int x, int y) { return ph.tq_out[x] < ph.tq_out[y]; });
+    for (int i = 0; i < ph.K; i++) {
+      dp.lbo[i] = (int8_t)ord[i];
+      dp.tqo[i] = (int8_t)ph.tq_out[ord[i]];
+    }
   }
   P.n_stages = (int)stages.size();
   // one device blob: passes | jobs | stages | gates | derivs | vslot
@@ -747,25 +895,40 @@ vqc_status make_plans(vqc_circuit c) {
     plan_passes(c->elems, nb, R, 0, R, true, c->adj, kMaxVarPerPass);
     st = upload_plan(c, c->adj, true);
     if (st) return st;
+    reset_plan(c->fwd_nr);
+    c->fwd_nr.prog = c->adj.prog + (c->adj.n_gates + 2) * kOpSlots;
   } else {
     const int kmin = R == 3 ? 8 : 5;
     if (nb < kmin) { R = Radj = 4; }
     K = std::max(R == 3 ? 8 : 5, std::min(K, nb));
-    low = std::min(low, K - 1);
+    // the low block plus any two-qubit op must fit in a tile
+    low = std::min(low, K - 2);
     int Ka = std::max(Radj == 3 ? 8 : 5, std::min(std::min(K, kDefaultAdjTile), nb));
-    plan_passes(c->elems, nb, K, low, R, false, c->fwd, 0);
+    const bool remap = c->tune.remap > 0 || (c->tune.remap == 0 && nb >= kRemapMinBits);
+    plan_passes(c->elems, nb, K, low, R, false, c->fwd, 0, remap);
     vqc_status st = upload_plan(c, c->fwd, false);
     if (st) return st;
     c->adj.prog = c->fwd.prog + (c->fwd.n_gates + 2) * kOpSlots;
-    plan_passes(c->elems, nb, Ka, std::min(low, Ka - 1), Radj, false, c->adj, kMaxVarPerPass);
+    plan_passes(c->elems, nb, Ka, std::min(low, Ka - 2), Radj, false, c->adj, kMaxVarPerPass);
     st = upload_plan(c, c->adj, true);
     if (st) return st;
+    reset_plan(c->fwd_nr);
+    c->fwd_nr.prog = c->adj.prog + (c->adj.n_gates + 2) * kOpSlots;
+    if (c->fwd.remap) {
+      plan_passes(c->elems, nb, K, low, R, false, c->fwd_nr, 0, false);
+      st = upload_plan(c, c->fwd_nr, false);
+      if (st) return st;
+    }
   }
-  c->mat_total = c->adj.prog + (c->adj.n_gates + 2) * kOpSlots;
+  c->mat_total = c->fwd_nr.prog + (c->fwd_nr.n_gates + 2) * kOpSlots;
   if (c->mats1.ensure((size_t)c->mat_total * sizeof(c128)) != hipSuccess) return VQC_ERR_HIP;
+  if (c->fwd.needs_scratch &&
+      c->scratch.ensure((size_t(1) << nb) * sizeof(c128)) != hipSuccess)
+    return VQC_ERR_OOM;
   c->tune.tile_bits = c->fwd.K;
   c->tune.low_bits = c->fwd.c;
   c->tune.reg_bits = c->fwd.R;
+  if (c->tune.remap == 0) c->tune.remap = c->fwd.remap ? 1 : -1;
   return VQC_OK;
 }
 
@@ -829,6 +992,10 @@ int grid_of(vqc_circuit c, int64_t units) {
   return (int)std::min<int64_t>(units, int64_t(1) << 30);
 }
 
+// forward plan of batched launches: the batch job tables run every pass in
+// place, so a circuit whose forward plan moves qubits uses its plain plan
+Plan &bplan(vqc_circuit c) { return c->fwd.remap ? c->fwd_nr : c->fwd; }
+
 // matrices, rotation records and the op programs of both plans for B items
 // (thetas / mats per item) or one item (theta0 / mats0)
 hipError_t build_mats(vqc_circuit c, const double *const *thetas, c128 *const *mats, int B, const double *theta0,
@@ -837,6 +1004,11 @@ hipError_t build_mats(vqc_circuit c, const double *const *thetas, c128 *const *m
   if (e != hipSuccess) return e;
   e = launch_assemble(c->fwd.d_gates, c->fwd.d_derivs, c->fwd.n_gates, c->fwd.prog, mats, B, mats0, st);
   if (e != hipSuccess) return e;
+  if (c->fwd.remap) {
+    e = launch_assemble(c->fwd_nr.d_gates, c->fwd_nr.d_derivs, c->fwd_nr.n_gates, c->fwd_nr.prog, mats, B, mats0,
+                        st);
+    if (e != hipSuccess) return e;
+  }
   return launch_assemble(c->adj.d_gates, c->adj.d_derivs, c->adj.n_gates, c->adj.prog, mats, B, mats0, st);
 }
 
@@ -852,8 +1024,18 @@ hipError_t run_passes(vqc_circuit c, Plan &P, int mode, c128 *a, c128 *b, const 
   ov.mode = (mode == 0 && b) ? 1 : 0;
   ov.use = 1;
   const int grid = grid_of(c, P.units_per_item);
+  // forward passes that move qubits alternate between the state and the
+  // circuit's scratch state (the plan ends in the state)
+  const bool pingpong = mode == 0 && !b && P.needs_scratch;
+  c128 *bufs[2] = {a, c->scratch.as<c128>()};
   for (int k = 0; k < p1 - p0; k++) {
     const int p = dir > 0 ? p0 + k : p1 - 1 - k;
+    if (pingpong) {
+      const PassH &ph = P.passes[p];
+      ov.a = bufs[ph.src];
+      ov.b = bufs[ph.dst];
+      ov.mode = ph.src != ph.dst ? 1 : 0;
+    }
     hipError_t e;
     if (P.reg_only) e = launch_pass_reg(P.R, mode, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
     else e = launch_pass_lds(P.K, P.R, mode != 0, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
@@ -1201,7 +1383,8 @@ vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops,
   if (kind != VQC_PURE && kind != VQC_MIXED) return VQC_ERR_ARG;
   if (n < 1 || (kind == VQC_PURE && n > 33) || (kind == VQC_MIXED && n > 16)) return VQC_ERR_ARG;
   if (tune && (tune->tile_bits < 0 || tune->tile_bits > kMaxTile || tune->low_bits < 0 || tune->grid_blocks < 0 ||
-               (tune->reg_bits != 0 && tune->reg_bits != 3 && tune->reg_bits != 4)))
+               (tune->reg_bits != 0 && tune->reg_bits != 3 && tune->reg_bits != 4) || tune->remap < -1 ||
+               tune->remap > 1))
     return VQC_ERR_ARG;
   for (int j = 0; j < n_ops; j++) {
     vqc_status st = validate_op(ops[j], n, kind, n_params);
@@ -1476,7 +1659,7 @@ static vqc_status batch_build_tables(vqc_batch b) {
     if (c->kind == VQC_PURE) qtot += al(std::max(1, c->n_gslots) * c->adj.units_per_item * sizeof(double));
     e_off[i] = etot;
     etot += expect_units(c->n);
-    b->max_passes = std::max(b->max_passes, (int)c->fwd.passes.size());
+    b->max_passes = std::max(b->max_passes, (int)bplan(c).passes.size());
     b->max_adj = std::max(b->max_adj, (int)c->adj.passes.size());
     b->max_params = std::max(b->max_params, c->n_params);
   }
@@ -1512,14 +1695,14 @@ static vqc_status batch_build_tables(vqc_batch b) {
     int64_t u0 = 0;
     for (int i = 0; i < B; i++) {
       vqc_circuit c = b->circ[i];
-      if (sI >= (int)c->fwd.passes.size()) continue;
+      if (sI >= (int)bplan(c).passes.size()) continue;
       DJob j;
       std::memset(&j, 0, sizeof(j));
       j.a = b->states[i];
       j.mats = reinterpret_cast<const c128 *>(b->mats.as<char>() + b->mat_off[i]);
-      j.pass = c->fwd.d_pass + sI;
+      j.pass = bplan(c).d_pass + sI;
       j.unit0 = u0;
-      j.n_units = c->fwd.units_per_item;
+      j.n_units = bplan(c).units_per_item;
       j.nbits = c->nbits;
       u0 += j.n_units;
       fj.push_back(j);
@@ -1615,8 +1798,8 @@ static vqc_status batch_forward_on(vqc_batch b, hipStream_t st) {
     const int64_t units = b->fwd_units[sI];
     const int grid = grid_of(c0, units);
     const DJob *jobs = b->d_fwd_jobs + b->fwd_first[sI];
-    if (b->reg_only) VQC_TRY(launch_pass_reg(c0->fwd.R, 0, jobs, b->fwd_count[sI], units, grid, ov, st));
-    else VQC_TRY(launch_pass_lds(c0->fwd.K, c0->fwd.R, false, jobs, b->fwd_count[sI], units, grid, ov, st));
+    if (b->reg_only) VQC_TRY(launch_pass_reg(bplan(c0).R, 0, jobs, b->fwd_count[sI], units, grid, ov, st));
+    else VQC_TRY(launch_pass_lds(bplan(c0).K, bplan(c0).R, false, jobs, b->fwd_count[sI], units, grid, ov, st));
   }
   return VQC_OK;
 }
@@ -1707,7 +1890,7 @@ vqc_status vqc_batch_create(vqc_batch *out, int B, const vqc_circuit *circuits, 
     if (circuits[i]->n_params > 0 && (!thetas || !thetas[i])) return VQC_ERR_ARG;
     const vqc_circuit c = circuits[i], c0 = circuits[0];
     if (c->kind != c0->kind) return VQC_ERR_KIND;
-    if (c->fwd.reg_only != c0->fwd.reg_only || c->fwd.K != c0->fwd.K || c->fwd.R != c0->fwd.R ||
+    if (bplan(c).reg_only != bplan(c0).reg_only || bplan(c).K != bplan(c0).K || bplan(c).R != bplan(c0).R ||
         c->adj.K != c0->adj.K || c->adj.R != c0->adj.R || c->adj.reg_only != c0->adj.reg_only)
       return VQC_ERR_UNSUPPORTED;
   }
@@ -1720,8 +1903,8 @@ vqc_status vqc_batch_create(vqc_batch *out, int B, const vqc_circuit *circuits, 
     b->thetas.push_back(thetas ? thetas[i] : nullptr);
   }
   b->stream = reinterpret_cast<hipStream_t>(stream);
-  b->reg_only = circuits[0]->fwd.reg_only;
-  b->K = circuits[0]->fwd.K;
+  b->reg_only = bplan(circuits[0]).reg_only;
+  b->K = bplan(circuits[0]).K;
   b->Kadj = circuits[0]->adj.K;
   vqc_status st = batch_build_tables(b.get());
   if (st) return st;

@@ -985,16 +985,32 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
       }
     }
     if (!dout) {
-      // LDS -> HBM
+      // LDS -> HBM in the pass's output layout (the input layout unless the
+      // pass moves qubits): lanes run over the output's lowest tile bits
+      uint64_t gbo = (uint64_t)tile;
+#pragma unroll
+      for (int i = 0; i < K; i++) gbo = ins0<uint64_t>(gbo, P->tqo[i]);
+      uint64_t so = 0;
+      int sl = 0;
+#pragma unroll
+      for (int i = 0; i < K - R; i++)
+        if ((t >> i) & 1) {
+          so |= 1ull << P->tqo[i];
+          sl |= 1 << P->lbo[i];
+        }
 #pragma unroll
       for (int j = 0; j < NR; j++) {
         uint64_t oj = 0;
+        int ol = 0;
 #pragma unroll
         for (int i = 0; i < R; i++)
-          if ((j >> i) & 1) oj |= 1ull << P->tq[K - R + i];
-        const uint64_t gi = gbase | st | oj;
-        stg(&dst[gi], la[swz(j * T + t)]);
-        if constexpr (ADJ) stg(&Bv[gi], lb[swz(j * T + t)]);
+          if ((j >> i) & 1) {
+            oj |= 1ull << P->tqo[K - R + i];
+            ol |= 1 << P->lbo[K - R + i];
+          }
+        const uint64_t gi = gbo | so | oj;
+        stg(&dst[gi], la[swz(sl | ol)]);
+        if constexpr (ADJ) stg(&Bv[gi], lb[swz(sl | ol)]);
       }
     }
     if constexpr (ADJ) {

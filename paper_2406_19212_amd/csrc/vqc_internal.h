@@ -105,7 +105,9 @@ struct DPass {
   int32_t nvar;     // derivative slots reduced in this pass
   int32_t lowfree;  // bit 0: stage 0 holds none of the low c bits; bit 1: the last stage
                     // holds none (that stage can then load/store HBM directly, coalesced)
-  int8_t tq[16];    // global qubit of tile-local bit i, ascending
+  int8_t tq[16];    // physical bit (input layout) of tile-local bit i, ascending
+  int8_t tqo[16];   // output layout: physical bits of the tile, ascending ...
+  int8_t lbo[16];   // ... and the tile-local bit stored at each (identity when the layout stays)
   int32_t prog;     // c128 offset of the plan's op program in the item's matrix buffer
   int32_t pad;
   const DStage *stages;   // absolute device pointers

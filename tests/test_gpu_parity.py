@@ -361,3 +361,36 @@ def test_rotation_kinds_at_edge_angles_mixed():
     st = State(n, mixed=True, init=v)
     Circuit(n, ops, mixed=True).apply(st)
     assert maxdiff(st.numpy(), oracle.run(n, ops, mixed=True, init=v)) < AMP_TOL
+
+
+@pytest.mark.parametrize("rows,cols,cycles,tile,low", [(3, 4, 14, 7, 3), (4, 4, 10, 8, 4), (3, 5, 12, 9, 2)])
+def test_forward_with_qubit_moves(rows, cols, cycles, tile, low):
+    """Forward plans that move qubits into the contiguous low block between
+    passes (ping-pong through the circuit's second buffer) agree with the
+    oracle and end in the standard layout."""
+    n = rows * cols
+    ops = W.rqc_grid(rows, cols, cycles, 41 + n)
+    ref = oracle.run(n, ops)
+    c = Circuit(n, ops, tune={"tile_bits": tile, "low_bits": low, "remap": 1})
+    assert c.stats()["remap"] == 1
+    c0 = Circuit(n, ops, tune={"tile_bits": tile, "low_bits": low, "remap": -1})
+    print("passes with moves %d, without %d" % (c.stats()["n_passes"], c0.stats()["n_passes"]))
+    psi0 = W.random_state(n, 5 + n)
+    st = State(n, init=psi0)
+    c.apply(st)
+    assert maxdiff(st.numpy(), oracle.run(n, ops, init=psi0)) < AMP_TOL
+    st = State(n)
+    ms = c.apply_timed(st)
+    assert len(ms) == c.stats()["n_passes"]
+    assert maxdiff(st.numpy(), ref) < AMP_TOL
+    # parametrised circuit with moves: forward and the adjoint gradient
+    ops2 = W.hea(n, 3)
+    th = W.theta_uniform(9, 1, W.count_params(ops2))[0]
+    c2 = Circuit(n, ops2, tune={"tile_bits": tile, "low_bits": low, "remap": 1})
+    st2 = State(n)
+    tht = torch.tensor(th, device="cuda")
+    c2.apply(st2, tht)
+    assert maxdiff(st2.numpy(), oracle.run(n, ops2, th)) < AMP_TOL
+    g, e = c2.backward(tht, st2, W.tfim(n))
+    e_ref, g_ref, _ = oracle.grad_pure(n, ops2, th, W.tfim(n))
+    assert maxdiff(g.cpu().numpy(), g_ref) < GRAD_TOL
