@@ -1502,8 +1502,10 @@ static vqc_status seed_and_energy(vqc_circuit c, const std::vector<DTerm> &terms
   return VQC_OK;
 }
 
-vqc_status vqc_backward(vqc_circuit c, const double *theta, vqc_state s, const vqc_pauli_sum *H, double *grad,
-                        double *energy_host, const void *init_dev, size_t budget) {
+// energy_dev: optional device destination of the energy (stream-ordered)
+static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s, const vqc_pauli_sum *H,
+                                double *grad, double *energy_host, double *energy_dev, const void *init_dev,
+                                size_t budget) {
   if (!c || !s || !H) return VQC_ERR_ARG;
   if (s->kind != c->kind || s->n != c->n) return VQC_ERR_KIND;
   if (c->n_params > 0 && (!theta || !grad)) return VQC_ERR_ARG;
@@ -1586,6 +1588,7 @@ vqc_status vqc_backward(vqc_circuit c, const double *theta, vqc_state s, const v
     VQC_TRY(hipStreamSynchronize(st));
     VQC_TRY(launch_grad_reduce(dg, 1, c->n_params, st));
   }
+  if (energy_dev) VQC_TRY(launch_take_real(dres, 1, energy_dev, st));
   if (energy_host) {
     double2 r;
     VQC_TRY(hipMemcpyAsync(&r, dres, sizeof(r), hipMemcpyDeviceToHost, st));
@@ -1593,6 +1596,11 @@ vqc_status vqc_backward(vqc_circuit c, const double *theta, vqc_state s, const v
     *energy_host = r.x;
   }
   return VQC_OK;
+}
+
+vqc_status vqc_backward(vqc_circuit c, const double *theta, vqc_state s, const vqc_pauli_sum *H, double *grad,
+                        double *energy_host, const void *init_dev, size_t budget) {
+  return backward_impl(c, theta, s, H, grad, energy_host, nullptr, init_dev, budget);
 }
 
 vqc_status vqc_circuit_autotune(vqc_circuit c, vqc_state s, const double *theta, vqc_tune *out) {
@@ -1954,20 +1962,19 @@ vqc_status vqc_batch_backward(vqc_batch b, const vqc_pauli_sum *H, double *const
     if (st) return st;
     return batch_backward_pure_on(b, energies, b->stream);
   }
-  // mixed items: checkpointed backward item by item on the batch stream
+  // mixed items: checkpointed backward item by item on the batch stream (the
+  // sweep recomputes the forward from |0><0| itself; the items' states are
+  // only read for their shape)
   for (int i = 0; i < b->B; i++) {
-    vqc_state s = nullptr;
-    vqc_status st = vqc_state_init(&s, VQC_MIXED, b->circ[i]->n, b->states[i], nullptr, b->stream);
-    (void)st;
-    // vqc_state_init wrote |0><0|: re-run the forward of this item
-    if (s == nullptr) return VQC_ERR_OOM;
-    st = vqc_apply_circuit(s, b->circ[i], b->thetas[i]);
-    double e = 0;
-    if (!st) st = vqc_backward(b->circ[i], b->thetas[i], s, H, grads[i], energies ? &e : nullptr, nullptr, budget);
-    vqc_state_destroy(s);
+    vqc_state_s it;
+    it.kind = VQC_MIXED;
+    it.n = b->circ[i]->n;
+    it.nbits = 2 * it.n;
+    it.buf = b->states[i];
+    it.stream = b->stream;
+    vqc_status st = backward_impl(b->circ[i], b->thetas[i], &it, H, grads[i], nullptr,
+                                  energies ? energies + i : nullptr, nullptr, budget);
     if (st) return st;
-    if (energies) VQC_TRY(hipMemcpyAsync(energies + i, &e, sizeof(double), hipMemcpyHostToDevice, b->stream));
-    VQC_TRY(hipStreamSynchronize(b->stream));
   }
   return VQC_OK;
 }
