@@ -545,6 +545,7 @@ struct vqc_circuit_s {
   std::vector<vqc_op> ops;
   std::vector<c128> cdata;
   std::vector<DRecipe> recipes;
+  std::vector<DRecipe> subrec;  // one-qubit ops of fused runs (not built on their own)
   int mat_size = 0;   // recipe outputs
   int mat_total = 0;  // recipe outputs + op programs of both plans (c128 per item)
   std::vector<Elem> elems;
@@ -642,38 +643,94 @@ int add_gate_recipe(vqc_circuit c, int gk, int type, int form, int nq, const vqc
   return add_recipe(c, type, form, 0, nq, op, data_off, n_data, d * d);
 }
 
+// a recipe for op `op` as a 4x4 superoperator of a fused run
+DRecipe sub_recipe(const vqc_op &op, int data_off, int n_data) {
+  DRecipe r;
+  std::memset(&r, 0, sizeof(r));
+  r.type = op.type;
+  r.form = is_channel(op.type) ? RF_SUPER_KRAUS : RF_SUPER_GATE;
+  r.nq = 1;
+  r.data = data_off;
+  r.n_data = n_data;
+  for (int i = 0; i < 5; i++) {
+    r.pidx[i] = op.param_index[i];
+    r.pval[i] = op.params[i];
+  }
+  return r;
+}
+
 vqc_status lower(vqc_circuit c) {
   const int n = c->n;
   const bool mixed = c->kind == VQC_MIXED;
   int n_factored = 0;
+  // constant data of every op (row-major)
+  std::vector<int> doff(c->ops.size(), -1), ndat(c->ops.size(), 0);
   for (size_t j = 0; j < c->ops.size(); j++) {
     const vqc_op &op = c->ops[j];
     const int m = op.n_qubits, d = 1 << m;
-    int data_off = -1, n_data = 0;
     if (op.data && op.n_data > 0) {
-      data_off = (int)c->cdata.size();
+      doff[j] = (int)c->cdata.size();
       if (op.type == VQC_CONTROL) {
         to_row_major(op.data, 2, c->cdata);  // the 2x2 target block
       } else {
         const int blocks = op.n_data / (d * d);
         for (int s = 0; s < blocks; s++) to_row_major(op.data + (size_t)s * d * d, d, c->cdata);
       }
-      n_data = op.n_data;
+      ndat[j] = op.n_data;
     }
+    if (op.type == VQC_MATRIX && !unitary_rm(c->cdata.data() + doff[j], d)) c->has_nonunitary_matrix = true;
+  }
+  auto slot_for = [&](int param) {
+    Deriv dv;
+    dv.param = param;
+    dv.gslot = c->n_gslots++;
+    c->gslot_param.push_back(param);
+    return dv;
+  };
+  for (size_t j = 0; j < c->ops.size(); j++) {
+    const vqc_op &op = c->ops[j];
+    const int m = op.n_qubits, d = 1 << m;
+    const int data_off = doff[j], n_data = ndat[j];
     bool var = false;
     for (int k = 0; k < 5; k++) var |= op.param_index[k] >= 0;
-    if (op.type == VQC_MATRIX) {
-      if (!unitary_rm(c->cdata.data() + data_off, d)) c->has_nonunitary_matrix = true;
-    }
     auto new_deriv = [&](int kind, int mat, int k) {
-      Deriv dv;
+      Deriv dv = slot_for(op.param_index[k]);
       dv.kind = kind;
       dv.mat = mat;
-      dv.param = op.param_index[k];
-      dv.gslot = c->n_gslots++;
-      c->gslot_param.push_back(dv.param);
       return dv;
     };
+    if (mixed && m == 1) {
+      // a run of one-qubit ops (gates and channels) on this qubit becomes one
+      // 4x4 superoperator: S_{m-1} ... S_0, with one derivative per parameter
+      size_t j2 = j + 1;
+      while (j2 < c->ops.size() && c->ops[j2].n_qubits == 1 && c->ops[j2].qubits[0] == op.qubits[0]) j2++;
+      if (j2 - j >= 2) {
+        const int first = (int)c->subrec.size();
+        for (size_t t = j; t < j2; t++) c->subrec.push_back(sub_recipe(c->ops[t], doff[t], ndat[t]));
+        vqc_op none;
+        std::memset(&none, 0, sizeof(none));
+        for (int k = 0; k < 5; k++) none.param_index[k] = -1;
+        Elem e;
+        e.nq = 2;
+        e.kind = GK_DENSE2;
+        e.q[0] = op.qubits[0];
+        e.q[1] = op.qubits[0] + n;
+        e.mat = add_recipe(c, VQC_ID, RF_FUSED, 0, 1, none, first, (int)(j2 - j), 16);
+        for (size_t t = j; t < j2; t++)
+          for (int k = 0; k < 5; k++)
+            if (c->ops[t].param_index[k] >= 0) {
+              const int mat = add_recipe(c, VQC_ID, RF_DFUSED, (int)(t - j) * 8 + k, 1, none, first,
+                                         (int)(j2 - j), 16);
+              Deriv dv = slot_for(c->ops[t].param_index[k]);
+              dv.kind = GK_DENSE2;
+              dv.mat = mat;
+              e.d.push_back(dv);
+            }
+        c->elems.push_back(e);
+        j = j2 - 1;
+        continue;
+      }
+    }
     if (is_channel(op.type)) {
       Elem e;
       e.nq = 2 * m;
@@ -941,14 +998,19 @@ vqc_status upload_const(vqc_circuit c) {
     ptr[p + 1] = ptr[p] + (int)per[p].size();
     for (int s : per[p]) slot.push_back(s);
   }
+  // fused runs refer to their sub-recipes, stored after the built recipes
+  std::vector<DRecipe> rec = c->recipes;
+  for (DRecipe &r : rec)
+    if (r.form == RF_FUSED || r.form == RF_DFUSED) r.data += (int)c->recipes.size();
+  rec.insert(rec.end(), c->subrec.begin(), c->subrec.end());
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t o_r = 0, o_c = al(c->recipes.size() * sizeof(DRecipe));
+  const size_t o_r = 0, o_c = al(rec.size() * sizeof(DRecipe));
   const size_t o_p = al(o_c + c->cdata.size() * sizeof(c128));
   const size_t o_s = al(o_p + ptr.size() * sizeof(int32_t));
   const size_t total = al(o_s + slot.size() * sizeof(int32_t));
   VQC_TRY(c->dconst.ensure(total));
   std::vector<char> blob(total, 0);
-  std::memcpy(blob.data() + o_r, c->recipes.data(), c->recipes.size() * sizeof(DRecipe));
+  std::memcpy(blob.data() + o_r, rec.data(), rec.size() * sizeof(DRecipe));
   std::memcpy(blob.data() + o_c, c->cdata.data(), c->cdata.size() * sizeof(c128));
   std::memcpy(blob.data() + o_p, ptr.data(), ptr.size() * sizeof(int32_t));
   std::memcpy(blob.data() + o_s, slot.data(), slot.size() * sizeof(int32_t));

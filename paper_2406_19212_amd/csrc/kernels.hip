@@ -202,10 +202,54 @@ __device__ void derive_srec(int kind, const c128 *M, c128 *out) {
   *reinterpret_cast<SRec *>(out) = r;  // kSRecSlots c128 slots, 16 B aligned
 }
 
-__device__ void build_recipe(const DRecipe &R, const c128 *__restrict__ cdata, const double *th, c128 *out_base) {
+__device__ void build_plain(const DRecipe &R, const c128 *__restrict__ cdata, const double *th, c128 *out);
+__device__ void build_fused(const DRecipe &R, const DRecipe *__restrict__ all, const c128 *__restrict__ cdata,
+                            const double *th, c128 *out);
+
+__device__ void build_into(const DRecipe &R, const DRecipe *__restrict__ all, const c128 *__restrict__ cdata,
+                           const double *th, c128 *out) {
+  if (R.form == RF_FUSED || R.form == RF_DFUSED) build_fused(R, all, cdata, th, out);
+  else build_plain(R, cdata, th, out);
+}
+
+// the recipe's matrix at its output offset, then its shear record
+__device__ void build_recipe(const DRecipe &R, const DRecipe *__restrict__ all, const c128 *__restrict__ cdata,
+                             const double *th, c128 *out_base) {
+  c128 *out = out_base + R.out;
+  build_into(R, all, cdata, th, out);
+  if (R.shear) {
+    const int d = R.nq == 2 ? 4 : 2;
+    derive_srec(R.shear, out, out + d * d);
+  }
+}
+
+// 4x4 superoperator product of a fused run (RF_FUSED / RF_DFUSED)
+__device__ void build_fused(const DRecipe &R, const DRecipe *__restrict__ all, const c128 *__restrict__ cdata,
+                            const double *th, c128 *out) {
+  c128 M[16], S[16], T[16];
+  for (int i = 0; i < 16; i++) M[i] = C((i % 5) == 0 ? 1.0 : 0.0, 0.0);
+  const int ds = R.form == RF_DFUSED ? R.k >> 3 : -1;
+  for (int s = 0; s < R.n_data; s++) {
+    DRecipe sub = all[R.data + s];
+    if (s == ds) {
+      sub.form = RF_DSUPER_GATE;
+      sub.k = R.k & 7;
+    }
+    build_plain(sub, cdata, th, S);
+    for (int r = 0; r < 4; r++)
+      for (int c = 0; c < 4; c++) {
+        c128 acc = C(0, 0);
+        for (int k = 0; k < 4; k++) acc = cfma(S[r * 4 + k], M[k * 4 + c], acc);
+        T[r * 4 + c] = acc;
+      }
+    for (int i = 0; i < 16; i++) M[i] = T[i];
+  }
+  for (int i = 0; i < 16; i++) out[i] = M[i];
+}
+
+__device__ void build_plain(const DRecipe &R, const c128 *__restrict__ cdata, const double *th, c128 *out) {
   double p[5];
   for (int k = 0; k < 5; k++) p[k] = (R.pidx[k] >= 0 && th) ? th[R.pidx[k]] : R.pval[k];
-  c128 *out = out_base + R.out;
   const c128 *data = R.data >= 0 ? cdata + R.data : nullptr;
   c128 G[16], dG[16];
   switch (R.form) {
@@ -262,10 +306,7 @@ __device__ void build_recipe(const DRecipe &R, const c128 *__restrict__ cdata, c
             }
       break;
     }
-  }
-  if (R.shear) {
-    const int d = R.nq == 2 ? 4 : 2;
-    derive_srec(R.shear, out, out + d * d);
+    default: break;
   }
 }
 
@@ -275,7 +316,7 @@ __global__ void k_build_mats(const DRecipe *__restrict__ rec, int n_rec, const c
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
   if (i >= n_rec || b >= B) return;
-  build_recipe(rec[i], cdata, thetas ? thetas[b] : theta0, mats ? mats[b] : mats0);
+  build_recipe(rec[i], rec, cdata, thetas ? thetas[b] : theta0, mats ? mats[b] : mats0);
 }
 
 // op program of a plan for each item: entry i + 1 is op i with its rotation
@@ -312,7 +353,7 @@ __global__ void k_assemble(const DGate *__restrict__ gates, const DDeriv *__rest
 }
 
 __global__ void k_build_one(DRecipe r, const c128 *__restrict__ cdata, c128 *out) {
-  if (threadIdx.x == 0) build_recipe(r, cdata, nullptr, out);
+  if (threadIdx.x == 0) build_recipe(r, nullptr, cdata, nullptr, out);
 }
 
 // -------------------------------------------------- expectation and seeds

@@ -150,7 +150,11 @@ enum RecipeForm : int32_t {
   RF_DSUPER_GATE = 5, // conj(dU) (x) U + conj(U) (x) dU
   RF_SUPER_KRAUS = 6,  // sum_s conj(K_s) (x) K_s
   RF_GATE_F = 7,       // gate matrix with the global phase e^{i pi/4} of sqrt(X/Y/W) removed
-  RF_GPHASE = 8        // diag(w, w), w = e^{i pi k / 4}
+  RF_GPHASE = 8,       // diag(w, w), w = e^{i pi k / 4}
+  // product S_{m-1} ... S_0 of the 4x4 superoperators of a run of one-qubit
+  // ops (data = index of S_0's recipe in the recipe array, n_data = m)
+  RF_FUSED = 9,
+  RF_DFUSED = 10       // the same with S_s replaced by its derivative: k = s * 8 + parameter
 };
 
 struct DRecipe {
