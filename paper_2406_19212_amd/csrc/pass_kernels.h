@@ -619,12 +619,6 @@ __device__ __forceinline__ void tied_set(double &d, double s) { asm("v_mov_b64 %
 // works on a copy whose results are moved back with register-tied moves, so
 // no dispatch arm leaves a value in another register (which would make the
 // register allocator copy all amplitudes after every op).
-// record of op g for the rotation kinds; for other kinds the first 64 B of
-// the matrix (or of the buffer, for ops without one), unused but in bounds
-__device__ __forceinline__ const SRec *srec_at(cmat *mats, const DGate &g) {
-  return (const SRec *)(mats + (g.mat > 0 ? g.mat : 0));
-}
-
 template <int R, bool ADJ, bool D4 = true>
 __device__ __forceinline__ void rg_apply_pre(c128 (&a)[1 << R], const DGate &g, const SRec &rec, cmat *mats) {
   constexpr int NR = 1 << R;
@@ -647,10 +641,6 @@ __device__ __forceinline__ void rg_apply_pre(c128 (&a)[1 << R], const DGate &g, 
   }
 }
 
-template <int R, bool ADJ, bool D4 = true>
-__device__ __forceinline__ void rg_apply(c128 (&a)[1 << R], const DGate &g, cmat *mats) {
-  rg_apply_pre<R, ADJ, D4>(a, g, ldc(srec_at(mats, g)), mats);
-}
 
 // one op from its program entry
 template <int R, bool ADJ, bool D4 = true>
