@@ -805,9 +805,11 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
 
-  // forward passes run persistent blocks that prefetch the next tile into
-  // registers while the current tile is in its register stages, so HBM
-  // traffic overlaps the FP64 work
+  // The forward loads its tile into registers first.  With a persistent grid
+  // (a grid size below the tile count, vqc_tune.grid_blocks) each block also
+  // prefetches its next tile during the current tile's stages; by default the
+  // grid has one block per tile and the hardware overlaps the blocks' memory
+  // and FP64 phases (measured faster than persistent prefetching).
   [[maybe_unused]] c128 pf[NR];
   [[maybe_unused]] bool have_pf = false;
   auto tile_addr = [&](int64_t uu, const DJob &JJ, const DPass &PQ, uint64_t &gb0, uint64_t &st0) {
