@@ -115,10 +115,11 @@ typedef struct {
  * tile includes (c); reg_bits: qubits held per thread (R, 3 or 4);
  * grid_blocks: persistent grid size (0 = one block per tile).  Zero fields
  * take the library default.
- * remap: forward passes may move qubits into the contiguous low block for
- * the next pass (the state ends in the standard layout; the circuit then
- * holds a second state buffer of the same size): 1 on, -1 off, 0 default
- * (on from 22 qubits, pure states). */
+ * remap: passes may move qubits into the contiguous low block for the next
+ * pass (the state ends in the standard layout; the circuit then holds a
+ * second state buffer of the same size, two for the gradient plan, and a
+ * batch one or two per item): 1 on, -1 off, 0 default (on from 12 qubits,
+ * pure states; the gradient plan moves qubits up to 30 qubits). */
 typedef struct {
   int tile_bits;
   int low_bits;
@@ -136,6 +137,9 @@ typedef struct {
   int n_params;
   vqc_tune tune;
   double alg_bytes_per_amp; /* algorithmic HBM bytes per amplitude, unfused ops */
+  int n_adj_passes;   /* HBM passes of the adjoint (gradient) plan */
+  int n_fwd_moves;    /* forward passes that move qubits (run out of place) */
+  int n_adj_moves;    /* adjoint passes that move qubits */
 } vqc_circuit_stats;
 
 /* ------------------------------------------------------------------ misc */

@@ -132,7 +132,8 @@ class Circuit:
         return {"n_ops": s.n_ops, "n_elementary": s.n_elementary, "n_passes": s.n_passes,
                 "n_stages": s.n_stages, "n_var": s.n_var, "n_params": s.n_params,
                 "tile_bits": s.tune.tile_bits, "low_bits": s.tune.low_bits, "reg_bits": s.tune.reg_bits,
-                "grid_blocks": s.tune.grid_blocks, "remap": s.tune.remap, "alg_bytes_per_amp": s.alg_bytes_per_amp}
+                "grid_blocks": s.tune.grid_blocks, "remap": s.tune.remap, "alg_bytes_per_amp": s.alg_bytes_per_amp,
+                "n_adj_passes": s.n_adj_passes, "n_fwd_moves": s.n_fwd_moves, "n_adj_moves": s.n_adj_moves}
 
     def _theta(self, theta):
         if self.n_params == 0:

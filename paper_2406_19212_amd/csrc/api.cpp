@@ -23,9 +23,13 @@ namespace {
 constexpr int kDefaultTile = 11;
 constexpr int kDefaultAdjTile = 11;
 constexpr int kDefaultLow = 4;
-// forward plans of states with at least this many qubits move qubits into
-// the low block between passes (and keep a second state buffer for it)
-constexpr int kRemapMinBits = 22;
+// plans of pure states with at least this many qubits move qubits into the
+// low block between passes (fewer passes; a second state buffer for the
+// forward, Phi and Psi each get one in the adjoint)
+constexpr int kRemapMinBits = 12;
+// the adjoint's moves need four states; above this many qubits its plan keeps
+// the standard layout
+constexpr int kAdjRemapMaxBits = 30;
 constexpr int kR = 4;
 
 #define VQC_TRY(expr)                                         \
@@ -334,8 +338,11 @@ uint64_t choose_low(const std::vector<Elem> &E, const std::vector<int> &rem, uin
   return best;
 }
 
+// adjoint: the passes run in reverse, so a pass that moves qubits reads the
+// layout the forward order leaves and writes the one it found; tile-local bits
+// then follow the adjoint's input layout
 void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, bool reg_only, Plan &P,
-                 int max_var, bool remap = false) {
+                 int max_var, bool remap = false, bool adjoint = false) {
   P.passes.clear();
   P.reg_only = reg_only;
   P.remap = remap && !reg_only && c > 0;
@@ -353,23 +360,24 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
   std::vector<int> pos, pos_next;
   layout_of(L, nbits, pos);
   auto finish_pass = [&](PassH &ph, uint64_t tile, const std::vector<int> &rest) {
-    // tile-local bits in ascending input position; output layout
-    std::vector<int> qs;
-    for (int b = 0; b < nbits; b++)
-      if ((tile >> b) & 1) qs.push_back(b);
-    std::sort(qs.begin(), qs.end(), [&](int x, int y) { return pos[x] < pos[y]; });
     uint64_t Ln = L;
     if (P.remap) {
       if (rest.empty()) Ln = ((home & ~tile) == 0) ? home : L;
       else Ln = choose_low(E, rest, tile, c, TK);
     }
     layout_of(Ln, nbits, pos_next);
+    // tile-local bits in ascending position of the layout the kernel reads
+    const std::vector<int> &pin = adjoint ? pos_next : pos, &pout = adjoint ? pos : pos_next;
+    std::vector<int> qs;
+    for (int b = 0; b < nbits; b++)
+      if ((tile >> b) & 1) qs.push_back(b);
+    std::sort(qs.begin(), qs.end(), [&](int x, int y) { return pin[x] < pin[y]; });
     ph.lq = qs;
     ph.tq.clear();
     ph.tq_out.clear();
     for (int q : qs) {
-      ph.tq.push_back(pos[q]);
-      ph.tq_out.push_back(pos_next[q]);
+      ph.tq.push_back(pin[q]);
+      ph.tq_out.push_back(pout[q]);
     }
     ph.moves = pos_next != pos;
     pos = pos_next;
@@ -553,8 +561,8 @@ struct vqc_circuit_s {
   std::vector<int> gslot_param;
   bool has_nonunitary_matrix = false;
   Plan fwd, adj;   // pure: LDS forward + LDS adjoint; mixed: register-only, shared
-  Plan fwd_nr;     // forward plan without qubit moves (batches), when fwd moves qubits
-  DevBuf scratch;  // second state buffer for forward passes that move qubits
+  DevBuf scratch;  // second state buffer for passes that move qubits (Phi in the adjoint)
+  DevBuf scratch2; // second Psi buffer for adjoint passes that move qubits
   DevBuf dconst;   // recipes, constant data, csr
   DRecipe *d_rec = nullptr;
   c128 *d_cdata = nullptr;
@@ -579,6 +587,9 @@ struct vqc_batch_s {
   int max_passes = 0, max_adj = 0;
   DevBuf mats, psi, part, tables, eparts, ck;
   std::vector<size_t> mat_off, psi_off, part_off;
+  // second buffers of items whose passes move qubits: Phi (forward state), Psi
+  DevBuf scr;
+  std::vector<size_t> scr_off;
   // grouped build launches
   struct Group { vqc_circuit c; DevBuf ptrs; int count; };
   std::vector<std::unique_ptr<Group>> groups;
@@ -869,8 +880,11 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
         return true;
       };
       // a pass that changes the layout stores through LDS (the output's low
-      // bits are other tile bits than the input's)
-      dp.lowfree = (lowfree(ph.stages.front()) ? 1 : 0) | ((lowfree(ph.stages.back()) && !ph.moves) ? 2 : 0);
+      // bits are other tile bits than the input's); the adjoint stores after
+      // the first stage in forward order
+      const bool out_front = adjoint && ph.moves, out_back = !adjoint && ph.moves;
+      dp.lowfree = ((lowfree(ph.stages.front()) && !out_front) ? 1 : 0) |
+                   ((lowfree(ph.stages.back()) && !out_back) ? 2 : 0);
     }
     for (int i = 0; i < ph.K; i++) dp.tq[i] = (int8_t)ph.tq[i];
     // output order: tile-local bits by ascending output position
@@ -952,8 +966,6 @@ vqc_status make_plans(vqc_circuit c) {
     plan_passes(c->elems, nb, R, 0, R, true, c->adj, kMaxVarPerPass);
     st = upload_plan(c, c->adj, true);
     if (st) return st;
-    reset_plan(c->fwd_nr);
-    c->fwd_nr.prog = c->adj.prog + (c->adj.n_gates + 2) * kOpSlots;
   } else {
     const int kmin = R == 3 ? 8 : 5;
     if (nb < kmin) { R = Radj = 4; }
@@ -966,20 +978,14 @@ vqc_status make_plans(vqc_circuit c) {
     vqc_status st = upload_plan(c, c->fwd, false);
     if (st) return st;
     c->adj.prog = c->fwd.prog + (c->fwd.n_gates + 2) * kOpSlots;
-    plan_passes(c->elems, nb, Ka, std::min(low, Ka - 2), Radj, false, c->adj, kMaxVarPerPass);
+    plan_passes(c->elems, nb, Ka, std::min(low, Ka - 2), Radj, false, c->adj, kMaxVarPerPass,
+                remap && nb <= kAdjRemapMaxBits, true);
     st = upload_plan(c, c->adj, true);
     if (st) return st;
-    reset_plan(c->fwd_nr);
-    c->fwd_nr.prog = c->adj.prog + (c->adj.n_gates + 2) * kOpSlots;
-    if (c->fwd.remap) {
-      plan_passes(c->elems, nb, K, low, R, false, c->fwd_nr, 0, false);
-      st = upload_plan(c, c->fwd_nr, false);
-      if (st) return st;
-    }
   }
-  c->mat_total = c->fwd_nr.prog + (c->fwd_nr.n_gates + 2) * kOpSlots;
+  c->mat_total = c->adj.prog + (c->adj.n_gates + 2) * kOpSlots;
   if (c->mats1.ensure((size_t)c->mat_total * sizeof(c128)) != hipSuccess) return VQC_ERR_HIP;
-  if (c->fwd.needs_scratch &&
+  if ((c->fwd.needs_scratch || c->adj.needs_scratch) &&
       c->scratch.ensure((size_t(1) << nb) * sizeof(c128)) != hipSuccess)
     return VQC_ERR_OOM;
   c->tune.tile_bits = c->fwd.K;
@@ -1054,10 +1060,6 @@ int grid_of(vqc_circuit c, int64_t units) {
   return (int)std::min<int64_t>(units, int64_t(1) << 30);
 }
 
-// forward plan of batched launches: the batch job tables run every pass in
-// place, so a circuit whose forward plan moves qubits uses its plain plan
-Plan &bplan(vqc_circuit c) { return c->fwd.remap ? c->fwd_nr : c->fwd; }
-
 // matrices, rotation records and the op programs of both plans for B items
 // (thetas / mats per item) or one item (theta0 / mats0)
 hipError_t build_mats(vqc_circuit c, const double *const *thetas, c128 *const *mats, int B, const double *theta0,
@@ -1066,11 +1068,6 @@ hipError_t build_mats(vqc_circuit c, const double *const *thetas, c128 *const *m
   if (e != hipSuccess) return e;
   e = launch_assemble(c->fwd.d_gates, c->fwd.d_derivs, c->fwd.n_gates, c->fwd.prog, mats, B, mats0, st);
   if (e != hipSuccess) return e;
-  if (c->fwd.remap) {
-    e = launch_assemble(c->fwd_nr.d_gates, c->fwd_nr.d_derivs, c->fwd_nr.n_gates, c->fwd_nr.prog, mats, B, mats0,
-                        st);
-    if (e != hipSuccess) return e;
-  }
   return launch_assemble(c->adj.d_gates, c->adj.d_derivs, c->adj.n_gates, c->adj.prog, mats, B, mats0, st);
 }
 
@@ -1081,21 +1078,33 @@ hipError_t run_passes(vqc_circuit c, Plan &P, int mode, c128 *a, c128 *b, const 
   DOverride ov;
   ov.a = a;
   ov.b = b;
+  ov.a2 = nullptr;
+  ov.b2 = nullptr;
   ov.mats = mats;
   ov.partials = partials;
   ov.mode = (mode == 0 && b) ? 1 : 0;
   ov.use = 1;
   const int grid = grid_of(c, P.units_per_item);
-  // forward passes that move qubits alternate between the state and the
-  // circuit's scratch state (the plan ends in the state)
-  const bool pingpong = mode == 0 && !b && P.needs_scratch;
+  // passes that move qubits alternate between the state and the circuit's
+  // scratch state (the plan ends in the state); the adjoint runs the plan
+  // backwards with Phi and Psi, so it reads a pass's destination and writes
+  // its source
+  const bool pingpong = P.needs_scratch && ((mode == 0 && !b) || mode == 1);
   c128 *bufs[2] = {a, c->scratch.as<c128>()};
+  c128 *bufb[2] = {b, c->scratch2.as<c128>()};
   for (int k = 0; k < p1 - p0; k++) {
     const int p = dir > 0 ? p0 + k : p1 - 1 - k;
     if (pingpong) {
       const PassH &ph = P.passes[p];
-      ov.a = bufs[ph.src];
-      ov.b = bufs[ph.dst];
+      if (mode == 0) {
+        ov.a = bufs[ph.src];
+        ov.b = bufs[ph.dst];
+      } else {
+        ov.a = bufs[ph.dst];
+        ov.b = bufb[ph.dst];
+        ov.a2 = bufs[ph.src];
+        ov.b2 = bufb[ph.src];
+      }
       ov.mode = ph.src != ph.dst ? 1 : 0;
     }
     hipError_t e;
@@ -1501,6 +1510,9 @@ vqc_status vqc_circuit_stats_get(vqc_circuit c, vqc_circuit_stats *out) {
     }
   }
   out->alg_bytes_per_amp = b;
+  out->n_adj_passes = (int)c->adj.passes.size();
+  for (const PassH &ph : c->fwd.passes) out->n_fwd_moves += ph.moves;
+  for (const PassH &ph : c->adj.passes) out->n_adj_moves += ph.moves;
   return VQC_OK;
 }
 
@@ -1584,6 +1596,7 @@ static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s,
   if (c->kind == VQC_PURE) {
     if (c->has_nonunitary_matrix) return VQC_ERR_NOT_UNITARY;
     VQC_TRY(c->psi1.ensure(N * sizeof(c128)));
+    if (P.needs_scratch && c->scratch2.ensure(N * sizeof(c128)) != hipSuccess) return VQC_ERR_OOM;
     c128 *psi = c->psi1.as<c128>();
     VQC_TRY(build_mats(c, nullptr, nullptr, 1, theta, mats, st));
     vs = seed_and_energy(c, terms, s->buf, psi, st, &dres);
@@ -1729,12 +1742,28 @@ static vqc_status batch_build_tables(vqc_batch b) {
     if (c->kind == VQC_PURE) qtot += al(std::max(1, c->n_gslots) * c->adj.units_per_item * sizeof(double));
     e_off[i] = etot;
     etot += expect_units(c->n);
-    b->max_passes = std::max(b->max_passes, (int)bplan(c).passes.size());
+    b->max_passes = std::max(b->max_passes, (int)c->fwd.passes.size());
     b->max_adj = std::max(b->max_adj, (int)c->adj.passes.size());
     b->max_params = std::max(b->max_params, c->n_params);
   }
   b->e_units = etot;
   VQC_TRY(b->mats.ensure(mtot));
+  // scratch states: one for the forward, two for the adjoint once Psi exists
+  size_t stot = 0;
+  b->scr_off.assign(B, 0);
+  for (int i = 0; i < B; i++) {
+    vqc_circuit c = b->circ[i];
+    b->scr_off[i] = stot;
+    const size_t sb = al(state_len(c->kind, c->n) * sizeof(c128));
+    const bool adj = b->psi.p && c->kind == VQC_PURE && c->adj.needs_scratch;
+    if (c->fwd.needs_scratch || adj) stot += sb;
+    if (adj) stot += sb;
+  }
+  if (stot) VQC_TRY(b->scr.ensure(stot));
+  auto scr_state = [&](int i, int k) {
+    const size_t sb = al(state_len(b->circ[i]->kind, b->circ[i]->n) * sizeof(c128));
+    return reinterpret_cast<c128 *>(b->scr.as<char>() + b->scr_off[i] + k * sb);
+  };
   VQC_TRY(b->eparts.ensure(etot * sizeof(double2) + al(B * sizeof(double2)) + 256));
   b->d_eres = reinterpret_cast<double2 *>(b->eparts.as<char>() + al(etot * sizeof(double2)));
   // groups of items sharing a circuit: pointer arrays for the matrix build
@@ -1765,14 +1794,21 @@ static vqc_status batch_build_tables(vqc_batch b) {
     int64_t u0 = 0;
     for (int i = 0; i < B; i++) {
       vqc_circuit c = b->circ[i];
-      if (sI >= (int)bplan(c).passes.size()) continue;
+      if (sI >= (int)c->fwd.passes.size()) continue;
       DJob j;
       std::memset(&j, 0, sizeof(j));
       j.a = b->states[i];
+      if (c->fwd.needs_scratch) {
+        c128 *bufs[2] = {b->states[i], scr_state(i, 0)};
+        const PassH &ph = c->fwd.passes[sI];
+        j.a = bufs[ph.src];
+        j.b = bufs[ph.dst];
+        j.mode = ph.src != ph.dst ? 1 : 0;
+      }
       j.mats = reinterpret_cast<const c128 *>(b->mats.as<char>() + b->mat_off[i]);
-      j.pass = bplan(c).d_pass + sI;
+      j.pass = c->fwd.d_pass + sI;
       j.unit0 = u0;
-      j.n_units = bplan(c).units_per_item;
+      j.n_units = c->fwd.units_per_item;
       j.nbits = c->nbits;
       u0 += j.n_units;
       fj.push_back(j);
@@ -1795,6 +1831,16 @@ static vqc_status batch_build_tables(vqc_batch b) {
       j.b = reinterpret_cast<c128 *>(b->psi.p ? b->psi.as<char>() + b->psi_off[i] : nullptr);
       j.mats = reinterpret_cast<const c128 *>(b->mats.as<char>() + b->mat_off[i]);
       j.partials = reinterpret_cast<double *>(b->part.p ? b->part.as<char>() + b->part_off[i] : nullptr);
+      if (b->psi.p && c->adj.needs_scratch) {
+        // reverse order: read the pass's destination, write its source
+        c128 *bufs[2] = {j.a, scr_state(i, 0)}, *bufb[2] = {j.b, scr_state(i, 1)};
+        const PassH &ph = c->adj.passes[PA - 1 - r];
+        j.a = bufs[ph.dst];
+        j.b = bufb[ph.dst];
+        j.a2 = bufs[ph.src];
+        j.b2 = bufb[ph.src];
+        j.mode = ph.src != ph.dst ? 1 : 0;
+      }
       j.pass = c->adj.d_pass + (PA - 1 - r);
       j.unit0 = u0;
       j.n_units = c->adj.units_per_item;
@@ -1868,8 +1914,8 @@ static vqc_status batch_forward_on(vqc_batch b, hipStream_t st) {
     const int64_t units = b->fwd_units[sI];
     const int grid = grid_of(c0, units);
     const DJob *jobs = b->d_fwd_jobs + b->fwd_first[sI];
-    if (b->reg_only) VQC_TRY(launch_pass_reg(bplan(c0).R, 0, jobs, b->fwd_count[sI], units, grid, ov, st));
-    else VQC_TRY(launch_pass_lds(bplan(c0).K, bplan(c0).R, false, jobs, b->fwd_count[sI], units, grid, ov, st));
+    if (b->reg_only) VQC_TRY(launch_pass_reg(c0->fwd.R, 0, jobs, b->fwd_count[sI], units, grid, ov, st));
+    else VQC_TRY(launch_pass_lds(c0->fwd.K, c0->fwd.R, false, jobs, b->fwd_count[sI], units, grid, ov, st));
   }
   return VQC_OK;
 }
@@ -1960,7 +2006,7 @@ vqc_status vqc_batch_create(vqc_batch *out, int B, const vqc_circuit *circuits, 
     if (circuits[i]->n_params > 0 && (!thetas || !thetas[i])) return VQC_ERR_ARG;
     const vqc_circuit c = circuits[i], c0 = circuits[0];
     if (c->kind != c0->kind) return VQC_ERR_KIND;
-    if (bplan(c).reg_only != bplan(c0).reg_only || bplan(c).K != bplan(c0).K || bplan(c).R != bplan(c0).R ||
+    if (c->fwd.reg_only != c0->fwd.reg_only || c->fwd.K != c0->fwd.K || c->fwd.R != c0->fwd.R ||
         c->adj.K != c0->adj.K || c->adj.R != c0->adj.R || c->adj.reg_only != c0->adj.reg_only)
       return VQC_ERR_UNSUPPORTED;
   }
@@ -1973,8 +2019,8 @@ vqc_status vqc_batch_create(vqc_batch *out, int B, const vqc_circuit *circuits, 
     b->thetas.push_back(thetas ? thetas[i] : nullptr);
   }
   b->stream = reinterpret_cast<hipStream_t>(stream);
-  b->reg_only = bplan(circuits[0]).reg_only;
-  b->K = bplan(circuits[0]).K;
+  b->reg_only = circuits[0]->fwd.reg_only;
+  b->K = circuits[0]->fwd.K;
   b->Kadj = circuits[0]->adj.K;
   vqc_status st = batch_build_tables(b.get());
   if (st) return st;

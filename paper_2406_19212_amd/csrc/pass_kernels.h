@@ -861,7 +861,17 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
 #pragma unroll
     for (int i = 0; i < K - R; i++) st |= (uint64_t)((t >> i) & 1) << P->tq[i];
     const gc128 *src = A;
-    gc128 *dst = (mode == 1) ? Bv : A;
+    [[maybe_unused]] const gc128 *srcb = Bv;
+    gc128 *dst = A;
+    [[maybe_unused]] gc128 *dstb = Bv;
+    if (mode == 1) {
+      if constexpr (ADJ) {
+        dst = (gc128 *)(ov.use ? ov.a2 : J.a2);
+        dstb = (gc128 *)(ov.use ? ov.b2 : J.b2);
+      } else {
+        dst = Bv;
+      }
+    }
     const int nst = P->nst;
     // direct HBM access for the first / last stage in execution order
     const bool din = ADJ ? (P->lowfree >> 1) & 1 : false;
@@ -883,7 +893,7 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
           if ((j >> i) & 1) oj |= 1ull << P->tq[K - R + i];
         const uint64_t gi = gbase | st | oj;
         la[swz(j * T + t)] = ldg(&src[gi]);
-        if constexpr (ADJ) lb[swz(j * T + t)] = ldg(&Bv[gi]);
+        if constexpr (ADJ) lb[swz(j * T + t)] = ldg(&srcb[gi]);
       }
       __syncthreads();
     }
@@ -921,7 +931,7 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
           for (int i = 0; i < R; i++)
             if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
           a[j] = ldg(&src[gb | go]);
-          if constexpr (ADJ) b[j] = ldg(&Bv[gb | go]);
+          if constexpr (ADJ) b[j] = ldg(&srcb[gb | go]);
         }
       } else {
 #pragma unroll
@@ -965,7 +975,7 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
           for (int i = 0; i < R; i++)
             if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
           stg(&dst[gb | go], a[j]);
-          if constexpr (ADJ) stg(&Bv[gb | go], b[j]);
+          if constexpr (ADJ) stg(&dstb[gb | go], b[j]);
         }
       } else {
 #pragma unroll
@@ -1002,7 +1012,7 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
           }
         const uint64_t gi = gbo | so | oj;
         stg(&dst[gi], la[swz(sl | ol)]);
-        if constexpr (ADJ) stg(&Bv[gi], lb[swz(sl | ol)]);
+        if constexpr (ADJ) stg(&dstb[gi], lb[swz(sl | ol)]);
       }
     }
     if constexpr (ADJ) {

@@ -120,13 +120,16 @@ struct DPass {
 struct DJob {
   c128 *a;          // state (forward) / Phi (adjoint)
   c128 *b;          // Psi (adjoint), or destination for out-of-place forward
+  c128 *a2;         // out-of-place adjoint: destinations of Phi ...
+  c128 *b2;         // ... and Psi
   const c128 *mats; // the item's matrices
   double *partials; // [gslot][n_units] (adjoint)
   const DPass *pass;
   int64_t unit0;    // first global unit of this job
   int64_t n_units;  // units (tiles, or blocks of tiles) of this job
   int32_t nbits;
-  int32_t mode;     // 0: in place; 1: out of place (read a, write b)
+  int32_t mode;     // 0: in place; 1: out of place (forward: read a, write b;
+                    // adjoint: read a, b, write a2, b2)
 };
 
 // buffers for single-item launches, passed by value so that the device job
@@ -134,6 +137,8 @@ struct DJob {
 struct DOverride {
   c128 *a;
   c128 *b;
+  c128 *a2;
+  c128 *b2;
   const c128 *mats;
   double *partials;
   int32_t mode;

@@ -384,9 +384,12 @@ def test_forward_with_qubit_moves(rows, cols, cycles, tile, low):
     assert len(ms) == c.stats()["n_passes"]
     assert maxdiff(st.numpy(), ref) < AMP_TOL
     # parametrised circuit with moves: forward and the adjoint gradient
-    ops2 = W.hea(n, 3)
+    ops2 = W.hea(n, 5)
     th = W.theta_uniform(9, 1, W.count_params(ops2))[0]
     c2 = Circuit(n, ops2, tune={"tile_bits": tile, "low_bits": low, "remap": 1})
+    s2 = c2.stats()
+    print("hea: adjoint passes %d, moving %d" % (s2["n_adj_passes"], s2["n_adj_moves"]))
+    assert s2["n_adj_moves"] > 0
     st2 = State(n)
     tht = torch.tensor(th, device="cuda")
     c2.apply(st2, tht)
