@@ -12,7 +12,11 @@ What each function follows:
   Eq. (circuitevolve); on mixed states, Eq. (channel2) on vec(rho) (Sec. 3.4).
 * ``expectation``: Sec. 2.5 (Pauli sums), Eq. (loss_pure) / Eq. (loss_mixed).
 * ``grad_pure``: Sec. 3.3, Eqs. (diff_pure)-(diff_pure2) and Alg. 2.
-* ``grad_mixed``: Sec. 3.5, Eqs. (diff_mixed)-(diff_mixed2).
+* ``grad_mixed``: Sec. 3.5, Eqs. (diff_mixed)-(diff_mixed2), states before
+  each op recomputed from stored ones.
+* ``grad_mixed_inverse``: the same gradient by Alg. 2 with channel inverses
+  for Phi (Sec. 3.3: the inverse form extends Alg. 2 to channels) and the
+  adjoint superoperator for Psi; ``invert`` is its Gauss-Jordan step.
 * ``lanczos`` (in ``oracle.lanczos``) and ``mlp`` (in ``oracle.mlp``) cover
   the ground energy and the surrogate network, which the paper does not define.
 """
@@ -68,6 +72,9 @@ def lib():
                                       ctypes.c_int, P, P, P]
         _lib.or_grad_mixed.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P,
                                        P, ctypes.c_int, P, P, ctypes.c_int]
+        _lib.or_grad_mixed_inverse.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P,
+                                               P, ctypes.c_int, P, P, P]
+        _lib.or_invert.argtypes = [ctypes.c_int, P, P]
         _lib.or_set_threads.argtypes = [ctypes.c_int]
         _lib.or_get_threads.restype = ctypes.c_int
     return _lib
@@ -254,3 +261,32 @@ def grad_mixed(n: int, ops, theta, terms, init=None, n_params=None, stride: int 
     if rc:
         raise ValueError("oracle grad_mixed failed (%d)" % rc)
     return float(e[0]), grad[:P]
+
+
+def invert(A: np.ndarray) -> np.ndarray:
+    """Inverse of a square matrix (D <= 16) by Gauss-Jordan with partial pivoting."""
+    A = np.ascontiguousarray(A, np.complex128)
+    D = A.shape[0]
+    out = np.zeros((D, D), np.complex128)
+    if lib().or_invert(D, _ptr(A), _ptr(out)):
+        raise ValueError("singular matrix")
+    return out
+
+
+def grad_mixed_inverse(n: int, ops, theta, terms, init=None, n_params=None):
+    """Noisy gradient by Alg. 2 with Phi <- M^{-1} Phi and Psi <- M^dagger Psi.
+    Returns (energy, grad, Phi after the sweep)."""
+    xm, zm, c = _terms(terms)
+    th = np.ascontiguousarray(theta, np.float64)
+    P = int(n_params if n_params is not None else th.size)
+    grad = np.zeros(max(P, 1), np.float64)
+    e = np.zeros(1, np.float64)
+    phi = np.zeros(1 << (2 * n), np.complex128)
+    ini = None if init is None else np.ascontiguousarray(init, np.complex128).ravel()
+    tab = _OpTable(ops)
+    rc = lib().or_grad_mixed_inverse(n, len(ops), tab.arr, _ptr(th), None if ini is None else _ptr(ini),
+                                     len(terms), _ptr(xm), _ptr(zm), _ptr(c), P, _ptr(grad), _ptr(e),
+                                     _ptr(phi))
+    if rc:
+        raise ValueError("oracle grad_mixed_inverse failed (%d)" % rc)
+    return float(e[0]), grad[:P], phi

@@ -33,7 +33,10 @@
  *     ((1+i) I + (1-i) G) / 2.
  *   - FSIM local index l = b_{q0} + 2 b_{q1} (column-major tensor order).
  *   - noisy backward: Psi_{j-1} = M_j^dagger Psi_j (adjoint superoperator);
- *     Phi_{j-1} is recomputed from stored states, not by channel inverses.
+ *     Phi_{j-1} is recomputed from stored states (or_grad_mixed) or, in the
+ *     inverse form that Sec. 3.3 says extends Alg. 2 to channels,
+ *     Phi_{j-1} = M_j^{-1} Phi_j (or_grad_mixed_inverse).  Using M^{-1} for
+ *     Psi as well would give wrong gradients for non-unitary channels.
  */
 #include <complex.h>
 #include <math.h>
@@ -551,6 +554,83 @@ done:
   if (ck) for (int i = 0; i < n_ck; i++) free(ck[i]);
   if (seg) for (int i = 0; i < stride; i++) free(seg[i]);
   free(ck); free(seg); free(psi); free(tmp); free(cur);
+  return rc;
+}
+
+/* Inverse of a D x D row-major matrix by Gauss-Jordan elimination with
+ * partial pivoting (textbook).  Returns 0, or -1 when a pivot is exactly 0. */
+int or_invert(int D, const cplx *A, cplx *Ainv) {
+  cplx W[16 * 32];
+  if (D < 1 || D > 16) return -1;
+  for (int r = 0; r < D; r++)
+    for (int c = 0; c < 2 * D; c++) W[r * 2 * D + c] = c < D ? A[r * D + c] : (c - D == r);
+  for (int k = 0; k < D; k++) {
+    int p = k;
+    for (int r = k + 1; r < D; r++)
+      if (cabs(W[r * 2 * D + k]) > cabs(W[p * 2 * D + k])) p = r;
+    if (W[p * 2 * D + k] == 0) return -1;
+    for (int c = 0; c < 2 * D; c++) {
+      cplx t = W[k * 2 * D + c];
+      W[k * 2 * D + c] = W[p * 2 * D + c];
+      W[p * 2 * D + c] = t;
+    }
+    cplx piv = W[k * 2 * D + k];
+    for (int c = 0; c < 2 * D; c++) W[k * 2 * D + c] /= piv;
+    for (int r = 0; r < D; r++) {
+      if (r == k) continue;
+      cplx f = W[r * 2 * D + k];
+      for (int c = 0; c < 2 * D; c++) W[r * 2 * D + c] -= f * W[k * 2 * D + c];
+    }
+  }
+  for (int r = 0; r < D; r++)
+    for (int c = 0; c < D; c++) Ainv[r * D + c] = W[r * 2 * D + D + c];
+  return 0;
+}
+
+/* Sec. 3.3 / 3.5, Alg. 2 in the inverse form for noisy circuits: Phi starts
+ * at the final vec(rho), Psi = vec(H); walking j = M..1:
+ *   Phi <- M_j^{-1} Phi;  g[var] += Re <<Psi| dM_j |Phi>>;  Psi <- M_j^dagger Psi.
+ * Only two states are kept.  On return phi_out (if given) holds Phi after the
+ * sweep, which equals the initial state up to rounding amplified by the
+ * channels' condition numbers.  Returns -1 - j when M_j is singular. */
+int or_grad_mixed_inverse(int n, int n_ops, const or_op *ops, const double *theta, const cplx *init,
+                          int nt, const uint64_t *xm, const uint64_t *zm, const cplx *coef,
+                          int n_params, double *grad, double *energy, cplx *phi_out) {
+  uint64_t N = 1ull << (2 * n);
+  cplx *phi = malloc(N * sizeof(cplx)), *psi = malloc(N * sizeof(cplx)), *tmp = malloc(N * sizeof(cplx));
+  cplx S[256], Si[256], Sd[256], U[256], dU[256], dS[256];
+  int qq[8], rc = 0;
+  if (!phi || !psi || !tmp) { rc = -100; goto done; }
+  for (uint64_t x = 0; x < N; x++) phi[x] = init ? init[x] : (x == 0);
+  for (int j = 0; j < n_ops; j++)
+    if (or_apply_op(phi, n, 1, &ops[j], theta)) { rc = -1 - j; goto done; }
+  vec_pauli_sum(n, nt, xm, zm, coef, psi);
+  *energy = creal(inner(psi, phi, N));
+  for (int p = 0; p < n_params; p++) grad[p] = 0;
+  for (int j = n_ops - 1; j >= 0; j--) {
+    const or_op *op = &ops[j];
+    int D = 1 << (2 * op->m);
+    super_qubits(op, n, qq);
+    if (op_superop(op, theta, S) < 0) { rc = -1 - j; goto done; }
+    if (or_invert(D, S, Si)) { rc = -1 - j; goto done; }
+    or_apply(phi, 2 * n, 2 * op->m, qq, Si);
+    if (!is_channel(op->code)) {
+      or_gate_matrix(op, theta, U);
+      for (int k = 0; k < n_params_of(op->code); k++) {
+        if (op->var[k] < 0) continue;
+        or_gate_dmatrix(op, theta, k, dU);
+        gate_dsuperop(U, dU, op->m, dS);
+        memcpy(tmp, phi, N * sizeof(cplx));
+        or_apply(tmp, 2 * n, 2 * op->m, qq, dS);
+        grad[op->var[k]] += creal(inner(psi, tmp, N));
+      }
+    }
+    dagger(S, D, Sd);
+    or_apply(psi, 2 * n, 2 * op->m, qq, Sd);
+  }
+  if (phi_out) memcpy(phi_out, phi, N * sizeof(cplx));
+done:
+  free(phi); free(psi); free(tmp);
   return rc;
 }
 

@@ -505,3 +505,71 @@ def test_noiseless_mixed_gradient_equals_pure(oracle_mod):
     _, gp, _ = oracle_mod.grad_pure(n, ops, th, terms)
     _, gm = oracle_mod.grad_mixed(n, ops, th, terms)
     assert np.max(np.abs(gp - gm)) < 1e-13
+
+
+# ------------------------------------------- noisy gradient, inverse form
+
+@pytest.mark.parametrize("D", [2, 4, 16])
+def test_invert_matches_library_inverse(oracle_mod, D):
+    rng = np.random.default_rng(90 + D)
+    A = rng.normal(size=(D, D)) + 1j * rng.normal(size=(D, D)) + 2 * D * np.eye(D)
+    A = A[rng.permutation(D)]  # a row permutation forces pivoting
+    Ai = oracle_mod.invert(A)
+    assert np.max(np.abs(A @ Ai - np.eye(D))) < 1e-13
+    assert np.max(np.abs(Ai @ A - np.eye(D))) < 1e-13
+    assert np.max(np.abs(Ai - np.linalg.inv(A))) < 1e-13
+
+
+def test_invert_zero_diagonal_and_singular(oracle_mod):
+    Pm = np.eye(4)[[2, 0, 3, 1]].astype(complex)  # permutation: zero diagonal
+    assert np.array_equal(oracle_mod.invert(Pm), Pm.T)
+    S = np.ones((4, 4), complex)
+    with pytest.raises(ValueError):
+        oracle_mod.invert(S)
+
+
+def test_channel_inverse_closed_forms(oracle_mod):
+    rho = W.random_density(1, 12)  # plays the channel's output rho'
+    p = g = 0.37
+    cases = {
+        "depolarizing": (rho - p * np.trace(rho) * I2 / 2) / (1 - p),
+        "amplitude_damping": np.array([[rho[0, 0] - g * rho[1, 1] / (1 - g), rho[0, 1] / math.sqrt(1 - g)],
+                                       [rho[1, 0] / math.sqrt(1 - g), rho[1, 1] / (1 - g)]]),
+        "phase_damping": np.array([[rho[0, 0], rho[0, 1] / math.sqrt(1 - g)],
+                                   [rho[1, 0] / math.sqrt(1 - g), rho[1, 1]]]),
+    }
+    for name, want in cases.items():
+        Si = oracle_mod.invert(oracle_mod.superop(oracle_mod.kraus(name, (p,))))
+        v = vec(rho)
+        oracle_mod.apply_matrix(v, 2, [0, 1], Si)
+        assert np.max(np.abs(unvec(v, 1) - want)) < 1e-14, name
+
+
+def test_adjoint_mixed_inverse_vs_parameter_shift(oracle_mod):
+    n = 3
+    ops, th = W.noisy_brickwall(n, 2, 44, p1=0.05, gamma=0.08, p2=0.1)
+    terms = W.zz(0, 1) + [W.pauli_string({2: "x"}, 0.5), W.pauli_string({0: "y", 2: "y"}, -0.3)]
+    e, g, phi = oracle_mod.grad_mixed_inverse(n, ops, th, terms)
+    assert abs(e - loss_mixed(oracle_mod, n, ops, th, terms)) < 1e-14
+    gs = shift_grad(lambda t: loss_mixed(oracle_mod, n, ops, t, terms), th)
+    assert np.max(np.abs(g - gs)) < 1e-12
+    # Phi walks back to the initial state
+    assert np.max(np.abs(phi - oracle_mod.initial_state(n, mixed=True))) < 1e-12
+    # the stored-state form gives the same gradient
+    assert np.max(np.abs(g - oracle_mod.grad_mixed(n, ops, th, terms)[1])) < 1e-12
+
+
+def test_adjoint_mixed_inverse_from_init_and_singular_channel(oracle_mod):
+    from types import SimpleNamespace as NS
+    n = 2
+    ops, th = W.noisy_brickwall(n, 2, 47, p1=0.2, gamma=0.3, p2=0.25)
+    init = vec(W.random_density(n, 13))
+    terms = W.tfim(n, 0.8)
+    e, g, phi = oracle_mod.grad_mixed_inverse(n, ops, th, terms, init=init)
+    e2, g2 = oracle_mod.grad_mixed(n, ops, th, terms, init=init)
+    assert abs(e - e2) < 1e-14 and np.max(np.abs(g - g2)) < 1e-12
+    assert np.max(np.abs(phi - init)) < 1e-12
+    # full amplitude damping has no inverse
+    bad = ops + [NS(name="amplitude_damping", qubits=(1,), params=(1.0,), var=(), data=None)]
+    with pytest.raises(ValueError):
+        oracle_mod.grad_mixed_inverse(n, bad, th, terms)
