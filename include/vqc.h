@@ -54,7 +54,8 @@ typedef enum {
   VQC_ERR_OOM = -7,           /* device allocation failed */
   VQC_ERR_HIP = -8,           /* HIP runtime error */
   VQC_ERR_NOT_HERMITIAN = -9, /* gradient asked for a complex-coefficient H */
-  VQC_ERR_NOT_UNITARY = -10   /* backward through a non-unitary gate matrix */
+  VQC_ERR_NOT_UNITARY = -10,  /* backward through a non-unitary gate matrix */
+  VQC_ERR_ILL_CONDITIONED = -11 /* a channel's inverse exceeds the condition bound */
 } vqc_status;
 
 typedef enum { VQC_PURE = 0, VQC_MIXED = 1 } vqc_kind;
@@ -228,6 +229,25 @@ vqc_status vqc_apply_circuit_timed(vqc_state s, vqc_circuit c, const double *the
 vqc_status vqc_backward(vqc_circuit c, const double *theta_dev, vqc_state s,
                         const vqc_pauli_sum *H, double *grad_dev, double *energy_host,
                         const void *init_dev, size_t checkpoint_budget_bytes);
+
+/* gradient(loss, circ) by Alg. 2 in its inverse form (Sec. 3.3: Q^{-1} in
+ * place of Q^dagger, which extends the sweep to channels; Sec. 3.5):
+ * walking the ops backwards, Phi <- M^{-1} Phi, g += Re<<Psi| dM |Phi>>,
+ * Psi <- M^dagger Psi.  Only two states are kept (no checkpoints), at the
+ * price of rounding amplified by the channels' condition numbers.  s holds
+ * the final state of vqc_apply_circuit(c, theta) and is uncomputed in place
+ * (back to the initial state up to that rounding).  max_cond bounds the
+ * 1-norm condition number ||M|| ||M^{-1}|| of every non-unitary op (a
+ * channel, or a fused run of one-qubit ops holding one), computed on the
+ * device; a larger one (or a singular channel) returns
+ * VQC_ERR_ILL_CONDITIONED before any state is touched.  max_cond <= 0 takes
+ * 1e8.  PURE circuits run vqc_backward (Q^{-1} = Q^dagger).  MIXED circuits
+ * with a non-unitary gate matrix return VQC_ERR_NOT_UNITARY.  grad_dev and
+ * energy_host as in vqc_backward.  Synchronises the stream once (the
+ * condition check). */
+vqc_status vqc_backward_inverse(vqc_circuit c, const double *theta_dev, vqc_state s,
+                                const vqc_pauli_sum *H, double *grad_dev, double *energy_host,
+                                double max_cond);
 
 /* Time candidate tunes for c on the scratch state s (contents destroyed) and
  * re-plan c with the fastest; the chosen tune is written to *out. */

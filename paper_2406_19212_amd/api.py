@@ -168,6 +168,21 @@ class Circuit:
               "vqc_backward")
         return grad[: self.n_params], (e.value if energy else None)
 
+    def backward_inverse(self, theta, state: State, terms, grad=None, energy=True, max_cond=0.0):
+        """Adjoint gradient by Alg. 2 with channel inverses for Phi (two states,
+        no checkpoints); ``state`` holds the forward result and is uncomputed in
+        place.  Raises VQCError(VQC_ERR_ILL_CONDITIONED) when a channel's
+        condition number exceeds ``max_cond`` (0: 1e8).  Returns (grad, energy)."""
+        th = self._theta(theta)
+        if grad is None:
+            grad = torch.zeros(max(1, self.n_params), dtype=torch.float64, device=state.tensor.device)
+        ps = B.PauliSum(terms)
+        e = ctypes.c_double()
+        check(lib().vqc_backward_inverse(self.h, _dptr(th), state.h, ps.ref(), _dptr(grad),
+                                         ctypes.byref(e) if energy else None, float(max_cond)),
+              "vqc_backward_inverse")
+        return grad[: self.n_params], (e.value if energy else None)
+
     def autotune(self, state: State, theta=None) -> dict:
         th = self._theta(theta)
         t = B.vqc_tune()

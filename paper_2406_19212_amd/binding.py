@@ -37,7 +37,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "qubit out of range or repeated",
           -3: "unsupported op or combination", -4: "pure/mixed mismatch",
           -5: "Kraus operators are not trace preserving", -6: "non-finite input",
           -7: "device out of memory", -8: "HIP runtime error",
-          -9: "observable must have real coefficients", -10: "gate matrix is not unitary"}
+          -9: "observable must have real coefficients", -10: "gate matrix is not unitary",
+          -11: "channel inverse exceeds the condition-number bound"}
 
 
 class VQCError(RuntimeError):
@@ -98,6 +99,8 @@ _SIGS = {
     "vqc_apply_circuit_timed": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "vqc_backward": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p,
                              ctypes.POINTER(c_double), c_void_p, c_size_t]),
+    "vqc_backward_inverse": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p,
+                                     ctypes.POINTER(c_double), c_double]),
     "vqc_circuit_autotune": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(vqc_tune)]),
     "vqc_batch_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "vqc_batch_destroy": (c_int, [c_void_p]),

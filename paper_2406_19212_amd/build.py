@@ -35,7 +35,7 @@ def units():
                 out.append(("inst_lds.hip", UNIFORM_CF + ["-DVQC_K=%d" % K, "-DVQC_R=%d" % R, "-DVQC_ADJ=%d" % A],
                             "lds_%d_%d_%d" % (K, R, A)))
     for R in (1, 2, 3, 4):
-        for M in (0, 1, 2):
+        for M in (0, 1, 2, 3):
             out.append(("inst_reg.hip", UNIFORM_CF + ["-DVQC_R=%d" % R, "-DVQC_MODE=%d" % M], "reg_%d_%d" % (R, M)))
     out.append(("kernels.hip", UNIFORM_CF, "kernels"))
     out.append(("api.cpp", ["-x", "hip"], "api"))

@@ -226,6 +226,7 @@ struct Elem {
   int nq;
   int q[4];    // global bits (vec(rho) bits for mixed)
   int mat;     // matrix offset (c128 units), -1 if none
+  bool inv = false;  // not unitary: its inverse is stored right after the matrix
   std::vector<Deriv> d;
   uint64_t mask() const {
     uint64_t m = 0;
@@ -560,6 +561,8 @@ struct vqc_circuit_s {
   int n_gslots = 0;
   std::vector<int> gslot_param;
   bool has_nonunitary_matrix = false;
+  std::vector<DInv> inv_list;  // non-unitary ops (mixed): matrices to invert
+  DevBuf dinv;                 // condition-number word, then inv_list
   Plan fwd, adj;   // pure: LDS forward + LDS adjoint; mixed: register-only, shared
   DevBuf scratch;  // second state buffer for passes that move qubits (Phi in the adjoint)
   DevBuf scratch2; // second Psi buffer for adjoint passes that move qubits
@@ -654,6 +657,15 @@ int add_gate_recipe(vqc_circuit c, int gk, int type, int form, int nq, const vqc
   return add_recipe(c, type, form, 0, nq, op, data_off, n_data, d * d);
 }
 
+// room for the inverse of the D x D matrix just added at `mat`
+void reserve_inverse(vqc_circuit c, int mat, int D) {
+  DInv v;
+  v.mat = mat;
+  v.dim = D;
+  c->inv_list.push_back(v);
+  c->mat_size += D * D;
+}
+
 // a recipe for op `op` as a 4x4 superoperator of a fused run
 DRecipe sub_recipe(const vqc_op &op, int data_off, int n_data) {
   DRecipe r;
@@ -727,6 +739,8 @@ vqc_status lower(vqc_circuit c) {
         e.q[0] = op.qubits[0];
         e.q[1] = op.qubits[0] + n;
         e.mat = add_recipe(c, VQC_ID, RF_FUSED, 0, 1, none, first, (int)(j2 - j), 16);
+        for (size_t t = j; t < j2; t++) e.inv = e.inv || is_channel(c->ops[t].type);
+        if (e.inv) reserve_inverse(c, e.mat, 4);
         for (size_t t = j; t < j2; t++)
           for (int k = 0; k < 5; k++)
             if (c->ops[t].param_index[k] >= 0) {
@@ -748,6 +762,8 @@ vqc_status lower(vqc_circuit c) {
       e.kind = m == 1 ? GK_DENSE2 : GK_DENSE4;
       for (int t = 0; t < m; t++) { e.q[t] = op.qubits[t]; e.q[t + m] = op.qubits[t] + n; }
       e.mat = add_recipe(c, op.type, RF_SUPER_KRAUS, 0, m, op, data_off, n_data, d * d * d * d);
+      e.inv = true;
+      reserve_inverse(c, e.mat, d * d);
       c->elems.push_back(e);
       continue;
     }
@@ -850,6 +866,7 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
         g.d0 = (int)derivs.size();
         g.nd = adjoint ? (int16_t)e.d.size() : 0;
         if (adjoint && !e.d.empty() && e.d[0].kind >= GK_GENX && e.d[0].kind <= GK_GENZ) g.nd |= kGenFlag;
+        if (adjoint && e.inv) g.nd |= kInvFlag;
         if (adjoint)
           for (const Deriv &dv : e.d) {
             DDeriv dd;
@@ -1027,6 +1044,11 @@ vqc_status upload_const(vqc_circuit c) {
   c->d_csr_ptr = reinterpret_cast<int32_t *>(base + o_p);
   c->d_csr_slot = reinterpret_cast<int32_t *>(base + o_s);
   VQC_TRY(c->mats1.ensure((size_t)c->mat_total * sizeof(c128)));
+  if (!c->inv_list.empty()) {
+    VQC_TRY(c->dinv.ensure(256 + c->inv_list.size() * sizeof(DInv)));
+    VQC_TRY(hipMemcpy(c->dinv.as<char>() + 256, c->inv_list.data(), c->inv_list.size() * sizeof(DInv),
+                      hipMemcpyHostToDevice));
+  }
   return VQC_OK;
 }
 
@@ -1136,6 +1158,7 @@ const char *vqc_status_string(int st) {
     case VQC_ERR_HIP: return "HIP runtime error";
     case VQC_ERR_NOT_HERMITIAN: return "observable must have real coefficients";
     case VQC_ERR_NOT_UNITARY: return "gate matrix is not unitary";
+    case VQC_ERR_ILL_CONDITIONED: return "channel inverse exceeds the condition-number bound";
     default: return "unknown status";
   }
 }
@@ -1576,10 +1599,11 @@ static vqc_status seed_and_energy(vqc_circuit c, const std::vector<DTerm> &terms
   return VQC_OK;
 }
 
-// energy_dev: optional device destination of the energy (stream-ordered)
+// energy_dev: optional device destination of the energy (stream-ordered);
+// max_cond > 0 selects the inverse form for mixed circuits
 static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s, const vqc_pauli_sum *H,
                                 double *grad, double *energy_host, double *energy_dev, const void *init_dev,
-                                size_t budget) {
+                                size_t budget, double max_cond = 0.0) {
   if (!c || !s || !H) return VQC_ERR_ARG;
   if (s->kind != c->kind || s->n != c->n) return VQC_ERR_KIND;
   if (c->n_params > 0 && (!theta || !grad)) return VQC_ERR_ARG;
@@ -1602,6 +1626,34 @@ static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s,
     vs = seed_and_energy(c, terms, s->buf, psi, st, &dres);
     if (vs) return vs;
     VQC_TRY(run_passes(c, P, 1, s->buf, psi, mats, c->part1.as<double>(), 0, np, -1, st));
+  } else if (max_cond > 0.0) {
+    // inverse form: invert the non-unitary ops' matrices, check their
+    // condition numbers, then one sweep with Phi <- M^{-1} Phi
+    if (c->has_nonunitary_matrix) return VQC_ERR_NOT_UNITARY;
+    VQC_TRY(c->psi1.ensure(N * sizeof(c128)));
+    c128 *psi = c->psi1.as<c128>();
+    VQC_TRY(build_mats(c, nullptr, nullptr, 1, theta, mats, st));
+    if (!c->inv_list.empty()) {
+      unsigned long long *kb = c->dinv.as<unsigned long long>();
+      VQC_TRY(hipMemsetAsync(kb, 0, sizeof(*kb), st));
+      VQC_TRY(launch_invert(reinterpret_cast<const DInv *>(c->dinv.as<char>() + 256), (int)c->inv_list.size(),
+                            nullptr, 1, mats, kb, st));
+      unsigned long long bits = 0;
+      VQC_TRY(hipMemcpyAsync(&bits, kb, sizeof(bits), hipMemcpyDeviceToHost, st));
+      VQC_TRY(hipStreamSynchronize(st));
+      double kappa;
+      std::memcpy(&kappa, &bits, sizeof(kappa));
+      if (!(kappa <= max_cond)) return VQC_ERR_ILL_CONDITIONED;
+    }
+    std::vector<DTerm> tt = terms;
+    VQC_TRY(c->small.ensure(std::max<size_t>(1, tt.size()) * sizeof(DTerm)));
+    if (!tt.empty())
+      VQC_TRY(hipMemcpyAsync(c->small.p, tt.data(), tt.size() * sizeof(DTerm), hipMemcpyHostToDevice, st));
+    VQC_TRY(hipStreamSynchronize(st));
+    VQC_TRY(launch_seed_mixed(psi, c->n, c->small.as<DTerm>(), (int)tt.size(), st));
+    vs = seed_and_energy(c, terms, s->buf, nullptr, st, &dres);
+    if (vs) return vs;
+    VQC_TRY(run_passes(c, P, 3, s->buf, psi, mats, c->part1.as<double>(), 0, np, -1, st));
   } else {
     // checkpoints every `stride` passes; a segment of states is recomputed
     // from its checkpoint before its backward steps
@@ -1676,6 +1728,14 @@ static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s,
 vqc_status vqc_backward(vqc_circuit c, const double *theta, vqc_state s, const vqc_pauli_sum *H, double *grad,
                         double *energy_host, const void *init_dev, size_t budget) {
   return backward_impl(c, theta, s, H, grad, energy_host, nullptr, init_dev, budget);
+}
+
+vqc_status vqc_backward_inverse(vqc_circuit c, const double *theta, vqc_state s, const vqc_pauli_sum *H,
+                                double *grad, double *energy_host, double max_cond) {
+  if (!c) return VQC_ERR_ARG;
+  if (!is_finite_d(max_cond)) return VQC_ERR_NONFINITE;
+  if (c->kind == VQC_PURE) return backward_impl(c, theta, s, H, grad, energy_host, nullptr, nullptr, 0);
+  return backward_impl(c, theta, s, H, grad, energy_host, nullptr, nullptr, 0, max_cond > 0.0 ? max_cond : 1e8);
 }
 
 vqc_status vqc_circuit_autotune(vqc_circuit c, vqc_state s, const double *theta, vqc_tune *out) {

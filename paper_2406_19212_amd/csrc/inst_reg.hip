@@ -1,4 +1,4 @@
-// one register-only pass instantiation per object file: -DVQC_R=<bits> -DVQC_MODE=<0|1|2>
+// one register-only pass instantiation per object file: -DVQC_R=<bits> -DVQC_MODE=<0|1|2|3>
 #include "pass_kernels.h"
 
 namespace vqc {

@@ -352,6 +352,78 @@ __global__ void k_assemble(const DGate *__restrict__ gates, const DDeriv *__rest
   *reinterpret_cast<DOp *>(M + prog + (size_t)i * kOpSlots) = e;
 }
 
+// Inverse superoperators for the inverse-form noisy adjoint.  Block (i, b)
+// inverts item b's D x D matrix at inv[i].mat (D = 4 or 16, any consistent
+// storage order) by Gauss-Jordan elimination with partial pivoting in LDS and
+// stores the inverse right after it.  kappa_bits receives the largest
+// 1-norm condition number ||M|| ||M^{-1}|| as the bits of a non-negative
+// double (ordered like the values; inf and NaN from a zero pivot order above
+// every finite value).
+__global__ void __launch_bounds__(64) k_invert(const DInv *__restrict__ inv, c128 *const *__restrict__ mats,
+                                               c128 *mats0, unsigned long long *kappa_bits) {
+  __shared__ c128 A[16][33];
+  __shared__ c128 f[16];
+  __shared__ int piv;
+  const int t = threadIdx.x;
+  const DInv I = inv[blockIdx.x];
+  c128 *M = (mats ? mats[blockIdx.y] : mats0) + I.mat;
+  const int D = I.dim, W = 2 * D;
+  for (int idx = t; idx < D * W; idx += 64) {
+    const int r = idx / W, c = idx % W;
+    A[r][c] = c < D ? M[r * D + c] : make_double2(c - D == r ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < D; k++) {
+    if (t == 0) {
+      int p = k;
+      double best = hypot(A[k][k].x, A[k][k].y);
+      for (int r = k + 1; r < D; r++) {
+        const double v = hypot(A[r][k].x, A[r][k].y);
+        if (v > best) { best = v; p = r; }
+      }
+      piv = p;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != k)
+      for (int c = t; c < W; c += 64) {
+        const c128 x = A[k][c];
+        A[k][c] = A[p][c];
+        A[p][c] = x;
+      }
+    __syncthreads();
+    const c128 pv = A[k][k];
+    const double den = pv.x * pv.x + pv.y * pv.y;
+    const c128 rp = make_double2(pv.x / den, -pv.y / den);
+    __syncthreads();
+    for (int c = t; c < W; c += 64) A[k][c] = cmul(A[k][c], rp);
+    if (t < D) f[t] = A[t][k];
+    __syncthreads();
+    for (int idx = t; idx < D * W; idx += 64) {
+      const int r = idx / W, c = idx % W;
+      if (r != k) A[r][c] = cfma(make_double2(-f[r].x, -f[r].y), A[k][c], A[r][c]);
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < D * D; idx += 64) M[D * D + idx] = A[idx / D][D + idx % D];
+  if (t == 0) {
+    double n0 = 0.0, n1 = 0.0;
+    bool finite = true;
+    for (int c = 0; c < D; c++) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int r = 0; r < D; r++) {
+        s0 += hypot(M[r * D + c].x, M[r * D + c].y);
+        s1 += hypot(A[r][D + c].x, A[r][D + c].y);
+      }
+      finite = finite && (s0 < HUGE_VAL) && (s1 < HUGE_VAL);  // false for inf and NaN
+      n0 = fmax(n0, s0);
+      n1 = fmax(n1, s1);
+    }
+    const double kappa = finite ? n0 * n1 : HUGE_VAL;
+    atomicMax(kappa_bits, (unsigned long long)__double_as_longlong(kappa));
+  }
+}
+
 __global__ void k_build_one(DRecipe r, const c128 *__restrict__ cdata, c128 *out) {
   if (threadIdx.x == 0) build_recipe(r, nullptr, cdata, nullptr, out);
 }
@@ -723,6 +795,13 @@ hipError_t launch_assemble(const DGate *gates, const DDeriv *derivs, int n_gates
   if (B <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_assemble, dim3((n_gates + 2 + 63) / 64, B), dim3(64), 0, st, gates, derivs, n_gates, prog,
                      mats, B, mats0);
+  return hipGetLastError();
+}
+
+hipError_t launch_invert(const DInv *inv, int n_inv, c128 *const *mats, int B, c128 *mats0,
+                         unsigned long long *kappa_bits, hipStream_t st) {
+  if (n_inv <= 0 || B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_invert, dim3(n_inv, B), dim3(64), 0, st, inv, mats, mats0, kappa_bits);
   return hipGetLastError();
 }
 

@@ -1035,6 +1035,10 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
 // J.b); MODE 1: noiseless adjoint (Alg. 2: Phi uncomputed in J.a, Psi in J.b);
 // MODE 2: noisy adjoint (Sec. 3.5): J.a holds Phi at the pass start and is
 // only read; Phi before each op is recomputed in registers, Psi <- M^dagger Psi.
+// MODE 3: noisy adjoint in the inverse form (Alg. 2 applied to channels):
+// Phi <- M^{-1} Phi in place (the inverse superoperator is stored right after
+// M for ops flagged kInvFlag; other ops are unitary and use M^dagger), then
+// the derivative reductions, then Psi <- M^dagger Psi.
 
 template <int R, int MODE>
 __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOverride ov) {
@@ -1089,7 +1093,7 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
         const DGate &G = E.g;
         const int nd = G.nd & 0xff;
         const bool gen = G.nd & kGenFlag;
-        if constexpr (MODE == 1) {
+        if constexpr (MODE == 1 || MODE == 3) {
           auto grads = [&]() {
             if (E.pad >> 31) {  // one generator derivative, carried in the entry
               const double v = wave_sum<64>(rg_grad_gen<R>(a, b, E.pad & 0xff, G.r[0]));
@@ -1102,8 +1106,17 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
               if (lane == 0) red[Dd.local][wave] = v;
             }
           };
-          if (gen) grads();  // generator form: Phi after the op
-          rg_apply_op<R, true>(a, E, MT);
+          // generator form (pure states only): Phi after the op.  Mixed
+          // circuits carry matrix derivatives only, and a second call site of
+          // the reductions makes MODE 3 spill registers.
+          if (MODE == 1 && gen) grads();
+          if (MODE == 3 && (G.nd & kInvFlag)) {
+            DOp Ei = E;
+            Ei.g.mat += G.kind == GK_DENSE4 ? 256 : 16;
+            rg_apply_op<R, false>(a, Ei, MT);
+          } else {
+            rg_apply_op<R, true>(a, E, MT);
+          }
           if (!gen) grads();
         } else {
           if (nd > 0) {
@@ -1125,7 +1138,7 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
       if (act) {
 #pragma unroll
         for (int j = 0; j < NR; j++) {
-          if constexpr (MODE == 1) stg(&A[off[j]], a[j]);
+          if constexpr (MODE == 1 || MODE == 3) stg(&A[off[j]], a[j]);
           stg(&Bv[off[j]], b[j]);
         }
       }

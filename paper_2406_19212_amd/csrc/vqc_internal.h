@@ -44,6 +44,9 @@ enum GateKind : int8_t {
 // DGate.nd: derivative count in the low byte; this bit set when the op's
 // derivatives are generator kinds (taken on Phi before the op is undone)
 constexpr int kGenFlag = 0x100;
+// DGate.nd: the op is not unitary (a channel, or a fused run holding one);
+// its inverse superoperator is stored right after its matrix
+constexpr int kInvFlag = 0x200;
 
 // Shear record of a rotation kind.  Rotation i by angle p (cos p = C,
 // sin p = S) is stored as a = -S/(1+C), b = S with C >= 0; an angle with
@@ -114,6 +117,12 @@ struct DPass {
   const DGate *gates;
   const DDeriv *derivs;
   const int32_t *vslot;   // gslot of pass-local derivative slot v
+};
+
+// a non-unitary op's matrix to invert (inverse-form noisy adjoint)
+struct DInv {
+  int32_t mat;  // matrix offset (c128 units); the inverse goes to mat + dim^2
+  int32_t dim;  // 4 or 16
 };
 
 // one (item, pass) of a launch
@@ -210,6 +219,8 @@ hipError_t launch_build_mats(const DRecipe *rec, int n_rec, const c128 *cdata, c
 hipError_t launch_build_one(const DRecipe &r, const c128 *cdata, c128 *out, hipStream_t st);
 hipError_t launch_assemble(const DGate *gates, const DDeriv *derivs, int n_gates, int prog, c128 *const *mats,
                            int B, c128 *mats0, hipStream_t st);
+hipError_t launch_invert(const DInv *inv, int n_inv, c128 *const *mats, int B, c128 *mats0,
+                         unsigned long long *kappa_bits, hipStream_t st);
 hipError_t launch_init_batched(c128 *const *ptrs, const uint64_t *sizes, int B, uint64_t max_n, hipStream_t st);
 int64_t expect_units(int nbits_iter);
 hipError_t launch_expect(const DEJob *jobs, int n_jobs, int64_t total, const DTerm *terms, int nt, hipStream_t st);

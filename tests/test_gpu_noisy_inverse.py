@@ -1,0 +1,108 @@
+"""Noisy gradient by Alg. 2 in its inverse form (Phi <- M^{-1} Phi,
+Psi <- M^dagger Psi, two states) against the oracle's inverse form, the
+stored-state gradient and the condition-number guard."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2406_19212_amd import Circuit, State
+from paper_2406_19212_amd import workloads as W
+from paper_2406_19212_amd.binding import VQCError
+from paper_2406_19212_amd.workloads import Op
+
+pytestmark = pytest.mark.gpu
+AMP_TOL, GRAD_TOL = 1e-12, 1e-10
+
+
+def maxdiff(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) if np.size(a) else 0.0
+
+
+def _run(n, ops, th, terms, max_cond=0.0):
+    c = Circuit(n, ops, mixed=True, n_params=len(th))
+    st = State(n, mixed=True)
+    tht = torch.tensor(th, device="cuda")
+    c.apply(st, tht)
+    g, e = c.backward_inverse(tht, st, terms, max_cond=max_cond)
+    return c, st, tht, g.cpu().numpy(), e
+
+
+@pytest.mark.parametrize("n,layers,p", [(3, 2, (0.02, 0.03, 0.05)), (5, 3, (0.1, 0.2, 0.15)),
+                                         (6, 4, (1e-3, 1e-3, 1e-2))])
+def test_inverse_form_matches_oracle(n, layers, p):
+    ops, th = W.noisy_brickwall(n, layers, 60 + n, p1=p[0], gamma=p[1], p2=p[2])
+    terms = W.zz(0, 1) + [W.pauli_string({n - 1: "x"}, 0.4)]
+    c, st, tht, g, e = _run(n, ops, th, terms)
+    e_ref, g_ref, phi_ref = oracle.grad_mixed_inverse(n, ops, th, terms)
+    print("inverse form n=%d: |dE|=%.2e |dg|=%.2e" % (n, abs(e - e_ref), maxdiff(g, g_ref)))
+    assert abs(e - e_ref) < AMP_TOL
+    assert maxdiff(g, g_ref) < GRAD_TOL
+    # Phi is walked back to |0..0><0..0| in place
+    assert maxdiff(st.numpy(), phi_ref) < AMP_TOL
+    # the stored-state form on the GPU gives the same gradient
+    st2 = State(n, mixed=True)
+    c.apply(st2, tht)
+    g2, _ = c.backward(tht, st2, terms)
+    assert maxdiff(g, g2.cpu().numpy()) < GRAD_TOL
+
+
+def test_inverse_form_every_op_kind():
+    """Unitary halves (structured kinds), fused runs with and without
+    channels, general Kraus channels on one and two qubits."""
+    n = 5
+    rng = np.random.default_rng(71)
+    ops, P = [], 0
+    for layer in range(3):
+        for q in range(n):
+            ops.append(Op("rx", (q,), (0.0,), (P,)))
+            P += 1
+            if q % 2 == 0:
+                ops.append(Op("amplitude_damping", (q,), (0.05 + 0.02 * q,)))
+            ops.append(Op("s" if q % 3 else "sx", (q,)))
+        ops.append(Op("cnot", (layer % n, (layer + 2) % n)))
+        ops.append(Op("fsim", (1, 3), (0.3, 0.7, 0, 0, 0)))
+        ops.append(Op("ry", (2,), (0.0,), (P,)))
+        P += 1
+        ops.append(Op("kraus", (4,), (), (), W.random_kraus(2, 3, 80 + layer)))
+        ops.append(Op("kraus", (0, 2), (), (), W.random_kraus(4, 2, 90 + layer)))
+        ops.append(Op("phase_damping", (1,), (0.2,)))
+        ops.append(Op("crz", (3, 4), (0.0,), (P,)))
+        P += 1
+        ops.append(Op("depolarizing2", (4, 1), (0.05,)))
+    th = rng.uniform(-np.pi, np.pi, P)
+    terms = W.tfim(n, 0.6)
+    c, st, tht, g, e = _run(n, ops, th, terms)
+    e_ref, g_ref, phi_ref = oracle.grad_mixed_inverse(n, ops, th, terms)
+    assert abs(e - e_ref) < AMP_TOL
+    assert maxdiff(g, g_ref) < GRAD_TOL
+    assert maxdiff(st.numpy(), phi_ref) < 1e-11
+
+
+def test_condition_guard():
+    n = 3
+    ops, th = W.noisy_brickwall(n, 2, 64, p1=0.05, gamma=0.05, p2=0.05)
+    terms = W.zz(0, 1)
+    # a singular channel: nothing is touched, the status names the cause
+    bad = ops + [Op("amplitude_damping", (1,), (1.0,))]
+    c = Circuit(n, bad, mixed=True, n_params=len(th))
+    st = State(n, mixed=True)
+    tht = torch.tensor(th, device="cuda")
+    c.apply(st, tht)
+    before = st.numpy().copy()
+    with pytest.raises(VQCError) as ei:
+        c.backward_inverse(tht, st, terms)
+    assert ei.value.status == -11
+    assert np.array_equal(st.numpy(), before)
+    # a nearly singular one passes or fails by the bound
+    near = ops + [Op("depolarizing", (2,), (0.999,))]
+    c2 = Circuit(n, near, mixed=True, n_params=len(th))
+    st2 = State(n, mixed=True)
+    c2.apply(st2, tht)
+    with pytest.raises(VQCError):
+        c2.backward_inverse(tht, st2, terms, max_cond=100.0)
+    g, e = c2.backward_inverse(tht, st2, terms, max_cond=1e6)
+    e_ref, g_ref, _ = oracle.grad_mixed_inverse(n, near, th, terms)
+    # rounding grows with the condition number (1e3 here)
+    assert maxdiff(g.cpu().numpy(), g_ref) < 1e-9
+    assert abs(e - e_ref) < AMP_TOL
