@@ -13,10 +13,15 @@ Also reported:
 * the 20-qubit batched VQE gradient workload (64 parameter sets, 1600
   parameters, transverse-field Ising energy): gradients/s batched versus
   the same library run item by item;
+* the noisy gradient (brick-wall circuit with one-qubit depolarizing and
+  amplitude damping after every rotation, two-qubit depolarizing after every
+  CZ, 20 layers) at n = 12 in both forms: states before each op recomputed
+  from checkpoints, and Alg. 2 with channel inverses (two states); at n = 8
+  also the oracle's inverse form on the host;
 * cpu_baseline: the plain C oracle on this host, timed on a bounded prefix of
   the same 28-qubit circuit.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-vqe]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-vqe] [--no-noisy]
        python bench.py --copy-calibration   (only a plain device copy of known
                                               size, for scaling HBM counters)
 """
@@ -46,6 +51,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-vqe", action="store_true")
+    ap.add_argument("--no-noisy", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
@@ -154,6 +160,49 @@ def vqe_batched(torch, steps):
     return out
 
 
+def noisy_backward(torch, with_cpu):
+    """Noisy brick-wall gradient (20 layers, <Z0 Z1>): checkpointed versus
+    inverse form on the GPU at n = 12, and at n = 8 beside the oracle."""
+    from paper_2406_19212_amd import Circuit, State
+    from paper_2406_19212_amd import workloads as W
+    out = {"workload": "noisy-brickwall-20layers-zz01", "unit": "ms per gradient"}
+    terms = W.zz(0, 1)
+    for n in (12, 8):
+        ops, th = W.noisy_brickwall(n, 20, W.CONFIG_SEED[3] + n)
+        c = Circuit(n, ops, mixed=True, n_params=len(th))
+        tht = torch.tensor(th, device="cuda")
+        st = State(n, mixed=True)
+        rec = {"ops": len(ops), "params": len(th), "passes": c.stats()["n_passes"]}
+        res = {}
+        for form in ("checkpoint", "inverse"):
+            best = None
+            for _ in range(3):
+                st.reset()
+                c.apply(st, tht)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if form == "checkpoint":
+                    g, _ = c.backward(tht, st, terms, energy=False)
+                else:
+                    g, _ = c.backward_inverse(tht, st, terms, energy=False)
+                torch.cuda.synchronize()
+                dt = 1e3 * (time.perf_counter() - t0)
+                best = dt if best is None else min(best, dt)
+            rec[form + "_ms"] = round(best, 3)
+            res[form] = g.cpu().numpy().copy()
+        rec["max_grad_diff"] = float(np.max(np.abs(res["checkpoint"] - res["inverse"])))
+        if n == 8 and with_cpu:
+            import oracle
+            t0 = time.perf_counter()
+            _, g_ref, _ = oracle.grad_mixed_inverse(n, ops, th, terms)
+            rec["oracle_inverse_ms"] = round(1e3 * (time.perf_counter() - t0), 1)
+            rec["oracle_threads"] = oracle.get_threads()
+            rec["max_diff_vs_oracle"] = float(np.max(np.abs(res["inverse"] - g_ref)))
+        out["n%d" % n] = rec
+        del st, c
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -221,6 +270,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_vqe:
         rec["vqe_batched"] = vqe_batched(torch, max(1, args.steps // 5))
+        torch.cuda.empty_cache()
+    if not args.no_noisy:
+        rec["noisy_backward"] = noisy_backward(torch, not args.no_cpu)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_seconds)
