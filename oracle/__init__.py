@@ -17,6 +17,9 @@ What each function follows:
 * ``grad_mixed_inverse``: the same gradient by Alg. 2 with channel inverses
   for Phi (Sec. 3.3: the inverse form extends Alg. 2 to channels) and the
   adjoint superoperator for Psi; ``invert`` is its Gauss-Jordan step.
+* ``measure`` / ``sample``: measure! of Sec. 2.4 (outcome, exact probability,
+  collapse in place) and bitstring sampling by the inverse cumulative
+  distribution over basis states.
 * ``lanczos`` (in ``oracle.lanczos``) and ``mlp`` (in ``oracle.mlp``) cover
   the ground energy and the surrogate network, which the paper does not define.
 """
@@ -75,6 +78,8 @@ def lib():
         _lib.or_grad_mixed_inverse.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P,
                                                P, ctypes.c_int, P, P, P]
         _lib.or_invert.argtypes = [ctypes.c_int, P, P]
+        _lib.or_measure.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, P, P]
+        _lib.or_sample.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
         _lib.or_set_threads.argtypes = [ctypes.c_int]
         _lib.or_get_threads.restype = ctypes.c_int
     return _lib
@@ -290,3 +295,23 @@ def grad_mixed_inverse(n: int, ops, theta, terms, init=None, n_params=None):
     if rc:
         raise ValueError("oracle grad_mixed_inverse failed (%d)" % rc)
     return float(e[0]), grad[:P], phi
+
+
+def measure(state: np.ndarray, n: int, q: int, u: float, mixed: bool = False):
+    """In place: measure qubit q with the uniform number u; returns (outcome, prob)."""
+    assert state.dtype == np.complex128 and state.flags.c_contiguous
+    o = ctypes.c_int()
+    p = ctypes.c_double()
+    if lib().or_measure(_ptr(state), n, int(mixed), int(q), float(u), ctypes.byref(o), ctypes.byref(p)):
+        raise ValueError("state of zero norm")
+    return o.value, p.value
+
+
+def sample(state: np.ndarray, n: int, u, mixed: bool = False) -> np.ndarray:
+    """Basis-state samples for the uniform numbers u (inverse cumulative distribution)."""
+    st = np.ascontiguousarray(state, np.complex128)
+    uu = np.ascontiguousarray(u, np.float64)
+    out = np.zeros(max(1, uu.size), np.int64)
+    if lib().or_sample(_ptr(st), n, int(mixed), int(uu.size), _ptr(uu), _ptr(out)):
+        raise ValueError("state of zero norm")
+    return out[: uu.size]

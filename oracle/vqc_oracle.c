@@ -634,6 +634,65 @@ done:
   return rc;
 }
 
+/* ------------------------------------------------- measurement, sampling */
+
+/* weight of basis state x: |psi_x|^2, or rho[x][x] (real part) for vec(rho) */
+static double basis_weight(const cplx *st, int n, int mixed, uint64_t x) {
+  uint64_t D = 1ull << n;
+  if (mixed) return creal(st[x + D * x]);
+  return creal(st[x]) * creal(st[x]) + cimag(st[x]) * cimag(st[x]);
+}
+
+/* measure!(state, q) of Sec. 2.4: the probability masses s0, s1 of bit q
+ * (normalised by their sum), outcome 0 when u < p0 (u uniform in [0,1)
+ * supplied by the caller), then the state collapsed onto the outcome and
+ * renormalised in place: psi -> P psi / sqrt(s), rho -> P rho P / s.
+ * Returns -1 for a state of zero norm. */
+int or_measure(cplx *st, int n, int mixed, int q, double u, int *outcome, double *prob) {
+  uint64_t D = 1ull << n, len = mixed ? D * D : D;
+  double s0 = 0, s1 = 0;
+  for (uint64_t x = 0; x < D; x++) {
+    double w = basis_weight(st, n, mixed, x);
+    if ((x >> q) & 1) s1 += w; else s0 += w;
+  }
+  double tot = s0 + s1;
+  if (!(tot > 0)) return -1;
+  int o = u < s0 / tot ? 0 : 1;
+  double so = o ? s1 : s0;
+  *outcome = o;
+  *prob = so / tot;
+  double scale = mixed ? 1.0 / so : 1.0 / sqrt(so);
+  for (uint64_t i = 0; i < len; i++) {
+    int keep = (int)((i >> q) & 1) == o;
+    if (mixed) keep = keep && (int)((i >> (q + n)) & 1) == o;
+    st[i] = keep ? st[i] * scale : 0;
+  }
+  return 0;
+}
+
+/* Bitstring sampling by the inverse of the cumulative distribution over basis
+ * states in index order: sample k is the first x with C(x) > u_k C(D-1),
+ * C(x) = sum_{y <= x} weight(y).  Returns -1 for a state of zero norm. */
+int or_sample(const cplx *st, int n, int mixed, int count, const double *u, int64_t *out) {
+  uint64_t D = 1ull << n;
+  double *C = malloc(D * sizeof(double));
+  if (!C) return -100;
+  double c = 0;
+  for (uint64_t x = 0; x < D; x++) { c += basis_weight(st, n, mixed, x); C[x] = c; }
+  if (!(c > 0)) { free(C); return -1; }
+  for (int k = 0; k < count; k++) {
+    double t = u[k] * c;
+    uint64_t lo = 0, hi = D - 1;
+    while (lo < hi) {
+      uint64_t mid = lo + (hi - lo) / 2;
+      if (C[mid] > t) hi = mid; else lo = mid + 1;
+    }
+    out[k] = (int64_t)lo;
+  }
+  free(C);
+  return 0;
+}
+
 /* ----------------------------------------------------------------- misc */
 
 void or_set_threads(int t) {

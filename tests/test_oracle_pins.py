@@ -573,3 +573,88 @@ def test_adjoint_mixed_inverse_from_init_and_singular_channel(oracle_mod):
     bad = ops + [NS(name="amplitude_damping", qubits=(1,), params=(1.0,), var=(), data=None)]
     with pytest.raises(ValueError):
         oracle_mod.grad_mixed_inverse(n, bad, th, terms)
+
+
+# ------------------------------------------------- measurement and sampling
+
+def test_measure_listing4_golden(oracle_mod):
+    from types import SimpleNamespace as NS
+    L4 = json.load(open(GOLD))["listing4_probability"]
+    ops = [NS(name=a, qubits=tuple(b), params=tuple(c), var=(), data=None) for a, b, c in L4["circuit"]]
+    q = L4["measured_qubit"]
+    for u, want_o in ((0.9, 1), (0.05, 0)):
+        st = oracle_mod.run(2, ops)
+        o, p = oracle_mod.measure(st, 2, q, u)
+        assert o == want_o
+        assert abs(p - (L4["p_outcome_1"] if o else 1 - L4["p_outcome_1"])) < 1e-15
+        # CNOT copied qubit 0 into qubit 1: the collapse leaves |00> or |11>
+        want = np.zeros(4, complex)
+        want[3 if o else 0] = 1
+        assert np.max(np.abs(np.abs(st) - np.abs(want))) < 1e-15
+
+
+def test_measure_product_state_and_repeat(oracle_mod):
+    from types import SimpleNamespace as NS
+    n, ang = 3, (0.3, 2.2, 1.1)
+    ops = [NS(name="ry", qubits=(q,), params=(a,), var=(), data=None) for q, a in enumerate(ang)]
+    st = oracle_mod.run(n, ops)
+    o, p = oracle_mod.measure(st, n, 1, 0.5)
+    p1 = math.sin(ang[1] / 2) ** 2  # Ry(t)|0> = cos(t/2)|0> + sin(t/2)|1>
+    assert o == (0 if 0.5 < 1 - p1 else 1)
+    assert abs(p - (p1 if o else 1 - p1)) < 1e-15
+    assert abs(np.sum(np.abs(st) ** 2) - 1) < 1e-15
+    # the other qubits are untouched: their marginals keep cos^2 / sin^2
+    for q in (0, 2):
+        m1 = sum(abs(st[x]) ** 2 for x in range(8) if (x >> q) & 1)
+        assert abs(m1 - math.sin(ang[q] / 2) ** 2) < 1e-15
+    # measuring again gives the same outcome with certainty
+    o2, p2 = oracle_mod.measure(st, n, 1, 0.999999)
+    assert o2 == o and p2 == 1.0
+
+
+def test_measure_chain_reproduces_born_rule(oracle_mod):
+    # forcing each outcome in turn, the product of the returned probabilities
+    # over all qubits is |psi_x|^2 (brute force over every x)
+    n = 4
+    psi = W.random_state(n, 21)
+    for x in range(1 << n):
+        st = psi.copy()
+        prob = 1.0
+        for q in range(n):
+            b = (x >> q) & 1
+            o, p = oracle_mod.measure(st, n, q, 0.999999999 if b else 0.0)
+            assert o == b
+            prob *= p
+        assert abs(prob - abs(psi[x]) ** 2) < 1e-14
+        assert abs(abs(st[x]) - 1) < 1e-12
+
+
+def test_measure_mixed_matches_pure(oracle_mod):
+    n = 3
+    psi = W.random_state(n, 22)
+    rho = np.outer(psi, psi.conj())
+    for q, u in ((0, 0.3), (2, 0.8)):
+        sp, sm = psi.copy(), vec(rho)
+        op_, pp = oracle_mod.measure(sp, n, q, u)
+        om, pm = oracle_mod.measure(sm, n, q, u, mixed=True)
+        assert op_ == om and abs(pp - pm) < 1e-15
+        assert np.max(np.abs(unvec(sm, n) - np.outer(sp, sp.conj()))) < 1e-15
+        psi, rho = sp, unvec(sm, n)
+
+
+def test_sample_stratified_counts(oracle_mod):
+    # with u_k = (k + 1/2)/K the inverse-CDF sampler returns x exactly
+    # floor or ceil of K p_x times (brute force over every x)
+    n, K = 5, 4096
+    psi = W.random_state(n, 23)
+    u = (np.arange(K) + 0.5) / K
+    s = oracle_mod.sample(psi, n, u)
+    p = np.abs(psi) ** 2
+    cnt = np.bincount(s, minlength=1 << n)
+    assert np.all(np.abs(cnt - K * p) <= 1.0 + 1e-9)
+    assert np.all(np.diff(s) >= 0)  # monotone in u
+    # mixed |psi><psi| gives the same samples; a basis state gives only itself
+    assert np.array_equal(oracle_mod.sample(vec(np.outer(psi, psi.conj())), n, u, mixed=True), s)
+    e = np.zeros(1 << n, complex)
+    e[13] = 1j
+    assert np.all(oracle_mod.sample(e, n, u) == 13)
