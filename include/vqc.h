@@ -197,6 +197,30 @@ vqc_status vqc_norm(vqc_state s, double *out_host);
  * idx_host: host int64 indices in [0, 2^n). */
 vqc_status vqc_gather(vqc_state s, int count, const int64_t *idx_host, vqc_c128 *out_host);
 
+/* measure!(state, i) of Sec. 2.4: measure qubit `qubit` (0-based) of a PURE or
+ * MIXED state and collapse it in place.  The probability masses s0, s1 of
+ * the qubit's two values are summed on the device (|psi_x|^2, resp. the
+ * diagonal of rho, over basis states x); outcome_out = 0 when u < s0/(s0+s1),
+ * else 1, with u a caller-supplied uniform number in [0,1); prob_out = the
+ * outcome's exact probability s_o/(s0+s1).  The state becomes P psi / sqrt(s_o)
+ * (PURE) or P rho P / s_o (MIXED), P the projector on the outcome, so it has
+ * unit norm (resp. trace) afterwards.  Synchronises the stream once.  Errors:
+ * VQC_ERR_QUBIT, VQC_ERR_ARG (u outside [0,1), a state of zero norm: then
+ * the state is unchanged), VQC_ERR_NONFINITE. */
+vqc_status vqc_measure(vqc_state s, int qubit, double u, int *outcome_out, double *prob_out);
+
+/* Bitstring sampling (the random-circuit sampling use of Sec. 1): for each
+ * of `count` caller-supplied uniform numbers u_host[k] in [0,1), out_host[k]
+ * is the first basis state x (index order) whose cumulative probability
+ * C(x) = sum_{y <= x} w(y) exceeds u_k C(2^n - 1), with w = |psi_y|^2 (PURE)
+ * or rho[y][y] (MIXED).  Cumulative sums are taken per block of 4096 basis
+ * states and then within a block, so an outcome can differ from a plain
+ * left-to-right sum only where u_k C lies within rounding of a boundary; a
+ * returned x always has w(x) > 0.  The state is not changed.  Host arrays;
+ * synchronises.  Errors: VQC_ERR_ARG (u outside [0,1), zero norm),
+ * VQC_ERR_NONFINITE. */
+vqc_status vqc_sample(vqc_state s, int count, const double *u_host, int64_t *out_host);
+
 /* ---------------------------------------------------------------- circuits */
 
 /* Build a circuit (QCircuit, Sec. 2.3) for states of `n_qubits` and `kind`,

@@ -97,6 +97,21 @@ class State:
         check(lib().vqc_gather(self.h, idx.size, idx.ctypes.data, out.ctypes.data), "vqc_gather")
         return out
 
+    def measure(self, qubit: int, u: float):
+        """measure!(state, qubit): collapse in place; returns (outcome, probability).
+        u is the caller's uniform number in [0, 1)."""
+        o = ctypes.c_int()
+        p = ctypes.c_double()
+        check(lib().vqc_measure(self.h, int(qubit), float(u), ctypes.byref(o), ctypes.byref(p)), "vqc_measure")
+        return o.value, p.value
+
+    def sample(self, u) -> np.ndarray:
+        """Basis-state samples (int64) for the uniform numbers u in [0, 1)."""
+        uu = np.ascontiguousarray(np.asarray(u, np.float64).ravel())
+        out = np.zeros(max(1, uu.size), np.int64)
+        check(lib().vqc_sample(self.h, uu.size, uu.ctypes.data, out.ctypes.data), "vqc_sample")
+        return out[: uu.size]
+
     def numpy(self) -> np.ndarray:
         return self.tensor.cpu().numpy()
 

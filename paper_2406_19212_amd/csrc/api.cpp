@@ -1469,6 +1469,59 @@ vqc_status vqc_gather(vqc_state s, int count, const int64_t *idx, vqc_c128 *out)
   return VQC_OK;
 }
 
+vqc_status vqc_measure(vqc_state s, int qubit, double u, int *outcome, double *prob) {
+  if (!s || !outcome || !prob) return VQC_ERR_ARG;
+  if (qubit < 0 || qubit >= s->n) return VQC_ERR_QUBIT;
+  if (!is_finite_d(u)) return VQC_ERR_NONFINITE;
+  if (u < 0.0 || u >= 1.0) return VQC_ERR_ARG;
+  const int mixed = s->kind == VQC_MIXED;
+  const int64_t m = prob_chunks(s->n);
+  VQC_TRY(s->red.ensure((size_t)(m + 1) * sizeof(double2) + 256));
+  double2 *part = s->red.as<double2>();
+  double2 *res = part + m;
+  VQC_TRY(launch_bit_mass(s->buf, s->n, mixed, qubit, part, res, s->stream));
+  double2 h;
+  VQC_TRY(hipMemcpyAsync(&h, res, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+  VQC_TRY(hipStreamSynchronize(s->stream));
+  const double tot = h.x + h.y;
+  if (!is_finite_d(tot)) return VQC_ERR_NONFINITE;
+  if (!(tot > 0.0)) return VQC_ERR_ARG;
+  const int o = u < h.x / tot ? 0 : 1;
+  const double so = o ? h.y : h.x;
+  *outcome = o;
+  *prob = so / tot;
+  const double scale = mixed ? 1.0 / so : 1.0 / std::sqrt(so);
+  VQC_TRY(launch_collapse(s->buf, state_len(s->kind, s->n), s->n, mixed, qubit, o, scale, s->stream));
+  return VQC_OK;
+}
+
+vqc_status vqc_sample(vqc_state s, int count, const double *u, int64_t *out) {
+  if (!s || count < 0 || (count > 0 && (!u || !out))) return VQC_ERR_ARG;
+  for (int k = 0; k < count; k++) {
+    if (!is_finite_d(u[k])) return VQC_ERR_NONFINITE;
+    if (u[k] < 0.0 || u[k] >= 1.0) return VQC_ERR_ARG;
+  }
+  const int mixed = s->kind == VQC_MIXED;
+  const int64_t m = prob_chunks(s->n);
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o_p = al(m * sizeof(double)), o_u = o_p + al(m * sizeof(double));
+  const size_t o_o = o_u + al(std::max(1, count) * sizeof(double));
+  VQC_TRY(s->red.ensure(o_o + al(std::max(1, count) * sizeof(int64_t))));
+  char *base = s->red.as<char>();
+  double *mass = reinterpret_cast<double *>(base), *pref = reinterpret_cast<double *>(base + o_p);
+  double *du = reinterpret_cast<double *>(base + o_u);
+  int64_t *dout = reinterpret_cast<int64_t *>(base + o_o);
+  if (count > 0) VQC_TRY(hipMemcpyAsync(du, u, count * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  VQC_TRY(launch_sample(s->buf, s->n, mixed, mass, pref, du, count, dout, s->stream));
+  double total = 0.0;
+  VQC_TRY(hipMemcpyAsync(&total, pref + (m - 1), sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  if (count > 0) VQC_TRY(hipMemcpyAsync(out, dout, count * sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
+  VQC_TRY(hipStreamSynchronize(s->stream));
+  if (!is_finite_d(total)) return VQC_ERR_NONFINITE;
+  if (!(total > 0.0)) return VQC_ERR_ARG;
+  return VQC_OK;
+}
+
 // -------------------------------------------------------------- circuits
 
 vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops, const vqc_op *ops, int n_params,

@@ -670,6 +670,153 @@ __global__ void k_copy(c128 *__restrict__ dst, const c128 *__restrict__ src, uin
     dst[i] = src[i];
 }
 
+// ------------------------------------------------ measurement and sampling
+
+constexpr int kPChunk = 4096;  // basis states per probability block (256 lanes x 16)
+
+// probability weight of basis state x: |psi_x|^2, or rho[x][x] on vec(rho)
+__device__ __forceinline__ double basis_weight(const c128 *__restrict__ v, uint64_t x, int n, int mixed) {
+  if (mixed) return v[x * ((1ull << n) + 1)].x;
+  const c128 a = v[x];
+  return fma(a.x, a.x, a.y * a.y);
+}
+
+// measure! (Sec. 2.4): per block of kPChunk basis states, the probability
+// mass with bit q clear (.x) and set (.y), in a fixed summation order
+__global__ void __launch_bounds__(256) k_bit_mass(const c128 *__restrict__ v, int n, int mixed, int q,
+                                                  double2 *__restrict__ part) {
+  __shared__ double2 sh[4];
+  const uint64_t D = 1ull << n, base = (uint64_t)blockIdx.x * kPChunk;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = 0; k < kPChunk / 256; k++) {
+    const uint64_t x = base + (uint64_t)k * 256 + threadIdx.x;
+    if (x < D) {
+      const double w = basis_weight(v, x, n, mixed);
+      if ((x >> q) & 1) acc.y += w;
+      else acc.x += w;
+    }
+  }
+  const double2 r = block_sum2(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+// out[0] = sum of m pairs in a fixed order (one block)
+__global__ void __launch_bounds__(256) k_sum2(const double2 *__restrict__ in, int64_t m, double2 *__restrict__ out) {
+  __shared__ double2 sh[4];
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t i = threadIdx.x; i < m; i += 256) {
+    acc.x += in[i].x;
+    acc.y += in[i].y;
+  }
+  const double2 r = block_sum2(acc, sh);
+  if (threadIdx.x == 0) out[0] = r;
+}
+
+// collapse onto bit q = outcome: psi -> P psi * scale (scale = 1/sqrt(p)),
+// vec(rho) -> (P (x) P) vec(rho) * scale (scale = 1/p)
+__global__ void __launch_bounds__(256) k_collapse(c128 *__restrict__ v, uint64_t len, int n, int mixed, int q,
+                                                  int outcome, double scale) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (uint64_t)gridDim.x * 256) {
+    bool keep = (int)((i >> q) & 1) == outcome;
+    if (mixed) keep = keep && (int)((i >> (q + n)) & 1) == outcome;
+    const c128 a = v[i];
+    v[i] = keep ? make_double2(a.x * scale, a.y * scale) : make_double2(0.0, 0.0);
+  }
+}
+
+// sampling, step 1: the probability mass of each block of kPChunk basis states
+__global__ void __launch_bounds__(256) k_chunk_mass(const c128 *__restrict__ v, int n, int mixed,
+                                                    double *__restrict__ mass) {
+  __shared__ double2 sh[4];
+  const uint64_t D = 1ull << n, base = (uint64_t)blockIdx.x * kPChunk;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = 0; k < kPChunk / 256; k++) {
+    const uint64_t x = base + (uint64_t)k * 256 + threadIdx.x;
+    if (x < D) acc.x += basis_weight(v, x, n, mixed);
+  }
+  const double2 r = block_sum2(acc, sh);
+  if (threadIdx.x == 0) mass[blockIdx.x] = r.x;
+}
+
+// step 2: inclusive prefix of the m chunk masses (one block: each thread sums
+// a contiguous segment, thread 0 scans the segment sums, each thread then
+// writes its segment's running sums)
+__global__ void __launch_bounds__(256) k_prefix(const double *__restrict__ mass, int64_t m, double *__restrict__ pref) {
+  __shared__ double seg[256];
+  const int t = threadIdx.x;
+  const int64_t per = (m + 255) / 256, i0 = t * per, i1 = i0 + per < m ? i0 + per : m;
+  double s = 0.0;
+  for (int64_t i = i0; i < i1; i++) s += mass[i];
+  seg[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    double c = 0.0;
+    for (int k = 0; k < 256; k++) {
+      const double x = seg[k];
+      seg[k] = c;
+      c += x;
+    }
+  }
+  __syncthreads();
+  double c = seg[t];
+  for (int64_t i = i0; i < i1; i++) {
+    c += mass[i];
+    pref[i] = c;
+  }
+}
+
+// step 3: one wave per sample.  The wave finds the first chunk whose running
+// mass exceeds u * total, then, inside it, each lane sums 64 consecutive
+// weights, a wave scan locates the lane holding the target and that lane
+// walks its weights.  Rounding can leave the target past the chunk's last
+// weight; the sample is then the chunk's last basis state of nonzero weight.
+__global__ void __launch_bounds__(256) k_sample(const c128 *__restrict__ v, int n, int mixed,
+                                                const double *__restrict__ pref, int64_t m,
+                                                const double *__restrict__ u, int count, int64_t *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= count) return;  // the whole wave leaves together
+  const uint64_t D = 1ull << n;
+  const double target = u[s] * pref[m - 1];
+  int64_t lo = 0, hi = m - 1;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (pref[mid] > target) hi = mid;
+    else lo = mid + 1;
+  }
+  const double r = target - (lo > 0 ? pref[lo - 1] : 0.0);
+  const uint64_t x0 = (uint64_t)lo * kPChunk + (uint64_t)lane * 64;
+  double w = 0.0;
+  for (int k = 0; k < 64; k++)
+    if (x0 + k < D) w += basis_weight(v, x0 + k, n, mixed);
+  double incl = w;
+  for (int off = 1; off < 64; off <<= 1) {
+    const double y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  double excl = __shfl_up(incl, 1, 64);
+  if (lane == 0) excl = 0.0;
+  unsigned long long hit = __ballot(incl > r);
+  const bool past = hit == 0;
+  if (past) hit = __ballot(w > 0.0);
+  if (hit == 0) return;  // no mass in the chunk (not reached: its prefix step is positive)
+  const int L = past ? 63 - __clzll(hit) : __ffsll((long long)hit) - 1;
+  if (lane == L) {
+    double c = excl;
+    int64_t pick = -1, last = -1;
+    for (int k = 0; k < 64 && x0 + k < D; k++) {
+      const double wk = basis_weight(v, x0 + k, n, mixed);
+      if (wk > 0.0) last = (int64_t)(x0 + k);
+      c += wk;
+      if (!past && c > r) {
+        pick = (int64_t)(x0 + k);
+        break;
+      }
+    }
+    out[s] = pick >= 0 ? pick : last;
+  }
+}
+
 __global__ void k_gather(const c128 *__restrict__ psi, const int64_t *__restrict__ idx, int count,
                          c128 *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -822,6 +969,31 @@ hipError_t launch_fill_zero(c128 *v, uint64_t N, hipStream_t st) {
 
 hipError_t launch_copy(c128 *dst, const c128 *src, uint64_t N, hipStream_t st) {
   hipLaunchKernelGGL(k_copy, dim3(grid_for(N, 256)), dim3(256), 0, st, dst, src, N);
+  return hipGetLastError();
+}
+
+int64_t prob_chunks(int n) { return ((int64_t(1) << n) + kPChunk - 1) / kPChunk; }
+
+hipError_t launch_bit_mass(const c128 *v, int n, int mixed, int q, double2 *part, double2 *out, hipStream_t st) {
+  const int64_t m = prob_chunks(n);
+  hipLaunchKernelGGL(k_bit_mass, dim3((unsigned)m), dim3(256), 0, st, v, n, mixed, q, part);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, st, part, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_collapse(c128 *v, uint64_t len, int n, int mixed, int q, int outcome, double scale,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_collapse, dim3(grid_for(len, 256)), dim3(256), 0, st, v, len, n, mixed, q, outcome, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const c128 *v, int n, int mixed, double *mass, double *pref, const double *u, int count,
+                         int64_t *out, hipStream_t st) {
+  const int64_t m = prob_chunks(n);
+  hipLaunchKernelGGL(k_chunk_mass, dim3((unsigned)m), dim3(256), 0, st, v, n, mixed, mass);
+  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(256), 0, st, mass, m, pref);
+  if (count > 0)
+    hipLaunchKernelGGL(k_sample, dim3((count + 3) / 4), dim3(256), 0, st, v, n, mixed, pref, m, u, count, out);
   return hipGetLastError();
 }
 

@@ -235,6 +235,12 @@ hipError_t launch_init_basis0(c128 *v, uint64_t N, hipStream_t st);
 hipError_t launch_fill_zero(c128 *v, uint64_t N, hipStream_t st);
 hipError_t launch_copy(c128 *dst, const c128 *src, uint64_t N, hipStream_t st);
 hipError_t launch_gather(const c128 *psi, const int64_t *idx, int count, c128 *out, hipStream_t st);
+int64_t prob_chunks(int n);  // blocks of basis states of the measurement / sampling kernels
+hipError_t launch_bit_mass(const c128 *v, int n, int mixed, int q, double2 *part, double2 *out, hipStream_t st);
+hipError_t launch_collapse(c128 *v, uint64_t len, int n, int mixed, int q, int outcome, double scale,
+                           hipStream_t st);
+hipError_t launch_sample(const c128 *v, int n, int mixed, double *mass, double *pref, const double *u, int count,
+                         int64_t *out, hipStream_t st);
 hipError_t launch_set_mat(c128 *dst, const c128 *m, int count, hipStream_t st);
 
 enum SingleKind { SK_DENSE1 = 0, SK_DIAG1, SK_PHASE1, SK_DENSE2, SK_DIAG2, SK_PHASE11, SK_FSIM, SK_CX, SK_CTRL };
