@@ -315,3 +315,57 @@ def sample(state: np.ndarray, n: int, u, mixed: bool = False) -> np.ndarray:
     if lib().or_sample(_ptr(st), n, int(mixed), int(uu.size), _ptr(uu), _ptr(out)):
         raise ValueError("state of zero norm")
     return out[: uu.size]
+
+
+def fuse_gates(ops, theta=None):
+    """fuse_gates of Sec. 2.3 on an op list (noiseless), applied until no
+    one-qubit gate sits next to a two-qubit gate on its qubit: a run of
+    one-qubit gates on a qubit is absorbed into the two-qubit gate before it
+    (U <- g U, in order), else into the one after it (U <- U g ... g');
+    every result is a general matrix evaluated at theta.
+    Returns [(qubits, row-major matrix)]."""
+    def mat(op):
+        params = list(getattr(op, "params", ()) or ())
+        var = list(getattr(op, "var", ()) or ())
+        params += [0.0] * (5 - len(params))
+        for k, v in enumerate(var):
+            if v is not None and v >= 0:
+                params[k] = float(theta[v])
+        return gate_matrix(op.name, tuple(op.qubits), tuple(params), getattr(op, "data", None))
+
+    def on_bit(g, t):  # 4x4 of g on local bit t (local index b0 + 2 b1)
+        return np.kron(np.eye(2), g) if t == 0 else np.kron(g, np.eye(2))
+
+    ops = list(ops)
+    nxt = [None] * len(ops)
+    seen = {}
+    for j in range(len(ops) - 1, -1, -1):  # seen[q]: next two-qubit op on q
+        qs = tuple(ops[j].qubits)
+        if len(qs) == 1:
+            nxt[j] = seen.get(qs[0])
+        else:
+            for q in qs:
+                seen[q] = j
+    out, last, pending = [], {}, {}
+    for j, op in enumerate(ops):
+        qs = tuple(op.qubits)
+        if op.name in CHANNELS:
+            raise ValueError("fuse_gates: noiseless circuits only")
+        G = mat(op)
+        if len(qs) == 1:
+            k = last.get(qs[0])
+            if k is not None and len(out[k][0]) == 2:
+                out[k][1] = on_bit(G, out[k][0].index(qs[0])) @ out[k][1]
+            elif nxt[j] is not None:
+                pending.setdefault(nxt[j], []).append(j)
+            else:
+                out.append([qs, G])
+                last[qs[0]] = len(out) - 1
+        else:
+            U = G
+            for pj in reversed(pending.get(j, [])):
+                U = U @ on_bit(mat(ops[pj]), qs.index(ops[pj].qubits[0]))
+            out.append([qs, U])
+            for q in qs:
+                last[q] = len(out) - 1
+    return [(tuple(q), M) for q, M in out]

@@ -658,3 +658,72 @@ def test_sample_stratified_counts(oracle_mod):
     e = np.zeros(1 << n, complex)
     e[13] = 1j
     assert np.all(oracle_mod.sample(e, n, u) == 13)
+
+
+# ------------------------------------------------------------ fuse_gates
+
+def _as_matrix_ops(fused):
+    from types import SimpleNamespace as NS
+    return [NS(name="matrix", qubits=q, params=(), var=(), data=M) for q, M in fused]
+
+
+@pytest.mark.parametrize("kind", ["brick", "hea", "rqc", "mixed_kinds"])
+def test_fuse_gates_preserves_the_state(oracle_mod, kind):
+    from types import SimpleNamespace as NS
+    rng = np.random.default_rng(5)
+    if kind == "brick":
+        n = 6
+        ops, th = W.brickwall(n, 4, 71)
+    elif kind == "hea":
+        n = 5
+        ops = W.hea(n, 3)
+        th = W.theta_uniform(72, 1, W.count_params(ops))[0]
+    elif kind == "rqc":
+        n = 9
+        ops, th = W.rqc_grid(3, 3, 6, 73), np.zeros(1)
+    else:
+        n = 4
+        names1 = ["x", "y", "z", "h", "s", "t", "sx", "sy", "sw", "rx", "ry", "rz", "id"]
+        names2 = ["cz", "cnot", "swap", "iswap", "fsim", "crx", "cry", "crz"]
+        ops, th = [], rng.uniform(-3, 3, 40)
+        for i in range(60):
+            if rng.uniform() < 0.55:
+                nm = names1[i % len(names1)]
+                var = (i % 40,) if nm in ("rx", "ry", "rz") else ()
+                ops.append(NS(name=nm, qubits=(int(rng.integers(n)),), params=(0.3,), var=var, data=None))
+            else:
+                nm = names2[i % len(names2)]
+                a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+                prm = (0.4, 1.1, 0.0, 0.0, 0.0) if nm == "fsim" else (0.8,)
+                var = (i % 40,) if nm in ("crx", "cry", "crz") else ()
+                ops.append(NS(name=nm, qubits=(a, b), params=prm, var=var, data=None))
+        U = W.random_unitary(4, 74)
+        ops.append(NS(name="matrix", qubits=(3, 0), params=(), var=(), data=U))
+        ops.append(NS(name="control", qubits=(1, 2), params=(), var=(), data=W.random_unitary(2, 75)))
+        ops.append(NS(name="h", qubits=(0,), params=(), var=(), data=None))
+    fused = oracle_mod.fuse_gates(ops, th)
+    ref = oracle_mod.run(n, ops, th)
+    got = oracle_mod.run(n, _as_matrix_ops(fused))
+    assert np.max(np.abs(got - ref)) < 1e-13
+    # structure: every two-qubit op survives, one-qubit ops only where no
+    # two-qubit op is their neighbour on their qubit
+    n2 = sum(1 for o in ops if len(o.qubits) == 2)
+    assert sum(1 for q, _ in fused if len(q) == 2) == n2
+    for k, (q, _) in enumerate(fused):
+        if len(q) != 1:
+            continue
+        prev = [p for p, _ in fused[:k] if q[0] in p]
+        nxt = [p for p, _ in fused[k + 1:] if q[0] in p]
+        assert not (prev and len(prev[-1]) == 2)
+        assert not (nxt and len(nxt[0]) == 2)
+    assert len(fused) < len(ops) or n2 == 0
+
+
+def test_fuse_gates_one_qubit_only_and_channels(oracle_mod):
+    from types import SimpleNamespace as NS
+    ops = [NS(name=nm, qubits=(q,), params=(0.5,), var=(), data=None)
+           for q, nm in [(0, "h"), (1, "rx"), (0, "t"), (2, "sy")]]
+    fused = oracle_mod.fuse_gates(ops, np.zeros(1))
+    assert [q for q, _ in fused] == [(0,), (1,), (0,), (2,)]
+    with pytest.raises(ValueError):
+        oracle_mod.fuse_gates(ops + [NS(name="depolarizing", qubits=(1,), params=(0.1,), var=(), data=None)])
