@@ -18,6 +18,8 @@ Also reported:
   CZ, 20 layers) at n = 12 in both forms: states before each op recomputed
   from checkpoints, and Alg. 2 with channel inverses (two states); at n = 8
   also the oracle's inverse form on the host;
+* bitstring sampling from the 28-qubit output state (2^20 samples, the
+  paper's random-circuit sampling use) and measure! of one qubit;
 * cpu_baseline: the plain C oracle on this host, timed on a bounded prefix of
   the same 28-qubit circuit.
 
@@ -160,6 +162,26 @@ def vqe_batched(torch, steps):
     return out
 
 
+def sampling(torch, st, n):
+    """2^20 bitstrings from the 28-qubit output state (uniform numbers drawn
+    on the host beforehand; host transfers of u and of the samples included),
+    then measure! of qubit 0 with its collapse."""
+    K = 1 << 20
+    u = np.random.default_rng(7).uniform(size=K)
+    st.sample(u[:1024])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = st.sample(u)
+    dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o, p = st.measure(0, 0.5)
+    torch.cuda.synchronize()
+    dm = time.perf_counter() - t0
+    return {"samples": K, "ms": round(1e3 * dt, 3), "samples_per_s": round(K / dt, 1),
+            "distinct": int(np.unique(x).size), "measure_ms": round(1e3 * dm, 3),
+            "measure_outcome": o, "measure_prob": p}
+
+
 def noisy_backward(torch, with_cpu):
     """Noisy brick-wall gradient (20 layers, <Z0 Z1>): checkpointed versus
     inverse form on the GPU at n = 12, and at n = 8 beside the oracle."""
@@ -266,6 +288,7 @@ def main():
                       "low_bits": stats["low_bits"], "norm_minus_1": float(nrm - 1.0),
                       "mean_2n_abs2": float(np.mean(np.abs(amps) ** 2) * amps_n)},
            "roofline": roof}
+    rec["sampling"] = sampling(torch, st, n)
     del st
     torch.cuda.empty_cache()
     if not args.no_vqe:

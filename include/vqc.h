@@ -221,6 +221,24 @@ vqc_status vqc_measure(vqc_state s, int qubit, double u, int *outcome_out, doubl
  * VQC_ERR_NONFINITE. */
 vqc_status vqc_sample(vqc_state s, int count, const double *u_host, int64_t *out_host);
 
+/* fuse_gates(circ) of Sec. 2.3, for noiseless circuits, applied until no
+ * one-qubit gate sits next to a two-qubit gate on its qubit: a run of
+ * one-qubit gates on a qubit is absorbed into the two-qubit gate before it on
+ * that qubit (U <- g U, in order), else into the two-qubit gate after it
+ * (U <- U g_last ... g_first); one-qubit gates on a qubit that no two-qubit
+ * gate touches stay.  Every
+ * output op is a general VQC_MATRIX gate evaluated at theta_host (host
+ * double[n_params]), so the result has no variational parameters.  The
+ * output holds the ops in their order of first appearance; the state it
+ * produces equals the input circuit's up to rounding.  out_ops: caller array
+ * of n_ops entries; out_data: caller array of 16 * n_ops complex entries that
+ * the output ops' data pointers refer to; *n_out receives the op count.
+ * Builds the matrices on the device (default stream; synchronises).  Errors:
+ * VQC_ERR_KIND for a channel, VQC_ERR_UNSUPPORTED for ops wider than two
+ * qubits, and the op validation errors of vqc_circuit_create. */
+vqc_status vqc_fuse_gates(int n_qubits, int n_ops, const vqc_op *ops, int n_params,
+                          const double *theta_host, vqc_op *out_ops, vqc_c128 *out_data, int *n_out);
+
 /* ---------------------------------------------------------------- circuits */
 
 /* Build a circuit (QCircuit, Sec. 2.3) for states of `n_qubits` and `kind`,

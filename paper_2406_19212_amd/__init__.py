@@ -7,5 +7,5 @@ as hand-written HIP kernels behind the C ABI in include/vqc.h.
 device memory and the current stream.  Importing the package does not load
 the library; the first handle does, and raises if it is not built.
 """
-from .api import State, Circuit, Batch, ops_params, stream_ptr  # noqa: F401
+from .api import State, Circuit, Batch, fuse_gates, ops_params, stream_ptr  # noqa: F401
 from . import workloads  # noqa: F401

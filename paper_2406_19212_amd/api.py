@@ -32,6 +32,28 @@ def ops_params(ops) -> int:
     return m + 1
 
 
+def fuse_gates(n: int, ops, theta=None):
+    """fuse_gates(circ): one-qubit gates absorbed into an adjacent two-qubit
+    gate on their qubit; returns general matrix ops (workloads.Op "matrix",
+    row-major numpy data) evaluated at theta (host values)."""
+    from .workloads import Op
+    arr = B.OpArray(ops)
+    P = ops_params(ops)
+    th = np.ascontiguousarray(np.zeros(max(1, P)) if theta is None else np.asarray(theta, np.float64).ravel())
+    out = (B.vqc_op * max(1, len(ops)))()
+    data = np.zeros(16 * max(1, len(ops)), np.complex128)
+    cnt = ctypes.c_int()
+    check(lib().vqc_fuse_gates(int(n), len(ops), arr.ptr(), P, th.ctypes.data, ctypes.cast(out, ctypes.c_void_p),
+                               data.ctypes.data, ctypes.byref(cnt)), "vqc_fuse_gates")
+    res = []
+    for k in range(cnt.value):
+        o = out[k]
+        d = 1 << o.n_qubits
+        M = data[16 * k:16 * k + d * d].reshape(d, d).T.copy()  # ABI column-major -> row-major
+        res.append(Op("matrix", tuple(o.qubits[t] for t in range(o.n_qubits)), (), (), M))
+    return res
+
+
 class State:
     """An n-qubit pure state (2^n amplitudes) or vectorised density matrix
     (4^n entries, v[x + 2^n y] = rho[x][y]) in a torch complex128 tensor."""

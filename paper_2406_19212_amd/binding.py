@@ -94,6 +94,8 @@ _SIGS = {
     "vqc_circuit_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_int, c_void_p, c_int,
                                    ctypes.POINTER(vqc_tune)]),
     "vqc_circuit_destroy": (c_int, [c_void_p]),
+    "vqc_fuse_gates": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
+                               ctypes.POINTER(c_int)]),
     "vqc_measure": (c_int, [c_void_p, c_int, c_double, ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
     "vqc_sample": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     "vqc_circuit_stats_get": (c_int, [c_void_p, ctypes.POINTER(vqc_circuit_stats)]),

@@ -1522,6 +1522,153 @@ vqc_status vqc_sample(vqc_state s, int count, const double *u, int64_t *out) {
   return VQC_OK;
 }
 
+// fuse_gates (Sec. 2.3): every op's matrix at theta, built on the device by
+// the same recipes the circuits use, then the absorption on the host
+vqc_status vqc_fuse_gates(int n, int n_ops, const vqc_op *ops, int n_params, const double *theta_host,
+                          vqc_op *out_ops, vqc_c128 *out_data, int *n_out) {
+  if (n < 1 || n > 33 || n_ops < 0 || !n_out || (n_ops > 0 && (!ops || !out_ops || !out_data))) return VQC_ERR_ARG;
+  if (n_params < 0 || (n_params > 0 && !theta_host)) return VQC_ERR_ARG;
+  for (int p = 0; p < n_params; p++)
+    if (!is_finite_d(theta_host[p])) return VQC_ERR_NONFINITE;
+  *n_out = 0;
+  if (n_ops == 0) return VQC_OK;
+  std::vector<DRecipe> rec(n_ops);
+  std::vector<c128> cdata;
+  for (int j = 0; j < n_ops; j++) {
+    const vqc_op &op = ops[j];
+    vqc_status st = validate_op(op, n, VQC_MIXED, n_params);
+    if (st) return st;
+    if (is_channel(op.type)) return VQC_ERR_KIND;  // noiseless circuits only
+    DRecipe &r = rec[j];
+    std::memset(&r, 0, sizeof(r));
+    r.type = op.type;
+    r.form = RF_GATE;
+    r.nq = op.n_qubits;
+    r.out = 16 * j;
+    r.data = -1;
+    if (op.data && op.n_data > 0) {
+      r.data = (int)cdata.size();
+      r.n_data = op.n_data;
+      to_row_major(op.data, op.type == VQC_CONTROL ? 2 : 1 << op.n_qubits, cdata);
+    }
+    for (int k = 0; k < 5; k++) {
+      r.pidx[k] = op.param_index[k];
+      r.pval[k] = op.params[k];
+    }
+  }
+  DevBuf drec, dcd, dth, dm;
+  VQC_TRY(drec.ensure(rec.size() * sizeof(DRecipe)));
+  VQC_TRY(dcd.ensure(std::max<size_t>(1, cdata.size()) * sizeof(c128)));
+  VQC_TRY(dth.ensure(std::max(1, n_params) * sizeof(double)));
+  VQC_TRY(dm.ensure((size_t)16 * n_ops * sizeof(c128)));
+  VQC_TRY(hipMemcpy(drec.p, rec.data(), rec.size() * sizeof(DRecipe), hipMemcpyHostToDevice));
+  if (!cdata.empty()) VQC_TRY(hipMemcpy(dcd.p, cdata.data(), cdata.size() * sizeof(c128), hipMemcpyHostToDevice));
+  if (n_params > 0) VQC_TRY(hipMemcpy(dth.p, theta_host, n_params * sizeof(double), hipMemcpyHostToDevice));
+  VQC_TRY(launch_build_mats(drec.as<DRecipe>(), n_ops, dcd.as<c128>(), nullptr, nullptr, 1, dth.as<double>(),
+                            dm.as<c128>(), nullptr));
+  std::vector<c128> M((size_t)16 * n_ops);
+  VQC_TRY(hipMemcpy(M.data(), dm.p, M.size() * sizeof(c128), hipMemcpyDeviceToHost));
+  // row-major d x d products; local bit t of a two-qubit op is its qubits[t]
+  auto cm = [](c128 a, c128 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); };
+  auto embed = [](const c128 *g, int t, c128 *G4) {  // g on local bit t of a 4x4
+    for (int r = 0; r < 4; r++)
+      for (int c = 0; c < 4; c++) {
+        const int o = t ? 1 : 2;  // the other bit
+        const bool same = ((r & o) != 0) == ((c & o) != 0);
+        const int gr = (r >> t) & 1, gc = (c >> t) & 1;
+        G4[r * 4 + c] = same ? g[gr * 2 + gc] : make_double2(0.0, 0.0);
+      }
+  };
+  auto mul4 = [&](const c128 *A, const c128 *B, c128 *C) {
+    for (int r = 0; r < 4; r++)
+      for (int c = 0; c < 4; c++) {
+        c128 acc = make_double2(0.0, 0.0);
+        for (int k = 0; k < 4; k++) {
+          const c128 p = cm(A[r * 4 + k], B[k * 4 + c]);
+          acc.x += p.x;
+          acc.y += p.y;
+        }
+        C[r * 4 + c] = acc;
+      }
+  };
+  struct F {
+    int m, q[2];
+    c128 M[16];
+  };
+  std::vector<F> out;
+  std::vector<int> last(n, -1);
+  // applied until no one-qubit op sits next to a two-qubit op on its qubit:
+  // a run of one-qubit ops goes into the two-qubit op before it (U <- g U),
+  // else waits for the next two-qubit op on that qubit (U <- U g' ... g)
+  std::vector<std::vector<int>> pending(n_ops);
+  std::vector<int> next_two(n, -1), next2(n_ops, -1);
+  for (int j = n_ops - 1; j >= 0; j--) {
+    const vqc_op &op = ops[j];
+    if (op.n_qubits == 1) next2[j] = next_two[op.qubits[0]];
+    else
+      for (int t = 0; t < op.n_qubits; t++) next_two[op.qubits[t]] = j;
+  }
+  for (int j = 0; j < n_ops; j++) {
+    const vqc_op &op = ops[j];
+    const c128 *G = M.data() + 16 * j;
+    if (op.n_qubits == 1) {
+      const int i = op.qubits[0], k = last[i];
+      if (k >= 0 && out[k].m == 2) {  // right after a two-qubit op on i: U <- g U
+        c128 G4[16], T[16];
+        embed(G, out[k].q[0] == i ? 0 : 1, G4);
+        mul4(G4, out[k].M, T);
+        std::memcpy(out[k].M, T, sizeof(T));
+      } else if (next2[j] >= 0) {  // right before one: U <- U g when it comes
+        pending[next2[j]].push_back(j);
+      } else {
+        F f;
+        f.m = 1;
+        f.q[0] = i;
+        f.q[1] = -1;
+        std::memcpy(f.M, G, 4 * sizeof(c128));
+        out.push_back(f);
+        last[i] = (int)out.size() - 1;
+      }
+    } else {
+      F f;
+      f.m = 2;
+      f.q[0] = op.qubits[0];
+      f.q[1] = op.qubits[1];
+      std::memcpy(f.M, G, 16 * sizeof(c128));
+      for (int a = (int)pending[j].size() - 1; a >= 0; a--) {  // latest first: U g_last ... g_first
+        const int pj = pending[j][a];
+        c128 G4[16], T[16];
+        embed(M.data() + 16 * pj, ops[pj].qubits[0] == f.q[0] ? 0 : 1, G4);
+        mul4(f.M, G4, T);
+        std::memcpy(f.M, T, sizeof(T));
+      }
+      out.push_back(f);
+      last[f.q[0]] = last[f.q[1]] = (int)out.size() - 1;
+    }
+  }
+  for (size_t k = 0; k < out.size(); k++) {
+    const F &f = out[k];
+    const int d = 1 << f.m;
+    vqc_op &o = out_ops[k];
+    std::memset(&o, 0, sizeof(o));
+    o.type = VQC_MATRIX;
+    o.n_qubits = f.m;
+    o.qubits[0] = f.q[0];
+    if (f.m == 2) o.qubits[1] = f.q[1];
+    for (int p = 0; p < 5; p++) o.param_index[p] = -1;
+    vqc_c128 *dst = out_data + 16 * k;
+    for (int r = 0; r < d; r++)
+      for (int c = 0; c < d; c++) {
+        dst[r + d * c].re = f.M[r * d + c].x;  // column-major in the ABI
+        dst[r + d * c].im = f.M[r * d + c].y;
+      }
+    o.data = dst;
+    o.n_data = d * d;
+  }
+  *n_out = (int)out.size();
+  return VQC_OK;
+}
+
 // -------------------------------------------------------------- circuits
 
 vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops, const vqc_op *ops, int n_params,
