@@ -54,7 +54,7 @@ enum {
   OR_X = 1, OR_Y, OR_Z, OR_H, OR_S, OR_T, OR_SX, OR_SY, OR_SW,
   OR_RX, OR_RY, OR_RZ, OR_ID,
   OR_CZ = 20, OR_CNOT, OR_SWAP, OR_ISWAP, OR_FSIM, OR_CRX, OR_CRY, OR_CRZ,
-  OR_CONTROL, OR_MATRIX,
+  OR_CONTROL, OR_MATRIX, OR_TOFFOLI, OR_FREDKIN, OR_CCONTROL,
   OR_AD = 40, OR_PD, OR_DEP, OR_DEP2, OR_KRAUS
 };
 
@@ -65,7 +65,7 @@ typedef struct {
   double prm[5];      /* parameter values */
   int var[5];         /* theta index of parameter k, or -1 */
   int n_data;         /* complex entries at data */
-  const cplx *data;   /* MATRIX: d*d; CONTROL: 2*2 target; KRAUS: nk*d*d */
+  const cplx *data;   /* MATRIX: d*d; CONTROL, CCONTROL: 2*2 target; KRAUS: nk*d*d */
 } or_op;
 
 static int is_channel(int code) { return code >= OR_AD; }
@@ -204,6 +204,29 @@ int or_gate_matrix(const or_op *op, const double *theta, cplx *G) {
       for (int i = 0; i < d * d; i++) G[i] = op->data[i];
       return d;
     }
+    /* three-qubit gates (Sec. 2.2), local index b_{q0} + 2 b_{q1} + 4 b_{q2} */
+    case OR_TOFFOLI: /* controls q0, q1; X on q2 */
+      zero(G, 8);
+      for (int l = 0; l < 8; l++) G[((l & 3) == 3 ? l ^ 4 : l) * 8 + l] = 1;
+      return 8;
+    case OR_FREDKIN: /* control q0; swap q1 and q2 */
+      zero(G, 8);
+      for (int l = 0; l < 8; l++) {
+        int o = l;
+        if ((l & 1) && ((l >> 1) & 1) != ((l >> 2) & 1)) o = l ^ 6;
+        G[o * 8 + l] = 1;
+      }
+      return 8;
+    case OR_CCONTROL: /* controls q0, q1; the 2x2 U on q2 */
+      if (op->n_data != 4) return -1;
+      zero(G, 8);
+      for (int l = 0; l < 8; l++) {
+        if ((l & 3) != 3) { G[l * 8 + l] = 1; continue; }
+        int b = l >> 2;
+        G[l * 8 + (3 | 0)] = op->data[b * 2 + 0];
+        G[l * 8 + (3 | 4)] = op->data[b * 2 + 1];
+      }
+      return 8;
   }
   return -1;
 }
@@ -375,13 +398,39 @@ int or_apply_op(cplx *st, int n, int mixed, const or_op *op, const double *theta
     cplx G[256];
     if (is_channel(op->code) || or_gate_matrix(op, theta, G) < 0) return -1;
     or_apply(st, n, op->m, op->q, G);
+  } else if (op->m == 3) {
+    /* three-qubit gates: rho -> U rho U^dagger as U on the ket bits and
+     * conj(U) on the bra bits (the superoperator conj(U) (x) U, applied by
+     * factors); there are no three-qubit channels */
+    cplx G[64], Gc[64];
+    int qq[3];
+    if (is_channel(op->code) || or_gate_matrix(op, theta, G) != 8) return -1;
+    for (int i = 0; i < 64; i++) Gc[i] = conj(G[i]);
+    for (int k = 0; k < 3; k++) qq[k] = op->q[k] + n;
+    or_apply(st, 2 * n, 3, op->q, G);
+    or_apply(st, 2 * n, 3, qq, Gc);
   } else {
     cplx S[256];
     int qq[8];
-    if (op_superop(op, theta, S) < 0) return -1;
+    if (op->m > 2 || op_superop(op, theta, S) < 0) return -1;
     super_qubits(op, n, qq);
     or_apply(st, 2 * n, 2 * op->m, qq, S);
   }
+  return 0;
+}
+
+/* vec(rho) -> M^dagger vec(rho) = vec(U^dagger rho U) for a three-qubit gate
+ * (also its inverse): U^dagger on the ket bits, U^T on the bra bits */
+static int mixed_gate3_adjoint(cplx *v, int n, const or_op *op, const double *theta) {
+  cplx G[64], Gd[64], Gt[64];
+  int qq[3];
+  if (or_gate_matrix(op, theta, G) != 8) return -1;
+  dagger(G, 8, Gd);
+  for (int r = 0; r < 8; r++)
+    for (int c = 0; c < 8; c++) Gt[r * 8 + c] = G[c * 8 + r];
+  for (int k = 0; k < 3; k++) qq[k] = op->q[k] + n;
+  or_apply(v, 2 * n, 3, op->q, Gd);
+  or_apply(v, 2 * n, 3, qq, Gt);
   return 0;
 }
 
@@ -533,6 +582,10 @@ int or_grad_mixed(int n, int n_ops, const or_op *ops, const double *theta, const
     for (int j = s1 - 1; j >= s0; j--) {
       const or_op *op = &ops[j];
       int D = 1 << (2 * op->m);
+      if (op->m == 3) {  /* three-qubit gates carry no parameters */
+        if (mixed_gate3_adjoint(psi, n, op, theta)) { rc = -1 - j; goto done; }
+        continue;
+      }
       super_qubits(op, n, qq);
       if (op_superop(op, theta, S) < 0) { rc = -1 - j; goto done; }
       if (!is_channel(op->code)) {
@@ -610,6 +663,13 @@ int or_grad_mixed_inverse(int n, int n_ops, const or_op *ops, const double *thet
   for (int j = n_ops - 1; j >= 0; j--) {
     const or_op *op = &ops[j];
     int D = 1 << (2 * op->m);
+    if (op->m == 3) {  /* unitary, no parameters: M^{-1} = M^dagger */
+      if (mixed_gate3_adjoint(phi, n, op, theta) || mixed_gate3_adjoint(psi, n, op, theta)) {
+        rc = -1 - j;
+        goto done;
+      }
+      continue;
+    }
     super_qubits(op, n, qq);
     if (op_superop(op, theta, S) < 0) { rc = -1 - j; goto done; }
     if (or_invert(D, S, Si)) { rc = -1 - j; goto done; }

@@ -727,3 +727,75 @@ def test_fuse_gates_one_qubit_only_and_channels(oracle_mod):
     assert [q for q, _ in fused] == [(0,), (1,), (0,), (2,)]
     with pytest.raises(ValueError):
         oracle_mod.fuse_gates(ops + [NS(name="depolarizing", qubits=(1,), params=(0.1,), var=(), data=None)])
+
+
+# ------------------------------------------------------- three-qubit gates
+
+def _ns(name, qubits, params=(), var=(), data=None):
+    from types import SimpleNamespace as NS
+    return NS(name=name, qubits=tuple(qubits), params=tuple(params), var=tuple(var), data=data)
+
+
+@pytest.mark.parametrize("qs", [(0, 1, 2), (3, 0, 2), (2, 3, 1)])
+def test_three_qubit_gates_truth_tables(oracle_mod, qs):
+    n = 4
+    a, b, t = qs
+    for x in range(1 << n):
+        e = np.zeros(1 << n, complex)
+        e[x] = 1
+        bit = lambda v, q: (v >> q) & 1
+        tof = oracle_mod.run(n, [_ns("toffoli", qs)], init=e)
+        want = x ^ ((1 << t) if bit(x, a) and bit(x, b) else 0)
+        assert tof[want] == 1 and np.sum(np.abs(tof)) == 1
+        fre = oracle_mod.run(n, [_ns("fredkin", qs)], init=e)
+        want = x
+        if bit(x, a) and bit(x, b) != bit(x, t):
+            want = x ^ (1 << b) ^ (1 << t)
+        assert fre[want] == 1 and np.sum(np.abs(fre)) == 1
+
+
+def test_ccontrol_is_doubly_controlled_u(oracle_mod):
+    n = 4
+    U = W.random_unitary(2, 91)
+    P11 = np.diag([0, 0, 0, 1.0])  # |11><11| on (q0, q1), local index b0 + 2 b1
+    G = np.kron(U, P11) + np.kron(I2, np.eye(4) - P11)  # target is local bit 2
+    for qs in [(0, 1, 2), (3, 1, 0)]:
+        psi = W.random_state(n, 92)
+        got = oracle_mod.run(n, [_ns("ccontrol", qs, data=U)], init=psi)
+        want = dense_op(n, list(qs), G) @ psi
+        assert np.max(np.abs(got - want)) < 1e-15
+    # a general three-qubit matrix at scattered positions
+    V = W.random_unitary(8, 93)
+    psi = W.random_state(n, 94)
+    got = oracle_mod.run(n, [_ns("matrix", (2, 0, 3), data=V)], init=psi)
+    assert np.max(np.abs(got - dense_op(n, [2, 0, 3], V) @ psi)) < 1e-14
+
+
+def test_three_qubit_gates_on_density_and_gradients(oracle_mod):
+    n = 4
+    U = W.random_unitary(2, 95)
+    ops = [_ns("rx", (0,), (0.0,), (0,)), _ns("h", (1,)), _ns("toffoli", (0, 1, 2)), _ns("ry", (2,), (0.0,), (1,)),
+           _ns("fredkin", (2, 3, 0)), _ns("ccontrol", (3, 2, 1), data=U), _ns("rz", (1,), (0.0,), (2,)),
+           _ns("matrix", (1, 3, 0), data=W.random_unitary(8, 96)), _ns("crx", (0, 3), (0.0,), (3,))]
+    th = np.array([0.7, -1.2, 2.1, 0.4])
+    psi = oracle_mod.run(n, ops, th)
+    rho = unvec(oracle_mod.run(n, ops, th, mixed=True), n)
+    assert np.max(np.abs(rho - np.outer(psi, psi.conj()))) < 1e-14
+    terms = W.tfim(n, 0.6)
+
+    def central(f, h=1e-5):  # the controlled rotation has no two-term shift rule
+        g = np.zeros_like(th)
+        for k in range(th.size):
+            tp, tm = th.copy(), th.copy()
+            tp[k] += h
+            tm[k] -= h
+            g[k] = (f(tp) - f(tm)) / (2 * h)
+        return g
+    _, gp, _ = oracle_mod.grad_pure(n, ops, th, terms)
+    assert np.max(np.abs(gp - central(lambda t: loss_pure(oracle_mod, n, ops, t, terms)))) < 1e-9
+    noisy = ops[:4] + [_ns("depolarizing", (2,), (0.1,))] + ops[4:] + [_ns("amplitude_damping", (0,), (0.2,))]
+    _, gm = oracle_mod.grad_mixed(n, noisy, th, terms)
+    _, gi, phi = oracle_mod.grad_mixed_inverse(n, noisy, th, terms)
+    gf = central(lambda t: loss_mixed(oracle_mod, n, noisy, t, terms))
+    assert np.max(np.abs(gm - gf)) < 1e-9 and np.max(np.abs(gi - gm)) < 1e-13
+    assert np.max(np.abs(phi - oracle_mod.initial_state(n, mixed=True))) < 1e-12
