@@ -76,7 +76,18 @@ enum {
   VQC_RX, VQC_RY, VQC_RZ, VQC_ID,
   VQC_CZ = 20, VQC_CNOT, VQC_SWAP, VQC_ISWAP, VQC_FSIM, VQC_CRX, VQC_CRY, VQC_CRZ,
   VQC_CONTROL, /* CONTROLGate(i, j, U): data = 2x2 target matrix */
-  VQC_MATRIX,  /* QuantumGate(positions, data): data = 2^m x 2^m, m <= 2 */
+  VQC_MATRIX,  /* QuantumGate(positions, data): data = 2^m x 2^m; m <= 2 in
+                  circuits, m <= 3 in vqc_apply_op / vqc_apply_gate */
+  /* three-qubit gates (Sec. 2.2), local index b_{q0} + 2 b_{q1} + 4 b_{q2}:
+   * TOFFOLI flips qubits[2] when qubits[0] and qubits[1] are 1; FREDKIN swaps
+   * qubits[1] and qubits[2] when qubits[0] is 1; CCONTROL is
+   * CONTROLCONTROLGate(i, j, k, U): the 2x2 data U on qubits[2] when
+   * qubits[0] and qubits[1] are 1.  In circuits they are expanded into exact
+   * one- and two-qubit sequences: Toffoli as six CNOTs with H, T and T^dagger
+   * (Nielsen and Chuang, Fig. 4.9), Fredkin as CNOT . Toffoli . CNOT, CCONTROL
+   * as CV, CNOT, CV^dagger, CNOT, CV with V the principal square root of U
+   * (Barenco et al. 1995, Lemma 6.1). */
+  VQC_TOFFOLI, VQC_FREDKIN, VQC_CCONTROL,
   /* channels (Sec. 2.2); params[0] = gamma or p.  Depolarizing uses
    * K0 = sqrt(1-3p/4) I, K1..3 = sqrt(p/4) sigma (trace preserving);
    * DEPOLARIZING2 uses K0 = sqrt(1-15p/16) I, K_ab = sqrt(p/16) sigma_a(x)sigma_b. */
@@ -91,7 +102,7 @@ enum {
  * parameters (Sec. 2.2). */
 typedef struct {
   int type;
-  int n_qubits;           /* 1 or 2 */
+  int n_qubits;           /* 1, 2, or 3 (three-qubit gates only) */
   int qubits[4];
   double params[5];
   int param_index[5];
@@ -168,10 +179,12 @@ vqc_status vqc_state_reset(vqc_state s);
 vqc_status vqc_state_rebind(vqc_state s, void *dev_buf, void *stream);
 vqc_status vqc_state_destroy(vqc_state s);
 
-/* Apply one m-qubit gate matrix (m = 1, 2), Eqs. (3) / (twoqubitgate).
+/* Apply one m-qubit gate matrix (m = 1, 2, 3), Eqs. (3) / (twoqubitgate) and
+ * Alg. 1 for m = 3 (one dense 8x8 product per group of eight amplitudes).
  * On a mixed state the gate acts as rho -> U rho U^dagger (Sec. 3.5: a gate
- * is a one-Kraus channel).  Diagonal and controlled matrices are detected and
- * take the kernels that touch only the amplitudes that change. */
+ * is a one-Kraus channel).  Diagonal and controlled matrices (m <= 2) are
+ * detected and take the kernels that touch only the amplitudes that change.
+ * m = 3 synchronises the stream (the matrix is copied from host memory). */
 vqc_status vqc_apply_gate(vqc_state s, int m, const int *qubits, const vqc_c128 *matrix);
 
 /* Apply one typed op (Sec. 2.2 predefined gates, parametric gates with the

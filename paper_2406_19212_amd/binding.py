@@ -24,7 +24,7 @@ TYPES = {
     "x": 1, "y": 2, "z": 3, "h": 4, "s": 5, "t": 6, "sx": 7, "sy": 8, "sw": 9,
     "rx": 10, "ry": 11, "rz": 12, "id": 13,
     "cz": 20, "cnot": 21, "swap": 22, "iswap": 23, "fsim": 24, "crx": 25, "cry": 26, "crz": 27,
-    "control": 28, "matrix": 29,
+    "control": 28, "matrix": 29, "toffoli": 30, "fredkin": 31, "ccontrol": 32,
     "amplitude_damping": 40, "phase_damping": 41, "depolarizing": 42, "depolarizing2": 43,
     "kraus": 44,
 }

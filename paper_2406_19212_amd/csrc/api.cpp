@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
+#include <deque>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -73,6 +75,7 @@ struct DevBuf {
 int op_arity(int type) {
   if (type >= VQC_X && type <= VQC_ID) return 1;
   if (type >= VQC_CZ && type <= VQC_CONTROL) return 2;
+  if (type >= VQC_TOFFOLI && type <= VQC_CCONTROL) return 3;
   if (type == VQC_AMPLITUDE_DAMPING || type == VQC_PHASE_DAMPING || type == VQC_DEPOLARIZING) return 1;
   if (type == VQC_DEPOLARIZING2) return 2;
   return 0;  // MATRIX, KRAUS: given by n_qubits
@@ -86,7 +89,7 @@ int n_params_of(int type) {
   }
 }
 bool valid_type(int t) {
-  return (t >= VQC_X && t <= VQC_ID) || (t >= VQC_CZ && t <= VQC_MATRIX) ||
+  return (t >= VQC_X && t <= VQC_ID) || (t >= VQC_CZ && t <= VQC_CCONTROL) ||
          (t >= VQC_AMPLITUDE_DAMPING && t <= VQC_KRAUS);
 }
 
@@ -166,7 +169,8 @@ vqc_status validate_op(const vqc_op &op, int n, vqc_kind kind, int n_params) {
   if (!valid_type(op.type)) return VQC_ERR_ARG;
   const int ar = op_arity(op.type);
   const int m = op.n_qubits;
-  if (m < 1 || m > 2) return VQC_ERR_UNSUPPORTED;
+  if (m < 1 || m > 3) return VQC_ERR_UNSUPPORTED;
+  if (m == 3 && op.type != VQC_MATRIX && ar != 3) return VQC_ERR_UNSUPPORTED;  // no three-qubit channels
   if (ar && ar != m) return VQC_ERR_ARG;
   vqc_status st = check_qubits(m, op.qubits, n);
   if (st) return st;
@@ -181,7 +185,7 @@ vqc_status validate_op(const vqc_op &op, int n, vqc_kind kind, int n_params) {
   const int d = 1 << m;
   if (op.type == VQC_MATRIX) {
     if (!op.data || op.n_data != d * d) return VQC_ERR_ARG;
-  } else if (op.type == VQC_CONTROL) {
+  } else if (op.type == VQC_CONTROL || op.type == VQC_CCONTROL) {
     if (!op.data || op.n_data != 4) return VQC_ERR_ARG;
   } else if (op.type == VQC_KRAUS) {
     if (!op.data || op.n_data <= 0 || op.n_data % (d * d) || op.n_data / (d * d) > 64) return VQC_ERR_ARG;
@@ -1262,12 +1266,34 @@ static int single_kind(int m, const c128 *G) {
 
 static hipError_t apply_single(vqc_state s, int m, const int *q, const c128 *dev_mat, int kind) {
   if (m == 1) return launch_g1(s->buf, s->nbits, q[0], dev_mat, kind, s->stream);
+  if (m == 3) return launch_gm(s->buf, s->nbits, 3, q, dev_mat, s->stream);
   return launch_g2(s->buf, s->nbits, q[0], q[1], dev_mat, kind, s->stream);
+}
+
+// the 8x8 matrix (ABI column-major) of a three-qubit gate type
+static void gate3_matrix(const vqc_op &o, vqc_c128 *cm) {
+  std::memset(cm, 0, 64 * sizeof(vqc_c128));
+  for (int l = 0; l < 8; l++) {  // column l (input), local index b0 + 2 b1 + 4 b2
+    if (o.type == VQC_TOFFOLI) {
+      cm[((l & 3) == 3 ? l ^ 4 : l) + 8 * l].re = 1;
+    } else if (o.type == VQC_FREDKIN) {
+      const bool sw = (l & 1) && (((l >> 1) & 1) != ((l >> 2) & 1));
+      cm[(sw ? l ^ 6 : l) + 8 * l].re = 1;
+    } else {  // CCONTROL: column-major 2x2 data u[out + 2 in] on bit 2
+      if ((l & 3) != 3) {
+        cm[l + 8 * l].re = 1;
+        continue;
+      }
+      const int b = l >> 2;
+      cm[3 + 8 * l] = o.data[0 + 2 * b];
+      cm[7 + 8 * l] = o.data[1 + 2 * b];
+    }
+  }
 }
 
 vqc_status vqc_apply_gate(vqc_state s, int m, const int *qubits, const vqc_c128 *matrix) {
   if (!s || !qubits || !matrix) return VQC_ERR_ARG;
-  if (m < 1 || m > 2) return VQC_ERR_UNSUPPORTED;
+  if (m < 1 || m > 3) return VQC_ERR_UNSUPPORTED;
   vqc_status st = check_qubits(m, qubits, s->n);
   if (st) return st;
   const int d = 1 << m;
@@ -1275,6 +1301,20 @@ vqc_status vqc_apply_gate(vqc_state s, int m, const int *qubits, const vqc_c128 
     if (!is_finite_d(matrix[i].re) || !is_finite_d(matrix[i].im)) return VQC_ERR_NONFINITE;
   std::vector<c128> G;
   to_row_major(matrix, d, G);
+  if (m == 3) {
+    // dense 8x8 (Alg. 1 with three nested strides): U, then conj(U) on the bra bits
+    c128 *dm = s->mat.as<c128>();
+    std::vector<c128> both(G);
+    for (const c128 &v : G) both.push_back(make_double2(v.x, -v.y));
+    VQC_TRY(hipMemcpyAsync(dm, both.data(), both.size() * sizeof(c128), hipMemcpyHostToDevice, s->stream));
+    VQC_TRY(apply_single(s, 3, qubits, dm, 0));
+    if (s->kind == VQC_MIXED) {
+      const int qb[3] = {qubits[0] + s->n, qubits[1] + s->n, qubits[2] + s->n};
+      VQC_TRY(apply_single(s, 3, qb, dm + 64, 0));
+    }
+    VQC_TRY(hipStreamSynchronize(s->stream));  // the host source is local
+    return VQC_OK;
+  }
   const int kind = single_kind(m, G.data());
   c128 *dm = s->mat.as<c128>();
   VQC_TRY(launch_set_mat(dm, G.data(), d * d, s->stream));
@@ -1319,6 +1359,11 @@ vqc_status vqc_apply_op(vqc_state s, const vqc_op *op) {
     return apply_channel_dev(s, m, o.qubits, o.type, o.params[0], K, o.n_data);
   }
   if (o.type == VQC_MATRIX) return vqc_apply_gate(s, m, o.qubits, o.data);
+  if (m == 3) {
+    vqc_c128 full[64];
+    gate3_matrix(o, full);
+    return vqc_apply_gate(s, 3, o.qubits, full);
+  }
   if (o.type == VQC_CONTROL) {
     vqc_c128 full[16];
     std::memset(full, 0, sizeof(full));
@@ -1539,6 +1584,7 @@ vqc_status vqc_fuse_gates(int n, int n_ops, const vqc_op *ops, int n_params, con
     vqc_status st = validate_op(op, n, VQC_MIXED, n_params);
     if (st) return st;
     if (is_channel(op.type)) return VQC_ERR_KIND;  // noiseless circuits only
+    if (op.n_qubits > 2) return VQC_ERR_UNSUPPORTED;
     DRecipe &r = rec[j];
     std::memset(&r, 0, sizeof(r));
     r.type = op.type;
@@ -1671,6 +1717,92 @@ vqc_status vqc_fuse_gates(int n, int n_ops, const vqc_op *ops, int n_params, con
 
 // -------------------------------------------------------------- circuits
 
+namespace {
+
+vqc_op plain_op(int type, int q0, int q1 = -1, const vqc_c128 *data = nullptr, int n_data = 0) {
+  vqc_op o;
+  std::memset(&o, 0, sizeof(o));
+  o.type = type;
+  o.n_qubits = q1 >= 0 ? 2 : 1;
+  o.qubits[0] = q0;
+  if (q1 >= 0) o.qubits[1] = q1;
+  for (int k = 0; k < 5; k++) o.param_index[k] = -1;
+  o.data = data;
+  o.n_data = n_data;
+  return o;
+}
+
+// T^dagger = diag(1, e^{-i pi/4}), column-major
+const vqc_c128 kTdg[4] = {{1.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.70710678118654752440, -0.70710678118654752440}};
+
+// Toffoli (controls a, b; target t) as six CNOTs with H, T and T^dagger
+// (Nielsen and Chuang, Fig. 4.9)
+void expand_toffoli(int a, int b, int t, std::vector<vqc_op> &out) {
+  out.push_back(plain_op(VQC_H, t));
+  out.push_back(plain_op(VQC_CNOT, b, t));
+  out.push_back(plain_op(VQC_MATRIX, t, -1, kTdg, 4));
+  out.push_back(plain_op(VQC_CNOT, a, t));
+  out.push_back(plain_op(VQC_T, t));
+  out.push_back(plain_op(VQC_CNOT, b, t));
+  out.push_back(plain_op(VQC_MATRIX, t, -1, kTdg, 4));
+  out.push_back(plain_op(VQC_CNOT, a, t));
+  out.push_back(plain_op(VQC_T, b));
+  out.push_back(plain_op(VQC_T, t));
+  out.push_back(plain_op(VQC_H, t));
+  out.push_back(plain_op(VQC_CNOT, a, b));
+  out.push_back(plain_op(VQC_T, a));
+  out.push_back(plain_op(VQC_MATRIX, b, -1, kTdg, 4));
+  out.push_back(plain_op(VQC_CNOT, a, b));
+}
+
+// a three-qubit gate as exact one- and two-qubit ops; matrices it needs are
+// kept in `store` (stable addresses)
+vqc_status expand_gate3(const vqc_op &op, std::vector<vqc_op> &out, std::deque<std::vector<vqc_c128>> &store) {
+  const int a = op.qubits[0], b = op.qubits[1], t = op.qubits[2];
+  if (op.type == VQC_TOFFOLI) {
+    expand_toffoli(a, b, t, out);
+  } else if (op.type == VQC_FREDKIN) {  // CNOT(t->b) . Toffoli(a, b; t) . CNOT(t->b)
+    out.push_back(plain_op(VQC_CNOT, t, b));
+    expand_toffoli(a, b, t, out);
+    out.push_back(plain_op(VQC_CNOT, t, b));
+  } else if (op.type == VQC_CCONTROL) {
+    // CV(b,t) CNOT(a,b) CV^dagger(b,t) CNOT(a,b) CV(a,t), V^2 = U
+    // (Barenco et al. 1995, Lemma 6.1); V = (U + s I) / sqrt(tr U + 2 s),
+    // s = sqrt(det U) with the sign that keeps the denominator away from 0
+    using cd = std::complex<double>;
+    const vqc_c128 *u = op.data;  // column-major: u[out + 2 in]
+    c128 rm[4] = {make_double2(u[0].re, u[0].im), make_double2(u[2].re, u[2].im), make_double2(u[1].re, u[1].im),
+                  make_double2(u[3].re, u[3].im)};
+    if (!unitary_rm(rm, 2)) return VQC_ERR_NOT_UNITARY;
+    const cd u00(u[0].re, u[0].im), u10(u[1].re, u[1].im), u01(u[2].re, u[2].im), u11(u[3].re, u[3].im);
+    const cd tr = u00 + u11;
+    cd sd = std::sqrt(u00 * u11 - u01 * u10);
+    if (std::abs(tr - 2.0 * sd) > std::abs(tr + 2.0 * sd)) sd = -sd;
+    const cd den = std::sqrt(tr + 2.0 * sd);
+    const cd v[4] = {(u00 + sd) / den, u10 / den, u01 / den, (u11 + sd) / den};  // column-major
+    store.emplace_back(4);
+    std::vector<vqc_c128> &V = store.back();
+    store.emplace_back(4);
+    std::vector<vqc_c128> &Vd = store.back();
+    for (int i = 0; i < 4; i++) V[i] = {v[i].real(), v[i].imag()};
+    for (int r = 0; r < 2; r++)
+      for (int c = 0; c < 2; c++) {  // (V^dagger)[r][c] = conj(V[c][r])
+        const cd x = std::conj(v[c + 2 * r]);
+        Vd[r + 2 * c] = {x.real(), x.imag()};
+      }
+    out.push_back(plain_op(VQC_CONTROL, b, t, V.data(), 4));
+    out.push_back(plain_op(VQC_CNOT, a, b));
+    out.push_back(plain_op(VQC_CONTROL, b, t, Vd.data(), 4));
+    out.push_back(plain_op(VQC_CNOT, a, b));
+    out.push_back(plain_op(VQC_CONTROL, a, t, V.data(), 4));
+  } else {
+    return VQC_ERR_UNSUPPORTED;  // a general three-qubit matrix: single ops only
+  }
+  return VQC_OK;
+}
+
+}  // namespace
+
 vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops, const vqc_op *ops, int n_params,
                               const vqc_tune *tune) {
   if (!out || n_ops < 0 || (n_ops > 0 && !ops) || n_params < 0) return VQC_ERR_ARG;
@@ -1692,7 +1824,15 @@ vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops,
   c->n_params = n_params;
   std::memset(&c->tune, 0, sizeof(c->tune));
   if (tune) c->tune = *tune;
-  c->ops.assign(ops, ops + n_ops);
+  std::deque<std::vector<vqc_c128>> store;  // matrices of expanded ops, alive through lowering
+  for (int j = 0; j < n_ops; j++) {
+    if (ops[j].n_qubits == 3) {
+      vqc_status st = expand_gate3(ops[j], c->ops, store);
+      if (st) return st;
+    } else {
+      c->ops.push_back(ops[j]);
+    }
+  }
   vqc_status st = lower(c.get());
   for (auto &o : c->ops) o.data = nullptr;  // data copied into cdata
   if (st) return st;
