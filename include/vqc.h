@@ -334,6 +334,15 @@ vqc_status vqc_batch_expectation(vqc_batch b, const vqc_pauli_sum *H, double *en
 vqc_status vqc_batch_backward(vqc_batch b, const vqc_pauli_sum *H, double *const *grads_dev,
                               double *energies_dev, size_t checkpoint_budget_bytes);
 
+/* vqc_backward_inverse for every item of a MIXED batch after
+ * vqc_batch_forward: one register-pass launch per step for all items (the
+ * items' inverse superoperators and the largest condition number are computed
+ * first; above max_cond, or for a singular channel, VQC_ERR_ILL_CONDITIONED
+ * before any state changes).  Each item's state is uncomputed in place.
+ * PURE batches run vqc_batch_backward.  Synchronises once. */
+vqc_status vqc_batch_backward_inverse(vqc_batch b, const vqc_pauli_sum *H, double *const *grads_dev,
+                                      double *energies_dev, double max_cond);
+
 /* Capture forward + backward (H, grads, energies as above) into a hipGraph
  * once; vqc_batch_replay launches it on the batch stream.  Capture queues no
  * work.  Replays reuse the pointers bound at creation. */

@@ -266,6 +266,13 @@ class Batch:
         gp = self._gptrs(grads)
         check(lib().vqc_batch_backward(self.h, ps.ref(), gp, _dptr(energies), int(budget)), "vqc_batch_backward")
 
+    def backward_inverse(self, terms, grads, energies=None, max_cond=0.0):
+        """Mixed items: Alg. 2 with channel inverses, all items per launch."""
+        ps = B.PauliSum(terms)
+        gp = self._gptrs(grads)
+        check(lib().vqc_batch_backward_inverse(self.h, ps.ref(), gp, _dptr(energies), float(max_cond)),
+              "vqc_batch_backward_inverse")
+
     def capture(self, terms, grads, energies=None, budget=0):
         ps = B.PauliSum(terms)
         gp = self._gptrs(grads)

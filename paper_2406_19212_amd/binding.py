@@ -111,6 +111,7 @@ _SIGS = {
     "vqc_batch_forward": (c_int, [c_void_p]),
     "vqc_batch_expectation": (c_int, [c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p]),
     "vqc_batch_backward": (c_int, [c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p, c_void_p, c_size_t]),
+    "vqc_batch_backward_inverse": (c_int, [c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p, c_void_p, c_double]),
     "vqc_batch_capture": (c_int, [c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p, c_void_p, c_size_t]),
     "vqc_batch_replay": (c_int, [c_void_p]),
     "vqc_gemm_bf16": (c_int, [c_int, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_int,

@@ -621,6 +621,7 @@ struct vqc_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
+  DevBuf kappa;  // largest condition number of the inverse-form backward
   // mixed batches: checkpoint layout
   int ck_stride = 0;
   std::vector<size_t> ck_off;  // per item: base offset into ck (bytes)
@@ -2137,9 +2138,9 @@ static vqc_status batch_build_tables(vqc_batch b) {
     b->mat_off[i] = mtot;
     mtot += al((size_t)c->mat_total * sizeof(c128));
     b->psi_off[i] = ptot;
-    if (c->kind == VQC_PURE) ptot += al(state_len(c->kind, c->n) * sizeof(c128));
+    ptot += al(state_len(c->kind, c->n) * sizeof(c128));  // allocated by the backward
     b->part_off[i] = qtot;
-    if (c->kind == VQC_PURE) qtot += al(std::max(1, c->n_gslots) * c->adj.units_per_item * sizeof(double));
+    qtot += al(std::max(1, c->n_gslots) * c->adj.units_per_item * sizeof(double));
     e_off[i] = etot;
     etot += expect_units(c->n);
     b->max_passes = std::max(b->max_passes, (int)c->fwd.passes.size());
@@ -2216,7 +2217,8 @@ static vqc_status batch_build_tables(vqc_batch b) {
     b->fwd_count.push_back((int)fj.size() - b->fwd_first.back());
     b->fwd_units.push_back(u0);
   }
-  // adjoint step jobs (pure items; aligned at each item's last pass)
+  // adjoint step jobs (aligned at each item's last pass; pure: Alg. 2, mixed:
+  // its inverse form)
   std::vector<DJob> aj;
   for (int r = 0; r < b->max_adj; r++) {
     b->adj_first.push_back((int)aj.size());
@@ -2224,7 +2226,7 @@ static vqc_status batch_build_tables(vqc_batch b) {
     for (int i = 0; i < B; i++) {
       vqc_circuit c = b->circ[i];
       const int PA = (int)c->adj.passes.size();
-      if (c->kind != VQC_PURE || r >= PA) continue;
+      if (r >= PA) continue;
       DJob j;
       std::memset(&j, 0, sizeof(j));
       j.a = b->states[i];
@@ -2341,7 +2343,6 @@ static vqc_status batch_ensure_adjoint(vqc_batch b) {
   size_t ptot = 0, qtot = 0;
   for (int i = 0; i < b->B; i++) {
     vqc_circuit c = b->circ[i];
-    if (c->kind != VQC_PURE) continue;
     ptot = std::max(ptot, b->psi_off[i] + ((state_len(c->kind, c->n) * sizeof(c128) + 255) & ~size_t(255)));
     qtot = std::max(qtot, b->part_off[i] + ((std::max(1, c->n_gslots) * c->adj.units_per_item * sizeof(double) + 255) &
                                             ~size_t(255)));
@@ -2356,7 +2357,7 @@ static vqc_status batch_ensure_adjoint(vqc_batch b) {
   return batch_build_tables(b);
 }
 
-static vqc_status batch_grad_jobs(vqc_batch b, double *const *grads) {
+static vqc_status batch_grad_jobs(vqc_batch b, double *const *grads, bool mixed_inverse = false) {
   std::vector<DGradJob> gj(b->B);
   for (int i = 0; i < b->B; i++) {
     vqc_circuit c = b->circ[i];
@@ -2367,8 +2368,8 @@ static vqc_status batch_grad_jobs(vqc_batch b, double *const *grads) {
     g.grad = grads[i];
     g.csr_ptr = c->d_csr_ptr;
     g.csr_slot = c->d_csr_slot;
-    g.n_params = c->kind == VQC_PURE ? c->n_params : 0;
-    g.scale = 2.0;
+    g.n_params = (c->kind == VQC_PURE || mixed_inverse) ? c->n_params : 0;
+    g.scale = c->kind == VQC_PURE ? 2.0 : 1.0;
   }
   VQC_TRY(hipMemcpy(b->d_gjobs, gj.data(), gj.size() * sizeof(DGradJob), hipMemcpyHostToDevice));
   return VQC_OK;
@@ -2484,6 +2485,62 @@ vqc_status vqc_batch_backward(vqc_batch b, const vqc_pauli_sum *H, double *const
                                   energies ? energies + i : nullptr, nullptr, budget);
     if (st) return st;
   }
+  return VQC_OK;
+}
+
+// inverse form for a batch of mixed items: all items' passes step together
+vqc_status vqc_batch_backward_inverse(vqc_batch b, const vqc_pauli_sum *H, double *const *grads, double *energies,
+                                      double max_cond) {
+  if (!b || !H || !grads) return VQC_ERR_ARG;
+  if (!is_finite_d(max_cond)) return VQC_ERR_NONFINITE;
+  if (b->circ[0]->kind == VQC_PURE) return vqc_batch_backward(b, H, grads, energies, 0);
+  const double bound = max_cond > 0.0 ? max_cond : 1e8;
+  for (int i = 0; i < b->B; i++) {
+    if (b->circ[i]->n_params > 0 && !grads[i]) return VQC_ERR_ARG;
+    if (b->circ[i]->has_nonunitary_matrix) return VQC_ERR_NOT_UNITARY;
+  }
+  VQC_TRY(hipStreamSynchronize(b->stream));
+  vqc_status st = batch_ensure_adjoint(b);
+  if (st) return st;
+  st = batch_upload_terms(b, H, true);
+  if (st) return st;
+  st = batch_grad_jobs(b, grads, true);
+  if (st) return st;
+  hipStream_t s = b->stream;
+  VQC_TRY(b->kappa.ensure(256));
+  unsigned long long *kb = b->kappa.as<unsigned long long>();
+  VQC_TRY(hipMemsetAsync(kb, 0, sizeof(*kb), s));
+  for (auto &g : b->groups) {
+    const double *const *th = reinterpret_cast<const double *const *>(g->ptrs.p);
+    c128 *const *mt = reinterpret_cast<c128 *const *>(g->ptrs.as<char>() + g->count * sizeof(void *));
+    VQC_TRY(build_mats(g->c, th, mt, g->count, nullptr, nullptr, s));
+    if (!g->c->inv_list.empty())
+      VQC_TRY(launch_invert(reinterpret_cast<const DInv *>(g->c->dinv.as<char>() + 256), (int)g->c->inv_list.size(),
+                            mt, g->count, nullptr, kb, s));
+  }
+  unsigned long long bits = 0;
+  VQC_TRY(hipMemcpyAsync(&bits, kb, sizeof(bits), hipMemcpyDeviceToHost, s));
+  VQC_TRY(hipStreamSynchronize(s));
+  double kappa;
+  std::memcpy(&kappa, &bits, sizeof(kappa));
+  if (!(kappa <= bound)) return VQC_ERR_ILL_CONDITIONED;
+  for (int i = 0; i < b->B; i++)
+    VQC_TRY(launch_seed_mixed(reinterpret_cast<c128 *>(b->psi.as<char>() + b->psi_off[i]), b->circ[i]->n, b->d_terms,
+                              b->n_terms, s));
+  VQC_TRY(launch_expect(b->d_ejobs, b->B, b->e_units, b->d_terms, b->n_terms, s));
+  VQC_TRY(launch_reduce_partials(b->d_ejobs, b->B, b->d_eres, s));
+  if (energies) VQC_TRY(launch_take_real(b->d_eres, b->B, energies, s));
+  DOverride ov;
+  std::memset(&ov, 0, sizeof(ov));
+  vqc_circuit c0 = b->circ[0];
+  for (int r = 0; r < b->max_adj; r++) {
+    if (b->adj_count[r] == 0) continue;
+    const int64_t units = b->adj_units[r];
+    const int grid = grid_of(c0, units);
+    const DJob *jobs = b->d_adj_jobs + b->adj_first[r];
+    VQC_TRY(launch_pass_reg(c0->adj.R, 3, jobs, b->adj_count[r], units, grid, ov, s));
+  }
+  VQC_TRY(launch_grad_reduce(b->d_gjobs, b->B, b->max_params, s));
   return VQC_OK;
 }
 

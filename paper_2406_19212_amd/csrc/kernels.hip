@@ -288,6 +288,20 @@ __device__ void build_plain(const DRecipe &R, const c128 *__restrict__ cdata, co
     }
     case RF_SUPER_KRAUS: {
       const int d = 1 << R.nq, D = d * d;
+      if (R.type == VQC_DEPOLARIZING || R.type == VQC_DEPOLARIZING2) {
+        // the Pauli Kraus sum in closed form: rho -> (1 - p) rho + p Tr(rho) I / d,
+        // S[(x + d y), (x' + d y')] = (1 - p) [x = x'][y = y'] + (p / d) [x = y][x' = y']
+        const double g = p[0];
+        for (int x = 0; x < d; x++)
+          for (int y = 0; y < d; y++)
+            for (int x2 = 0; x2 < d; x2++)
+              for (int y2 = 0; y2 < d; y2++) {
+                double v = (x == x2 && y == y2) ? 1.0 - g : 0.0;
+                if (x == y && x2 == y2) v += g / d;
+                out[(x + d * y) * D + (x2 + d * y2)] = C(v, 0.0);
+              }
+        break;
+      }
       int nk;
       switch (R.type) {
         case VQC_AMPLITUDE_DAMPING: case VQC_PHASE_DAMPING: nk = 2; break;
