@@ -17,9 +17,12 @@ Also reported:
   amplitude damping after every rotation, two-qubit depolarizing after every
   CZ, 20 layers) at n = 12 in both forms: states before each op recomputed
   from checkpoints, and Alg. 2 with channel inverses (two states); at n = 8
-  also the oracle's inverse form on the host;
+  also the oracle's inverse form on the host; and the batch of 32 such
+  circuits with n in {8, 10, 12} (forward + backward per batch, both forms);
 * bitstring sampling from the 28-qubit output state (2^20 samples, the
   paper's random-circuit sampling use) and measure! of one qubit;
+* single unfused ops on the same state (dense one-, two- and three-qubit
+  matrices, CZ) as GB/s against their algorithmic bytes;
 * cpu_baseline: the plain C oracle on this host, timed on a bounded prefix of
   the same 28-qubit circuit.
 
@@ -162,6 +165,33 @@ def vqe_batched(torch, steps):
     return out
 
 
+def single_ops(torch, st, n):
+    """One unfused op per HBM pass on the 28-qubit state (Eqs. (3) and
+    (twoqubitgate), Alg. 1 for three qubits): GB/s from HIP events on the
+    launch stream, against the algorithmic bytes of each op kind."""
+    from paper_2406_19212_amd import workloads as W
+    from paper_2406_19212_amd.workloads import Op
+    N = 1 << n
+    cases = [("dense_1q_q27", Op("matrix", (27,), (), (), W.random_unitary(2, 1)), 32.0),
+             ("dense_2q_q3_q27", Op("matrix", (3, 27), (), (), W.random_unitary(4, 2)), 32.0),
+             ("dense_3q_q0_q13_q27", Op("matrix", (0, 13, 27), (), (), W.random_unitary(8, 3)), 32.0),
+             ("cz_q5_q26", Op("cz", (5, 26)), 8.0)]
+    out = {}
+    for name, op, bpa in cases:
+        st.apply_op(op)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            st.apply_op(op)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 4), "GB_per_s": round(bpa * N / (ms * 1e-3) / 1e9, 1),
+                     "alg_bytes_per_amp": bpa}
+    return out
+
+
 def sampling(torch, st, n):
     """2^20 bitstrings from the 28-qubit output state (uniform numbers drawn
     on the host beforehand; host transfers of u and of the samples included),
@@ -222,6 +252,35 @@ def noisy_backward(torch, with_cpu):
             rec["max_diff_vs_oracle"] = float(np.max(np.abs(res["inverse"] - g_ref)))
         out["n%d" % n] = rec
         del st, c
+    # 32 circuits of n in {8, 10, 12} per batch: forward + backward, both forms
+    from paper_2406_19212_amd import Batch
+    items = W.noisy_batch(W.CONFIG_SEED[3], 32, (8, 10, 12), 20)
+    circs = [Circuit(n, ops, mixed=True, n_params=len(th)) for n, ops, th in items]
+    states = [torch.empty(1 << (2 * n), dtype=torch.complex128, device="cuda") for n, *_ in items]
+    thetas = [torch.tensor(th, device="cuda") for *_, th in items]
+    grads = {f: [torch.zeros(t.numel(), dtype=torch.float64, device="cuda") for t in thetas]
+             for f in ("checkpoint", "inverse")}
+    en = torch.zeros(len(items), dtype=torch.float64, device="cuda")
+    bt = Batch(circs, states, thetas)
+    rec = {"circuits": len(items), "widths": [8, 10, 12]}
+    for form in ("checkpoint", "inverse"):
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bt.forward()
+            if form == "checkpoint":
+                bt.backward(terms, grads[form], en)
+            else:
+                bt.backward_inverse(terms, grads[form], en)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        rec[form + "_s"] = round(best, 4)
+        rec[form + "_circuits_per_s"] = round(len(items) / best, 2)
+    rec["max_grad_diff"] = float(max((a - b).abs().max() for a, b in zip(grads["checkpoint"], grads["inverse"])))
+    out["batch32"] = rec
+    del bt, states
     return out
 
 
@@ -289,6 +348,7 @@ def main():
                       "mean_2n_abs2": float(np.mean(np.abs(amps) ** 2) * amps_n)},
            "roofline": roof}
     rec["sampling"] = sampling(torch, st, n)
+    rec["single_ops"] = single_ops(torch, st, n)
     del st
     torch.cuda.empty_cache()
     if not args.no_vqe:
