@@ -229,9 +229,10 @@ vqc_status vqc_measure(vqc_state s, int qubit, double u, int *outcome_out, doubl
  * or rho[y][y] (MIXED).  Cumulative sums are taken per block of 4096 basis
  * states and then within a block, so an outcome can differ from a plain
  * left-to-right sum only where u_k C lies within rounding of a boundary; a
- * returned x always has w(x) > 0.  The state is not changed.  Host arrays;
- * synchronises.  Errors: VQC_ERR_ARG (u outside [0,1), zero norm),
- * VQC_ERR_NONFINITE. */
+ * returned x has w(x) > 0.  The samples are grouped by block on the device,
+ * so each block of the state is read once however many samples fall in it.
+ * The state is not changed.  count < 2^31.  Host arrays; synchronises.
+ * Errors: VQC_ERR_ARG (u outside [0,1), zero norm), VQC_ERR_NONFINITE. */
 vqc_status vqc_sample(vqc_state s, int count, const double *u_host, int64_t *out_host);
 
 /* fuse_gates(circ) of Sec. 2.3, for noiseless circuits, applied until no

@@ -1549,18 +1549,36 @@ vqc_status vqc_sample(vqc_state s, int count, const double *u, int64_t *out) {
   }
   const int mixed = s->kind == VQC_MIXED;
   const int64_t m = prob_chunks(s->n);
+  const size_t cn = (size_t)std::max(1, count);
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t o_p = al(m * sizeof(double)), o_u = o_p + al(m * sizeof(double));
-  const size_t o_o = o_u + al(std::max(1, count) * sizeof(double));
-  VQC_TRY(s->red.ensure(o_o + al(std::max(1, count) * sizeof(int64_t))));
+  // mass | pref | cnt (2m) | off | u | out | chunk | perm | rem
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += al(bytes);
+    return at;
+  };
+  const size_t o_mass = take(m * sizeof(double)), o_pref = take(m * sizeof(double));
+  const size_t o_cnt = take(2 * m * sizeof(uint32_t)), o_off = take(m * sizeof(uint32_t));
+  const size_t o_u = take(cn * sizeof(double)), o_out = take(cn * sizeof(int64_t));
+  const size_t o_chunk = take(cn * sizeof(int32_t)), o_perm = take(cn * sizeof(int32_t));
+  const size_t o_rem = take(cn * sizeof(double));
+  VQC_TRY(s->red.ensure(o));
   char *base = s->red.as<char>();
-  double *mass = reinterpret_cast<double *>(base), *pref = reinterpret_cast<double *>(base + o_p);
+  SampleBufs sb;
+  sb.mass = reinterpret_cast<double *>(base + o_mass);
+  sb.pref = reinterpret_cast<double *>(base + o_pref);
+  sb.cnt = reinterpret_cast<uint32_t *>(base + o_cnt);
+  sb.off = reinterpret_cast<uint32_t *>(base + o_off);
+  sb.chunk = reinterpret_cast<int32_t *>(base + o_chunk);
+  sb.perm = reinterpret_cast<int32_t *>(base + o_perm);
+  sb.rem = reinterpret_cast<double *>(base + o_rem);
   double *du = reinterpret_cast<double *>(base + o_u);
-  int64_t *dout = reinterpret_cast<int64_t *>(base + o_o);
+  int64_t *dout = reinterpret_cast<int64_t *>(base + o_out);
   if (count > 0) VQC_TRY(hipMemcpyAsync(du, u, count * sizeof(double), hipMemcpyHostToDevice, s->stream));
-  VQC_TRY(launch_sample(s->buf, s->n, mixed, mass, pref, du, count, dout, s->stream));
+  VQC_TRY(launch_sample(s->buf, s->n, mixed, sb, du, count, dout, s->stream));
   double total = 0.0;
-  VQC_TRY(hipMemcpyAsync(&total, pref + (m - 1), sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  VQC_TRY(hipMemcpyAsync(&total, sb.pref + (m - 1), sizeof(double), hipMemcpyDeviceToHost, s->stream));
   if (count > 0) VQC_TRY(hipMemcpyAsync(out, dout, count * sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
   VQC_TRY(hipStreamSynchronize(s->stream));
   if (!is_finite_d(total)) return VQC_ERR_NONFINITE;

@@ -674,6 +674,11 @@ __global__ void k_init_batched(c128 *const *__restrict__ ptrs, const uint64_t *_
     v[i] = make_double2(i == 0 ? 1.0 : 0.0, 0.0);
 }
 
+__global__ void k_fill_u32(uint32_t *__restrict__ v, uint64_t N) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+    v[i] = 0u;
+}
+
 __global__ void k_fill_zero(c128 *__restrict__ v, uint64_t N) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
     v[i] = make_double2(0.0, 0.0);
@@ -779,55 +784,117 @@ __global__ void __launch_bounds__(256) k_prefix(const double *__restrict__ mass,
   }
 }
 
-// step 3: one wave per sample.  The wave finds the first chunk whose running
-// mass exceeds u * total, then, inside it, each lane sums 64 consecutive
-// weights, a wave scan locates the lane holding the target and that lane
-// walks its weights.  Rounding can leave the target past the chunk's last
-// weight; the sample is then the chunk's last basis state of nonzero weight.
-__global__ void __launch_bounds__(256) k_sample(const c128 *__restrict__ v, int n, int mixed,
-                                                const double *__restrict__ pref, int64_t m,
-                                                const double *__restrict__ u, int count, int64_t *__restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (s >= count) return;  // the whole wave leaves together
-  const uint64_t D = 1ull << n;
-  const double target = u[s] * pref[m - 1];
+// step 3: per sample, the first chunk whose running mass exceeds u * total
+// and the mass r still to cover inside it; samples are counted per chunk
+__global__ void __launch_bounds__(256) k_locate(const double *__restrict__ pref, int64_t m,
+                                                const double *__restrict__ u, int count, int32_t *__restrict__ chunk,
+                                                double *__restrict__ rem, uint32_t *__restrict__ cnt) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= count) return;
+  const double target = u[k] * pref[m - 1];
   int64_t lo = 0, hi = m - 1;
   while (lo < hi) {
     const int64_t mid = lo + (hi - lo) / 2;
     if (pref[mid] > target) hi = mid;
     else lo = mid + 1;
   }
-  const double r = target - (lo > 0 ? pref[lo - 1] : 0.0);
-  const uint64_t x0 = (uint64_t)lo * kPChunk + (uint64_t)lane * 64;
-  double w = 0.0;
-  for (int k = 0; k < 64; k++)
-    if (x0 + k < D) w += basis_weight(v, x0 + k, n, mixed);
-  double incl = w;
-  for (int off = 1; off < 64; off <<= 1) {
-    const double y = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += y;
-  }
-  double excl = __shfl_up(incl, 1, 64);
-  if (lane == 0) excl = 0.0;
-  unsigned long long hit = __ballot(incl > r);
-  const bool past = hit == 0;
-  if (past) hit = __ballot(w > 0.0);
-  if (hit == 0) return;  // no mass in the chunk (not reached: its prefix step is positive)
-  const int L = past ? 63 - __clzll(hit) : __ffsll((long long)hit) - 1;
-  if (lane == L) {
-    double c = excl;
-    int64_t pick = -1, last = -1;
-    for (int k = 0; k < 64 && x0 + k < D; k++) {
-      const double wk = basis_weight(v, x0 + k, n, mixed);
-      if (wk > 0.0) last = (int64_t)(x0 + k);
-      c += wk;
-      if (!past && c > r) {
-        pick = (int64_t)(x0 + k);
-        break;
-      }
+  chunk[k] = (int32_t)lo;
+  rem[k] = target - (lo > 0 ? pref[lo - 1] : 0.0);
+  atomicAdd(&cnt[lo], 1u);
+}
+
+// step 4: exclusive prefix of the per-chunk counts (one block, as k_prefix)
+__global__ void __launch_bounds__(256) k_count_offsets(const uint32_t *__restrict__ cnt, int64_t m,
+                                                       uint32_t *__restrict__ off) {
+  __shared__ uint32_t seg[256];
+  const int t = threadIdx.x;
+  const int64_t per = (m + 255) / 256, i0 = t * per, i1 = i0 + per < m ? i0 + per : m;
+  uint32_t s = 0;
+  for (int64_t i = i0; i < i1; i++) s += cnt[i];
+  seg[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t c = 0;
+    for (int k = 0; k < 256; k++) {
+      const uint32_t x = seg[k];
+      seg[k] = c;
+      c += x;
     }
-    out[s] = pick >= 0 ? pick : last;
+  }
+  __syncthreads();
+  uint32_t c = seg[t];
+  for (int64_t i = i0; i < i1; i++) {
+    off[i] = c;
+    c += cnt[i];
+  }
+}
+
+// step 5: sample indices grouped by chunk
+__global__ void __launch_bounds__(256) k_bucket(const int32_t *__restrict__ chunk, int count,
+                                                const uint32_t *__restrict__ off, uint32_t *__restrict__ cursor,
+                                                int32_t *__restrict__ perm) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= count) return;
+  const int32_t b = chunk[k];
+  perm[off[b] + atomicAdd(&cursor[b], 1u)] = k;
+}
+
+// step 6: one block per chunk that holds samples.  The chunk's kPChunk
+// weights are read once into LDS with their running sums (16 consecutive
+// weights per thread, then the threads' offsets); each of the chunk's samples
+// takes the first basis state whose running sum exceeds its r.  Rounding can
+// leave r past the chunk's last running sum; the sample is then the chunk's
+// last basis state of nonzero weight.
+__global__ void __launch_bounds__(256) k_resolve(const c128 *__restrict__ v, int n, int mixed,
+                                                 const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ off,
+                                                 const int32_t *__restrict__ perm, const double *__restrict__ rem,
+                                                 int64_t *__restrict__ out) {
+  __shared__ double P[kPChunk];
+  __shared__ double seg[256];
+  __shared__ int last_nz;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const uint32_t nb = cnt[b];
+  if (nb == 0) return;  // the whole block leaves together
+  const uint64_t D = 1ull << n, base = (uint64_t)b * kPChunk;
+  double w[16];
+  double s = 0.0;
+  int my_last = -1;
+  for (int k = 0; k < 16; k++) {
+    const uint64_t x = base + (uint64_t)t * 16 + k;
+    w[k] = x < D ? basis_weight(v, x, n, mixed) : 0.0;
+    s += w[k];
+    if (w[k] > 0.0) my_last = t * 16 + k;
+  }
+  seg[t] = s;
+  if (t == 0) last_nz = -1;
+  __syncthreads();
+  atomicMax(&last_nz, my_last);
+  if (t == 0) {
+    double c = 0.0;
+    for (int k = 0; k < 256; k++) {
+      const double x = seg[k];
+      seg[k] = c;
+      c += x;
+    }
+  }
+  __syncthreads();
+  double c = seg[t];
+  for (int k = 0; k < 16; k++) {
+    c += w[k];
+    P[t * 16 + k] = c;
+  }
+  __syncthreads();
+  for (uint32_t j = t; j < nb; j += 256) {
+    const int32_t k = perm[off[b] + j];
+    const double r = rem[k];
+    int lo = 0, hi = kPChunk - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      if (P[mid] > r) hi = mid;
+      else lo = mid + 1;
+    }
+    const int pick = (P[lo] > r || last_nz < 0) ? lo : last_nz;
+    out[k] = (int64_t)(base + (uint64_t)pick);
   }
 }
 
@@ -1001,13 +1068,19 @@ hipError_t launch_collapse(c128 *v, uint64_t len, int n, int mixed, int q, int o
   return hipGetLastError();
 }
 
-hipError_t launch_sample(const c128 *v, int n, int mixed, double *mass, double *pref, const double *u, int count,
+hipError_t launch_sample(const c128 *v, int n, int mixed, const SampleBufs &sb, const double *u, int count,
                          int64_t *out, hipStream_t st) {
   const int64_t m = prob_chunks(n);
-  hipLaunchKernelGGL(k_chunk_mass, dim3((unsigned)m), dim3(256), 0, st, v, n, mixed, mass);
-  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(256), 0, st, mass, m, pref);
-  if (count > 0)
-    hipLaunchKernelGGL(k_sample, dim3((count + 3) / 4), dim3(256), 0, st, v, n, mixed, pref, m, u, count, out);
+  hipLaunchKernelGGL(k_chunk_mass, dim3((unsigned)m), dim3(256), 0, st, v, n, mixed, sb.mass);
+  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(256), 0, st, sb.mass, m, sb.pref);
+  if (count <= 0) return hipGetLastError();
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(2 * m, 256)), dim3(256), 0, st, sb.cnt, (uint64_t)(2 * m));
+  const unsigned gs = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL(k_locate, dim3(gs), dim3(256), 0, st, sb.pref, m, u, count, sb.chunk, sb.rem, sb.cnt);
+  hipLaunchKernelGGL(k_count_offsets, dim3(1), dim3(256), 0, st, sb.cnt, m, sb.off);
+  hipLaunchKernelGGL(k_bucket, dim3(gs), dim3(256), 0, st, sb.chunk, count, sb.off, sb.cnt + m, sb.perm);
+  hipLaunchKernelGGL(k_resolve, dim3((unsigned)m), dim3(256), 0, st, v, n, mixed, sb.cnt, sb.off, sb.perm, sb.rem,
+                     out);
   return hipGetLastError();
 }
 

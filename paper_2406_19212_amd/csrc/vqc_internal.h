@@ -239,7 +239,15 @@ int64_t prob_chunks(int n);  // blocks of basis states of the measurement / samp
 hipError_t launch_bit_mass(const c128 *v, int n, int mixed, int q, double2 *part, double2 *out, hipStream_t st);
 hipError_t launch_collapse(c128 *v, uint64_t len, int n, int mixed, int q, int outcome, double scale,
                            hipStream_t st);
-hipError_t launch_sample(const c128 *v, int n, int mixed, double *mass, double *pref, const double *u, int count,
+// device buffers of one sampling call (m = prob_chunks(n) chunks, `count` samples)
+struct SampleBufs {
+  double *mass, *pref;   // [m] chunk masses and their running sums
+  uint32_t *cnt;         // [2 m] samples per chunk, then the bucketing cursors
+  uint32_t *off;         // [m] first bucket slot of each chunk
+  int32_t *chunk, *perm; // [count] chunk of each sample; sample indices by chunk
+  double *rem;           // [count] mass left to cover inside the chunk
+};
+hipError_t launch_sample(const c128 *v, int n, int mixed, const SampleBufs &sb, const double *u, int count,
                          int64_t *out, hipStream_t st);
 hipError_t launch_set_mat(c128 *dst, const c128 *m, int count, hipStream_t st);
 
