@@ -34,6 +34,9 @@ def units():
                     continue
                 out.append(("inst_lds.hip", UNIFORM_CF + ["-DVQC_K=%d" % K, "-DVQC_R=%d" % R, "-DVQC_ADJ=%d" % A],
                             "lds_%d_%d_%d" % (K, R, A)))
+    # density matrices of at least 6 qubits: 11-bit tiles with 16x16 superoperators
+    for A in (2, 3):
+        out.append(("inst_lds.hip", UNIFORM_CF + ["-DVQC_K=11", "-DVQC_R=4", "-DVQC_ADJ=%d" % A], "lds_11_4_%d" % A))
     for R in (1, 2, 3, 4):
         for M in (0, 1, 2, 3):
             out.append(("inst_reg.hip", UNIFORM_CF + ["-DVQC_R=%d" % R, "-DVQC_MODE=%d" % M], "reg_%d_%d" % (R, M)))

@@ -32,6 +32,11 @@ constexpr int kRemapMinBits = 12;
 // the adjoint's moves need four states; above this many qubits its plan keeps
 // the standard layout
 constexpr int kAdjRemapMaxBits = 30;
+// density matrices with at least this many vec(rho) bits run their forward and
+// inverse-form adjoint on 11-bit LDS tiles (the 16x16 superoperator kind is
+// compiled into that instantiation only)
+constexpr int kMixedLdsMinBits = 12;
+constexpr int kMixedTile = 11;
 constexpr int kR = 4;
 
 #define VQC_TRY(expr)                                         \
@@ -256,6 +261,7 @@ struct PassH {
 struct Plan {
   bool reg_only = false;
   bool remap = false;          // passes move qubits between the low block and the rest
+  bool d4 = false;             // LDS passes with 16x16 superoperators (density matrices)
   bool needs_scratch = false;  // some pass runs out of place
   int K = 0, R = kR, c = kDefaultLow;
   std::vector<PassH> passes;
@@ -278,6 +284,7 @@ void reset_plan(Plan &P) {
   P.passes.clear();
   P.reg_only = false;
   P.remap = false;
+  P.d4 = false;
   P.needs_scratch = false;
   P.n_stages = 0;
   P.units_per_item = 0;
@@ -567,7 +574,11 @@ struct vqc_circuit_s {
   bool has_nonunitary_matrix = false;
   std::vector<DInv> inv_list;  // non-unitary ops (mixed): matrices to invert
   DevBuf dinv;                 // condition-number word, then inv_list
-  Plan fwd, adj;   // pure: LDS forward + LDS adjoint; mixed: register-only, shared
+  Plan fwd, adj;   // pure: LDS forward + LDS adjoint; small mixed: register-only
+  // mixed states of at least kMixedLdsMinBits vec(rho) bits: fwd and adj_lds
+  // (inverse-form adjoint) on LDS tiles; adj and fwd_reg register-only with
+  // one pass structure (the checkpointed adjoint and its forward recompute)
+  Plan fwd_reg, adj_lds;
   DevBuf scratch;  // second state buffer for passes that move qubits (Phi in the adjoint)
   DevBuf scratch2; // second Psi buffer for adjoint passes that move qubits
   DevBuf dconst;   // recipes, constant data, csr
@@ -967,7 +978,8 @@ vqc_status make_plans(vqc_circuit c) {
   int K = c->tune.tile_bits > 0 ? c->tune.tile_bits : kDefaultTile;
   int low = c->tune.low_bits > 0 ? c->tune.low_bits : kDefaultLow;
   if (K > kMaxTile) K = kMaxTile;
-  const bool reg_only = mixed || nb < 5;
+  const bool mixed_lds = mixed && nb >= kMixedLdsMinBits;
+  const bool reg_only = (mixed && !mixed_lds) || nb < 5;
   int R = std::min(kR, nb);
   // the adjoint step keeps two states and runs derivative reductions: three
   // register bits (more waves per SIMD) beat four there, while four are best
@@ -979,8 +991,33 @@ vqc_status make_plans(vqc_circuit c) {
     Radj = 3;
   }
   // op programs follow the recipe outputs in each item's matrix buffer
+  reset_plan(c->fwd_reg);
+  reset_plan(c->adj_lds);
+  c->fwd.d4 = c->adj.d4 = false;
   c->fwd.prog = c->mat_size;
-  if (reg_only) {
+  auto prog_end = [](const Plan &P) { return P.prog + (P.n_gates + 2) * kOpSlots; };
+  if (mixed_lds) {
+    const int lowm = std::min(low, kMixedTile - 4);  // a two-qubit superoperator spans 4 bits
+    const bool remap = c->tune.remap > 0 || (c->tune.remap == 0 && nb >= kRemapMinBits);
+    plan_passes(c->elems, nb, kMixedTile, lowm, 4, false, c->fwd, 0, remap);
+    c->fwd.d4 = true;
+    vqc_status st = upload_plan(c, c->fwd, false);
+    if (st) return st;
+    c->adj.prog = prog_end(c->fwd);
+    plan_passes(c->elems, nb, 4, 0, 4, true, c->adj, kMaxVarPerPass);
+    st = upload_plan(c, c->adj, true);
+    if (st) return st;
+    c->fwd_reg.prog = prog_end(c->adj);
+    plan_passes(c->elems, nb, 4, 0, 4, true, c->fwd_reg, kMaxVarPerPass);
+    st = upload_plan(c, c->fwd_reg, false);
+    if (st) return st;
+    c->adj_lds.prog = prog_end(c->fwd_reg);
+    plan_passes(c->elems, nb, kMixedTile, lowm, 4, false, c->adj_lds, kMaxVarPerPass,
+                remap && nb <= kAdjRemapMaxBits, true);
+    c->adj_lds.d4 = true;
+    st = upload_plan(c, c->adj_lds, true);
+    if (st) return st;
+  } else if (reg_only) {
     plan_passes(c->elems, nb, R, 0, R, true, c->fwd, kMaxVarPerPass);
     vqc_status st = upload_plan(c, c->fwd, false);
     if (st) return st;
@@ -1005,9 +1042,9 @@ vqc_status make_plans(vqc_circuit c) {
     st = upload_plan(c, c->adj, true);
     if (st) return st;
   }
-  c->mat_total = c->adj.prog + (c->adj.n_gates + 2) * kOpSlots;
+  c->mat_total = std::max(prog_end(c->adj), c->adj_lds.passes.empty() ? 0 : prog_end(c->adj_lds));
   if (c->mats1.ensure((size_t)c->mat_total * sizeof(c128)) != hipSuccess) return VQC_ERR_HIP;
-  if ((c->fwd.needs_scratch || c->adj.needs_scratch) &&
+  if ((c->fwd.needs_scratch || c->adj.needs_scratch || c->adj_lds.needs_scratch) &&
       c->scratch.ensure((size_t(1) << nb) * sizeof(c128)) != hipSuccess)
     return VQC_ERR_OOM;
   c->tune.tile_bits = c->fwd.K;
@@ -1087,7 +1124,14 @@ int grid_of(vqc_circuit c, int64_t units) {
   return (int)std::min<int64_t>(units, int64_t(1) << 30);
 }
 
-// matrices, rotation records and the op programs of both plans for B items
+// forward plan whose passes line up with the register-only adjoint (the
+// checkpointed mixed backward recomputes states pass by pass)
+Plan &ck_fwd(vqc_circuit c) { return c->fwd_reg.passes.empty() ? c->fwd : c->fwd_reg; }
+// adjoint plan of the inverse-form mixed backward (and of batches)
+Plan &inv_adj(vqc_circuit c) { return c->adj_lds.passes.empty() ? c->adj : c->adj_lds; }
+Plan &batch_adj(vqc_circuit c) { return c->kind == VQC_MIXED ? inv_adj(c) : c->adj; }
+
+// matrices, rotation records and the op programs of every plan for B items
 // (thetas / mats per item) or one item (theta0 / mats0)
 hipError_t build_mats(vqc_circuit c, const double *const *thetas, c128 *const *mats, int B, const double *theta0,
                       c128 *mats0, hipStream_t st) {
@@ -1095,6 +1139,11 @@ hipError_t build_mats(vqc_circuit c, const double *const *thetas, c128 *const *m
   if (e != hipSuccess) return e;
   e = launch_assemble(c->fwd.d_gates, c->fwd.d_derivs, c->fwd.n_gates, c->fwd.prog, mats, B, mats0, st);
   if (e != hipSuccess) return e;
+  for (const Plan *P : {&c->fwd_reg, &c->adj_lds})
+    if (!P->passes.empty()) {
+      e = launch_assemble(P->d_gates, P->d_derivs, P->n_gates, P->prog, mats, B, mats0, st);
+      if (e != hipSuccess) return e;
+    }
   return launch_assemble(c->adj.d_gates, c->adj.d_derivs, c->adj.n_gates, c->adj.prog, mats, B, mats0, st);
 }
 
@@ -1136,7 +1185,7 @@ hipError_t run_passes(vqc_circuit c, Plan &P, int mode, c128 *a, c128 *b, const 
     }
     hipError_t e;
     if (P.reg_only) e = launch_pass_reg(P.R, mode, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
-    else e = launch_pass_lds(P.K, P.R, mode != 0, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
+    else e = launch_pass_lds(P.K, P.R, mode != 0, P.d4, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1973,6 +2022,7 @@ static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s,
   const uint64_t N = state_len(c->kind, c->n);
   c128 *mats = c->mats1.as<c128>();
   Plan &P = c->adj;
+  Plan *PG = &P;  // the plan whose partials hold the gradient
   const int np = (int)P.passes.size();
   VQC_TRY(c->part1.ensure(std::max<size_t>(1, (size_t)c->n_gslots) * P.units_per_item * sizeof(double) + 256));
   double2 *dres = nullptr;
@@ -2012,7 +2062,14 @@ static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s,
     VQC_TRY(launch_seed_mixed(psi, c->n, c->small.as<DTerm>(), (int)tt.size(), st));
     vs = seed_and_energy(c, terms, s->buf, nullptr, st, &dres);
     if (vs) return vs;
-    VQC_TRY(run_passes(c, P, 3, s->buf, psi, mats, c->part1.as<double>(), 0, np, -1, st));
+    Plan &PI = inv_adj(c);
+    PG = &PI;
+    VQC_TRY(c->part1.ensure(std::max<size_t>(1, (size_t)c->n_gslots) * PI.units_per_item * sizeof(double) + 256));
+    if (PI.needs_scratch && c->scratch2.ensure(N * sizeof(c128)) != hipSuccess) return VQC_ERR_OOM;
+    // register-only plans take the inverse-form mode; LDS plans apply M^{-1}
+    // for the ops flagged non-unitary in their adjoint step
+    VQC_TRY(run_passes(c, PI, PI.reg_only ? 3 : 1, s->buf, psi, mats, c->part1.as<double>(), 0,
+                       (int)PI.passes.size(), -1, st));
   } else {
     // checkpoints every `stride` passes; a segment of states is recomputed
     // from its checkpoint before its backward steps
@@ -2035,9 +2092,10 @@ static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s,
     VQC_TRY(build_mats(c, nullptr, nullptr, 1, theta, mats, st));
     if (init_dev) VQC_TRY(launch_copy(W, reinterpret_cast<const c128 *>(init_dev), N, st));
     else VQC_TRY(launch_init_basis0(W, N, st));
+    Plan &F = ck_fwd(c);
     for (int p = 0; p < np; p++) {
       if (p % sd == 0) VQC_TRY(launch_copy(ck0 + (size_t)(p / sd) * N, W, N, st));
-      VQC_TRY(run_passes(c, c->fwd, 0, W, nullptr, mats, nullptr, p, p + 1, 1, st));
+      VQC_TRY(run_passes(c, F, 0, W, nullptr, mats, nullptr, p, p + 1, 1, st));
     }
     {
       // vec(H) needs the terms on device
@@ -2054,7 +2112,7 @@ static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s,
       const int s0 = k * sd, s1 = std::min(np, s0 + sd);
       auto segp = [&](int i) { return i == 0 ? ck0 + (size_t)k * N : seg0 + (size_t)(i - 1) * N; };
       for (int i = 1; i < s1 - s0; i++)
-        VQC_TRY(run_passes(c, c->fwd, 0, segp(i - 1), segp(i), mats, nullptr, s0 + i - 1, s0 + i, 1, st));
+        VQC_TRY(run_passes(c, F, 0, segp(i - 1), segp(i), mats, nullptr, s0 + i - 1, s0 + i, 1, st));
       for (int p = s1 - 1; p >= s0; p--)
         VQC_TRY(run_passes(c, P, 2, segp(p - s0), psi, mats, c->part1.as<double>(), p, p + 1, 1, st));
     }
@@ -2062,7 +2120,7 @@ static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s,
   if (c->n_params > 0) {
     DGradJob gj;
     gj.partials = c->part1.as<double>();
-    gj.n_units = P.units_per_item;
+    gj.n_units = PG->units_per_item;
     gj.grad = grad;
     gj.csr_ptr = c->d_csr_ptr;
     gj.csr_slot = c->d_csr_slot;
@@ -2158,11 +2216,11 @@ static vqc_status batch_build_tables(vqc_batch b) {
     b->psi_off[i] = ptot;
     ptot += al(state_len(c->kind, c->n) * sizeof(c128));  // allocated by the backward
     b->part_off[i] = qtot;
-    qtot += al(std::max(1, c->n_gslots) * c->adj.units_per_item * sizeof(double));
+    qtot += al(std::max(1, c->n_gslots) * batch_adj(c).units_per_item * sizeof(double));
     e_off[i] = etot;
     etot += expect_units(c->n);
     b->max_passes = std::max(b->max_passes, (int)c->fwd.passes.size());
-    b->max_adj = std::max(b->max_adj, (int)c->adj.passes.size());
+    b->max_adj = std::max(b->max_adj, (int)batch_adj(c).passes.size());
     b->max_params = std::max(b->max_params, c->n_params);
   }
   b->e_units = etot;
@@ -2174,7 +2232,7 @@ static vqc_status batch_build_tables(vqc_batch b) {
     vqc_circuit c = b->circ[i];
     b->scr_off[i] = stot;
     const size_t sb = al(state_len(c->kind, c->n) * sizeof(c128));
-    const bool adj = b->psi.p && c->kind == VQC_PURE && c->adj.needs_scratch;
+    const bool adj = b->psi.p && batch_adj(c).needs_scratch;
     if (c->fwd.needs_scratch || adj) stot += sb;
     if (adj) stot += sb;
   }
@@ -2243,7 +2301,8 @@ static vqc_status batch_build_tables(vqc_batch b) {
     int64_t u0 = 0;
     for (int i = 0; i < B; i++) {
       vqc_circuit c = b->circ[i];
-      const int PA = (int)c->adj.passes.size();
+      const Plan &A = batch_adj(c);
+      const int PA = (int)A.passes.size();
       if (r >= PA) continue;
       DJob j;
       std::memset(&j, 0, sizeof(j));
@@ -2251,19 +2310,19 @@ static vqc_status batch_build_tables(vqc_batch b) {
       j.b = reinterpret_cast<c128 *>(b->psi.p ? b->psi.as<char>() + b->psi_off[i] : nullptr);
       j.mats = reinterpret_cast<const c128 *>(b->mats.as<char>() + b->mat_off[i]);
       j.partials = reinterpret_cast<double *>(b->part.p ? b->part.as<char>() + b->part_off[i] : nullptr);
-      if (b->psi.p && c->adj.needs_scratch) {
+      if (b->psi.p && A.needs_scratch) {
         // reverse order: read the pass's destination, write its source
         c128 *bufs[2] = {j.a, scr_state(i, 0)}, *bufb[2] = {j.b, scr_state(i, 1)};
-        const PassH &ph = c->adj.passes[PA - 1 - r];
+        const PassH &ph = A.passes[PA - 1 - r];
         j.a = bufs[ph.dst];
         j.b = bufb[ph.dst];
         j.a2 = bufs[ph.src];
         j.b2 = bufb[ph.src];
         j.mode = ph.src != ph.dst ? 1 : 0;
       }
-      j.pass = c->adj.d_pass + (PA - 1 - r);
+      j.pass = A.d_pass + (PA - 1 - r);
       j.unit0 = u0;
-      j.n_units = c->adj.units_per_item;
+      j.n_units = A.units_per_item;
       j.nbits = c->nbits;
       u0 += j.n_units;
       aj.push_back(j);
@@ -2335,7 +2394,8 @@ static vqc_status batch_forward_on(vqc_batch b, hipStream_t st) {
     const int grid = grid_of(c0, units);
     const DJob *jobs = b->d_fwd_jobs + b->fwd_first[sI];
     if (b->reg_only) VQC_TRY(launch_pass_reg(c0->fwd.R, 0, jobs, b->fwd_count[sI], units, grid, ov, st));
-    else VQC_TRY(launch_pass_lds(c0->fwd.K, c0->fwd.R, false, jobs, b->fwd_count[sI], units, grid, ov, st));
+    else VQC_TRY(launch_pass_lds(c0->fwd.K, c0->fwd.R, false, c0->fwd.d4, jobs, b->fwd_count[sI], units, grid, ov,
+                                 st));
   }
   return VQC_OK;
 }
@@ -2362,7 +2422,7 @@ static vqc_status batch_ensure_adjoint(vqc_batch b) {
   for (int i = 0; i < b->B; i++) {
     vqc_circuit c = b->circ[i];
     ptot = std::max(ptot, b->psi_off[i] + ((state_len(c->kind, c->n) * sizeof(c128) + 255) & ~size_t(255)));
-    qtot = std::max(qtot, b->part_off[i] + ((std::max(1, c->n_gslots) * c->adj.units_per_item * sizeof(double) + 255) &
+    qtot = std::max(qtot, b->part_off[i] + ((std::max(1, c->n_gslots) * batch_adj(c).units_per_item * sizeof(double) + 255) &
                                             ~size_t(255)));
   }
   VQC_TRY(b->psi.ensure(std::max<size_t>(ptot, 16)));
@@ -2382,7 +2442,7 @@ static vqc_status batch_grad_jobs(vqc_batch b, double *const *grads, bool mixed_
     DGradJob &g = gj[i];
     std::memset(&g, 0, sizeof(g));
     g.partials = reinterpret_cast<const double *>(b->part.as<char>() + b->part_off[i]);
-    g.n_units = c->adj.units_per_item;
+    g.n_units = batch_adj(c).units_per_item;
     g.grad = grads[i];
     g.csr_ptr = c->d_csr_ptr;
     g.csr_slot = c->d_csr_slot;
@@ -2411,7 +2471,7 @@ static vqc_status batch_backward_pure_on(vqc_batch b, double *energies, hipStrea
     const int64_t units = b->adj_units[r];
     const int grid = grid_of(c0, units);
     const DJob *jobs = b->d_adj_jobs + b->adj_first[r];
-    VQC_TRY(launch_pass_lds(c0->adj.K, c0->adj.R, true, jobs, b->adj_count[r], units, grid, ov, st));
+    VQC_TRY(launch_pass_lds(c0->adj.K, c0->adj.R, true, false, jobs, b->adj_count[r], units, grid, ov, st));
   }
   VQC_TRY(launch_grad_reduce(b->d_gjobs, b->B, b->max_params, st));
   return VQC_OK;
@@ -2425,8 +2485,9 @@ vqc_status vqc_batch_create(vqc_batch *out, int B, const vqc_circuit *circuits, 
     if (circuits[i]->n_params > 0 && (!thetas || !thetas[i])) return VQC_ERR_ARG;
     const vqc_circuit c = circuits[i], c0 = circuits[0];
     if (c->kind != c0->kind) return VQC_ERR_KIND;
+    const Plan &A = batch_adj(c), &A0 = batch_adj(c0);
     if (c->fwd.reg_only != c0->fwd.reg_only || c->fwd.K != c0->fwd.K || c->fwd.R != c0->fwd.R ||
-        c->adj.K != c0->adj.K || c->adj.R != c0->adj.R || c->adj.reg_only != c0->adj.reg_only)
+        c->fwd.d4 != c0->fwd.d4 || A.K != A0.K || A.R != A0.R || A.reg_only != A0.reg_only || A.d4 != A0.d4)
       return VQC_ERR_UNSUPPORTED;
   }
   std::unique_ptr<vqc_batch_s> b(new (std::nothrow) vqc_batch_s());
@@ -2556,7 +2617,9 @@ vqc_status vqc_batch_backward_inverse(vqc_batch b, const vqc_pauli_sum *H, doubl
     const int64_t units = b->adj_units[r];
     const int grid = grid_of(c0, units);
     const DJob *jobs = b->d_adj_jobs + b->adj_first[r];
-    VQC_TRY(launch_pass_reg(c0->adj.R, 3, jobs, b->adj_count[r], units, grid, ov, s));
+    const Plan &A0 = inv_adj(c0);
+    if (A0.reg_only) VQC_TRY(launch_pass_reg(A0.R, 3, jobs, b->adj_count[r], units, grid, ov, s));
+    else VQC_TRY(launch_pass_lds(A0.K, A0.R, true, A0.d4, jobs, b->adj_count[r], units, grid, ov, s));
   }
   VQC_TRY(launch_grad_reduce(b->d_gjobs, b->B, b->max_params, s));
   return VQC_OK;

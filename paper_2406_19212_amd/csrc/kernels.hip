@@ -930,10 +930,11 @@ static int grid_for(uint64_t work, int block) {
 #undef VQC_DECL_LDS
 #undef VQC_DECL_REG
 
-hipError_t launch_pass_lds(int K, int R, bool adj, const DJob *jobs, int n_jobs, int64_t total, int grid,
+hipError_t launch_pass_lds(int K, int R, bool adj, bool d4, const DJob *jobs, int n_jobs, int64_t total, int grid,
                            const DOverride &ov, hipStream_t st) {
+  const int mode = (adj ? 1 : 0) | (d4 ? 2 : 0);
 #define VQC_DECL_LDS(KK, RR, AA) \
-  if (K == KK && R == RR && (int)adj == AA) return launch_lds_##KK##_##RR##_##AA(jobs, n_jobs, total, grid, ov, st);
+  if (K == KK && R == RR && mode == AA) return launch_lds_##KK##_##RR##_##AA(jobs, n_jobs, total, grid, ov, st);
 #define VQC_DECL_REG(RR, MM)
 #include "inst_list.h"
 #undef VQC_DECL_LDS

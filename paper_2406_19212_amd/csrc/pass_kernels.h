@@ -791,9 +791,13 @@ __device__ __forceinline__ int find_job(const JT *__restrict__ jobs, int n_jobs,
 
 // ------------------------------------------------------------ fused LDS pass
 
-template <int K, int R, bool ADJ>
+// MODE bit 0: the adjoint step; bit 1: 16x16 superoperators compiled in
+// (density matrices), whose adjoint takes M^{-1} for non-unitary ops
+template <int K, int R, int MODE>
 __global__ void __launch_bounds__(1 << (K - R))
 k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOverride ov) {
+  constexpr bool ADJ = (MODE & 1) != 0;
+  constexpr bool D4 = (MODE & 2) != 0;
   constexpr int T = 1 << (K - R);
   constexpr int NR = 1 << R;
   constexpr int WS = T < 64 ? T : 64;
@@ -941,7 +945,7 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
         }
       }
       if constexpr (!ADJ) {
-        rg_run<R, false>(a, prog, S.g0, S.g1, MT);
+        rg_run<R, D4>(a, prog, S.g0, S.g1, MT);
       } else {
         DOp E = ldc(&prog[S.g1 - 1]);
         for (int g = S.g1 - 1; g >= S.g0; g--) {
@@ -956,14 +960,22 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
             }
             for (int d = 0; d < nd; d++) {
               const DDeriv Dd = ldc(&P->derivs[E.g.d0 + d]);
-              double v = wave_sum<WS>(rg_grad<R, false>(a, b, E.g, Dd, MT));
+              double v = wave_sum<WS>(rg_grad<R, D4>(a, b, E.g, Dd, MT));
               if (lane == 0) red[Dd.local][wave] = v;
             }
           };
-          if (E.g.nd & kGenFlag) grads();         // generator form: Phi after Q
-          rg_apply_op<R, true, false>(a, E, MT);  // Phi <- Q^dagger Phi
-          if (!(E.g.nd & kGenFlag)) grads();
-          rg_apply_op<R, true, false>(b, E, MT);  // Psi <- Q^dagger Psi
+          // generator form (pure states only): Phi after Q; density
+          // matrices keep one call site of the reductions (no spills)
+          if (!D4 && (E.g.nd & kGenFlag)) grads();
+          if (D4 && (E.g.nd & kInvFlag)) {  // Phi <- M^{-1} Phi (stored after M)
+            DOp Ei = E;
+            Ei.g.mat += E.g.kind == GK_DENSE4 ? 256 : 16;
+            rg_apply_op<R, false, D4>(a, Ei, MT);
+          } else {
+            rg_apply_op<R, true, D4>(a, E, MT);  // Phi <- Q^dagger Phi
+          }
+          if (D4 || !(E.g.nd & kGenFlag)) grads();
+          rg_apply_op<R, true, D4>(b, E, MT);  // Psi <- Q^dagger Psi
           E = En;
         }
       }
@@ -1016,6 +1028,9 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
       }
     }
     if constexpr (ADJ) {
+      // a last stage stored straight to HBM has no barrier after its
+      // reductions: wait for every wave's entries before summing them
+      if (dout) __syncthreads();
       const int nv = P->nvar;
       for (int v = t; v < nv; v += T) {
         double s = 0.0;
@@ -1152,13 +1167,13 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
 }
 
 
-template <int K, int R, bool ADJ>
+template <int K, int R, int MODE>
 hipError_t launch_lds_t(const DJob *jobs, int n_jobs, int64_t total, int grid, const DOverride &ov,
                         hipStream_t st) {
-  const size_t shmem = (ADJ ? 2 : 1) * (size_t(1) << K) * sizeof(c128);
+  const size_t shmem = ((MODE & 1) ? 2 : 1) * (size_t(1) << K) * sizeof(c128);
   static bool attr_set = false;
   if (!attr_set && shmem > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_pass_lds<K, R, ADJ>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_pass_lds<K, R, MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
     attr_set = true;
@@ -1171,13 +1186,13 @@ hipError_t launch_lds_t(const DJob *jobs, int n_jobs, int64_t total, int grid, c
       int per_cu = 0, dev = 0, cus = 0;
       (void)hipGetDevice(&dev);
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_pass_lds<K, R, ADJ>, 1 << (K - R),
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_pass_lds<K, R, MODE>, 1 << (K - R),
                                                          shmem);
       resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 256);
     }
     g = (int)(total < resident ? total : resident);
   }
-  hipLaunchKernelGGL((k_pass_lds<K, R, ADJ>), dim3(g), dim3(1 << (K - R)), shmem, st, jobs, n_jobs, total, ov);
+  hipLaunchKernelGGL((k_pass_lds<K, R, MODE>), dim3(g), dim3(1 << (K - R)), shmem, st, jobs, n_jobs, total, ov);
   return hipGetLastError();
 }
 

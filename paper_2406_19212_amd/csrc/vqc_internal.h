@@ -210,7 +210,7 @@ struct DGradJob {
 };
 
 // launchers (kernels.hip)
-hipError_t launch_pass_lds(int K, int R, bool adj, const DJob *jobs, int n_jobs, int64_t total, int grid,
+hipError_t launch_pass_lds(int K, int R, bool adj, bool d4, const DJob *jobs, int n_jobs, int64_t total, int grid,
                            const DOverride &ov, hipStream_t st);
 hipError_t launch_pass_reg(int R, int mode, const DJob *jobs, int n_jobs, int64_t total, int grid,
                            const DOverride &ov, hipStream_t st);
