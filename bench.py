@@ -333,7 +333,7 @@ def main():
     traffic = measured_traffic()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_pass_lds<%d,%d,false>" % (stats["tile_bits"], stats["reg_bits"]),
+            "kernel": "k_pass_lds<%d,%d,0>" % (stats["tile_bits"], stats["reg_bits"]),
             "avg_pass_ms": round(avg_ms, 4), "passes": stats["n_passes"], "bytes_per_pass": pass_bytes,
             "kernel_digest": kernel_digest()}
 

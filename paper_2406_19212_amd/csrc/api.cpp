@@ -449,7 +449,8 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
           uint64_t lm = 0;
           for (int t = 0; t < E[i].nq; t++) lm |= 1ull << loc[E[i].q[t]];
           bool ok = !(lm & sblk) && popc(reg | lm) <= R;
-          if (ok && E[i].kind == GK_DENSE4) {
+          const bool ordered = E[i].kind == GK_DENSE4 || E[i].kind == GK_DEPOL4;  // register bits 0..3 in order
+          if (ok && ordered) {
             if (order4[0] >= 0) {
               for (int t = 0; t < 4; t++)
                 if (order4[t] != loc[E[i].q[t]]) ok = false;
@@ -461,7 +462,7 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
           if (!ok) { sblk |= lm; sleft.push_back(i); continue; }
           reg |= lm;
           st.push_back(i);
-          if (E[i].kind == GK_DENSE4 && order4[0] < 0)
+          if (ordered && order4[0] < 0)
             for (int t = 0; t < 4; t++) order4[t] = loc[E[i].q[t]];
         }
         if (st.empty()) {
@@ -775,7 +776,7 @@ vqc_status lower(vqc_circuit c) {
     if (is_channel(op.type)) {
       Elem e;
       e.nq = 2 * m;
-      e.kind = m == 1 ? GK_DENSE2 : GK_DENSE4;
+      e.kind = m == 1 ? GK_DENSE2 : (op.type == VQC_DEPOLARIZING2 ? GK_DEPOL4 : GK_DENSE4);
       for (int t = 0; t < m; t++) { e.q[t] = op.qubits[t]; e.q[t + m] = op.qubits[t] + n; }
       e.mat = add_recipe(c, op.type, RF_SUPER_KRAUS, 0, m, op, data_off, n_data, d * d * d * d);
       e.inv = true;

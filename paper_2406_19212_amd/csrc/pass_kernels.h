@@ -263,6 +263,28 @@ __device__ __forceinline__ void rg_cx(c128 (&a)[NR]) {
   }
 }
 
+// a I + b |I>><<I| on four bits (ket pair, bra pair): every entry scaled by
+// a, and b times the sum of the four diagonal entries (x = y: local 0, 5,
+// 10, 15) added to each of them; real and symmetric, so its adjoint is itself
+template <int NR>
+__device__ __forceinline__ void rg_depol4(c128 (&a)[NR], cmat *M) {
+  if constexpr (NR == 16) {
+    const double al = M[1 * 16 + 1].x, be = M[0 * 16 + 5].x;
+    const double sr = (a[0].x + a[5].x) + (a[10].x + a[15].x);
+    const double si = (a[0].y + a[5].y) + (a[10].y + a[15].y);
+#pragma unroll
+    for (int l = 0; l < 16; l++) {
+      a[l].x *= al;
+      a[l].y *= al;
+    }
+#pragma unroll
+    for (int l = 0; l < 16; l += 5) {
+      a[l].x = fma(be, sr, a[l].x);
+      a[l].y = fma(be, si, a[l].y);
+    }
+  }
+}
+
 template <int NR, bool ADJ>
 __device__ __forceinline__ void rg_dense4(c128 (&a)[NR], cmat *M) {
   if constexpr (NR == 16) {
@@ -606,6 +628,9 @@ __device__ __forceinline__ void rg_apply_generic(c128 (&a)[1 << R], const DGate 
     case GK_DENSE4:
       if constexpr (D4) rg_dense4<NR, ADJ>(a, M);
       break;
+    case GK_DEPOL4:
+      if constexpr (D4) rg_depol4<NR>(a, M);
+      break;
     default: break;
   }
 }
@@ -624,7 +649,7 @@ __device__ __forceinline__ void rg_apply_pre(c128 (&a)[1 << R], const DGate &g, 
   constexpr int NR = 1 << R;
   cmat *M = mats + g.mat;
   const int kind = g.kind;
-  if (kind >= GK_SXR1) {
+  if (kind >= GK_SXR1 && kind <= GK_SFX) {
     if (kind == GK_SFX) rg_apply_sfx<R, ADJ>(a, g, rec);
     else rg_apply_s1<R, ADJ>(a, g, rec);
     return;
@@ -969,7 +994,7 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
           if (!D4 && (E.g.nd & kGenFlag)) grads();
           if (D4 && (E.g.nd & kInvFlag)) {  // Phi <- M^{-1} Phi (stored after M)
             DOp Ei = E;
-            Ei.g.mat += E.g.kind == GK_DENSE4 ? 256 : 16;
+            Ei.g.mat += (E.g.kind == GK_DENSE4 || E.g.kind == GK_DEPOL4) ? 256 : 16;
             rg_apply_op<R, false, D4>(a, Ei, MT);
           } else {
             rg_apply_op<R, true, D4>(a, E, MT);  // Phi <- Q^dagger Phi
@@ -1127,7 +1152,7 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
           if (MODE == 1 && gen) grads();
           if (MODE == 3 && (G.nd & kInvFlag)) {
             DOp Ei = E;
-            Ei.g.mat += G.kind == GK_DENSE4 ? 256 : 16;
+            Ei.g.mat += (G.kind == GK_DENSE4 || G.kind == GK_DEPOL4) ? 256 : 16;
             rg_apply_op<R, false>(a, Ei, MT);
           } else {
             rg_apply_op<R, true>(a, E, MT);

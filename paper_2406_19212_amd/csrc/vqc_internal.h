@@ -39,7 +39,11 @@ enum GateKind : int8_t {
   // Phi is uncomputed through U (no derivative matrix)
   GK_GENX = 19,
   GK_GENY = 20,
-  GK_GENZ = 21
+  GK_GENZ = 21,
+  // a two-qubit depolarizing superoperator a I + b |I>><<I| on (q1, q2,
+  // q1 + n, q2 + n), register bits 0..3 in order: a = M[1][1], b = M[0][5]
+  // of its stored 16x16 (the inverse has the same form)
+  GK_DEPOL4 = 22
 };
 // DGate.nd: derivative count in the low byte; this bit set when the op's
 // derivatives are generator kinds (taken on Phi before the op is undone)
