@@ -267,6 +267,11 @@ vqc_status vqc_circuit_stats_get(vqc_circuit c, vqc_circuit_stats *out);
  * passes.  theta_dev: device double[n_params] (may be NULL when n_params = 0). */
 vqc_status vqc_apply_circuit(vqc_state s, vqc_circuit c, const double *theta_dev);
 
+/* apply(circ, state) / circ * state of Sec. 2.4: the circuit applied to a copy
+ * of src written into dst (same kind and size; src is left unchanged).  Runs
+ * on dst's stream: work queued on another stream for src must be complete. */
+vqc_status vqc_apply_circuit_out(vqc_state dst, const vqc_state src, vqc_circuit c, const double *theta_dev);
+
 /* vqc_apply_circuit with a HIP event recorded on the state's stream between
  * consecutive pass launches; pass_ms_host[p] receives the duration of pass p
  * (host float[n_passes], see vqc_circuit_stats).  Synchronises the stream. */

@@ -24,6 +24,20 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def flatten_ops(ops) -> list:
+    """QCircuit nesting (Sec. 2.3): an element may be an op, a Circuit or a
+    list of elements; the result is the flat op sequence in order."""
+    out = []
+    for x in ops:
+        if hasattr(x, "name"):
+            out.append(x)
+        elif isinstance(x, Circuit):
+            out.extend(x.ops)
+        else:
+            out.extend(flatten_ops(x))
+    return out
+
+
 def ops_params(ops) -> int:
     m = -1
     for op in ops:
@@ -144,7 +158,7 @@ class Circuit:
     def __init__(self, n: int, ops, n_params=None, mixed: bool = False, tune=None):
         self.n = int(n)
         self.mixed = bool(mixed)
-        self.ops = list(ops)
+        self.ops = flatten_ops(ops)
         self.n_params = ops_params(self.ops) if n_params is None else int(n_params)
         arr = B.OpArray(self.ops)
         t = None
@@ -183,6 +197,18 @@ class Circuit:
     def apply(self, state: State, theta=None):
         th = self._theta(theta)
         check(lib().vqc_apply_circuit(state.h, self.h, _dptr(th)), "vqc_apply_circuit")
+
+    def apply_out(self, state: State, theta=None) -> State:
+        """apply(circ, state): a new state holding the circuit applied to a copy
+        of ``state`` (which is left unchanged)."""
+        th = self._theta(theta)
+        out = State(state.n, mixed=state.mixed, device=state.tensor.device)
+        check(lib().vqc_apply_circuit_out(out.h, state.h, self.h, _dptr(th)), "vqc_apply_circuit_out")
+        return out
+
+    def __mul__(self, state: State) -> State:
+        """circ * state (Sec. 2.4) for circuits without variational parameters."""
+        return self.apply_out(state)
 
     def apply_timed(self, state: State, theta=None) -> np.ndarray:
         """Apply with HIP events between pass launches; returns ms per pass."""

@@ -100,6 +100,7 @@ _SIGS = {
     "vqc_sample": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     "vqc_circuit_stats_get": (c_int, [c_void_p, ctypes.POINTER(vqc_circuit_stats)]),
     "vqc_apply_circuit": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "vqc_apply_circuit_out": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "vqc_apply_circuit_timed": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "vqc_backward": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p,
                              ctypes.POINTER(c_double), c_void_p, c_size_t]),

@@ -1958,6 +1958,14 @@ vqc_status vqc_apply_circuit(vqc_state s, vqc_circuit c, const double *theta) {
   return VQC_OK;
 }
 
+vqc_status vqc_apply_circuit_out(vqc_state dst, const vqc_state src, vqc_circuit c, const double *theta) {
+  if (!dst || !src || !c) return VQC_ERR_ARG;
+  if (src->kind != dst->kind || src->n != dst->n) return VQC_ERR_KIND;
+  if (dst->buf == src->buf) return vqc_apply_circuit(dst, c, theta);
+  VQC_TRY(launch_copy(dst->buf, src->buf, state_len(dst->kind, dst->n), dst->stream));
+  return vqc_apply_circuit(dst, c, theta);
+}
+
 vqc_status vqc_apply_circuit_timed(vqc_state s, vqc_circuit c, const double *theta, float *pass_ms) {
   if (!s || !c || !pass_ms) return VQC_ERR_ARG;
   if (s->kind != c->kind || s->n != c->n) return VQC_ERR_KIND;
