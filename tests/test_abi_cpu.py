@@ -102,3 +102,26 @@ def test_state_init_rejects_bad_sizes_on_host(L):
     assert L.vqc_state_init(ctypes.byref(h), 0, 40, ctypes.c_void_p(1), None, None) == -1
     assert L.vqc_state_init(ctypes.byref(h), 1, 17, ctypes.c_void_p(1), None, None) == -1
     assert L.vqc_state_init(ctypes.byref(h), 0, 4, None, None, None) == -1
+
+
+def test_new_entry_points_reject_bad_arguments_on_host(L):
+    P = ctypes.c_void_p
+    o, p = ctypes.c_int(), ctypes.c_double()
+    assert L.vqc_measure(None, 0, 0.5, ctypes.byref(o), ctypes.byref(p)) == -1
+    assert L.vqc_sample(None, 4, None, None) == -1
+    assert L.vqc_backward_inverse(None, None, None, None, None, None, 0.0) == -1
+    assert L.vqc_batch_backward_inverse(None, None, None, None, 0.0) == -1
+    assert L.vqc_apply_circuit_out(None, None, None, None) == -1
+    n_out = ctypes.c_int()
+    assert L.vqc_fuse_gates(3, 1, None, 0, None, None, None, ctypes.byref(n_out)) == -1  # no ops array
+    assert L.vqc_fuse_gates(0, 0, None, 0, None, None, None, ctypes.byref(n_out)) == -1  # n out of range
+    # validation before any device work: a channel (noiseless only), a wide op, a bad theta index
+    for ops, code in (([W.Op("depolarizing", (0,), (0.1,))], -4),
+                      ([W.Op("toffoli", (0, 1, 2))], -3),
+                      ([W.Op("rx", (0,), (0.1,), (3,))], -1)):
+        arr = B.OpArray(ops)
+        out = (B.vqc_op * 4)()
+        data = np.zeros(64, np.complex128)
+        th = np.zeros(2)
+        assert L.vqc_fuse_gates(3, arr.n, arr.ptr(), 2, th.ctypes.data, ctypes.cast(out, P), data.ctypes.data,
+                                ctypes.byref(n_out)) == code
