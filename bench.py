@@ -23,10 +23,17 @@ Also reported:
   paper's random-circuit sampling use) and measure! of one qubit;
 * single unfused ops on the same state (dense one-, two- and three-qubit
   matrices, CZ) as GB/s against their algorithmic bytes;
+* the surrogate's pieces at their working shapes (16 qubits, 10 layers, 320
+  parameters; network 320 -> 512 -> 512 -> 1, batch 512): labels (energy and
+  gradient) per second from the batched simulator, training steps per second
+  (forward, backward with the gradient-matching term, Adam), and the BF16
+  MFMA matrix product in TFLOP/s against the dense BF16 peak, at the
+  network's layer shape and at 4096^3;
 * cpu_baseline: the plain C oracle on this host, timed on a bounded prefix of
   the same 28-qubit circuit.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-vqe] [--no-noisy]
+                       [--no-surrogate]
        python bench.py --copy-calibration   (only a plain device copy of known
                                               size, for scaling HBM counters)
 """
@@ -40,6 +47,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 HERE = os.path.dirname(os.path.abspath(__file__))
 # measured HBM traffic of the fused pass (rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a plain copy); used only while the kernel
@@ -57,6 +65,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-vqe", action="store_true")
     ap.add_argument("--no-noisy", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
@@ -162,6 +171,66 @@ def vqe_batched(torch, steps):
     except Exception as e:  # report, do not hide
         out["batched_error"] = str(e)
     out.update({"workload": "hea-20q-40layers-1600params-tfim-batch64", "unit": "grads/s"})
+    return out
+
+
+def surrogate_leg(torch):
+    """The surrogate's kernels at their working shapes: simulator labels,
+    network training steps and the BF16 MFMA matrix product."""
+    from paper_2406_19212_amd import surrogate as S
+    from paper_2406_19212_amd.mlp import MLP, gemm_bf16
+    out = {"workload": "hea-16q-10layers-320params-tfim; mlp-320-512-512-1-batch512"}
+    sim = S.Simulator(16, 10, batch=256)
+    count = 4096
+    S.generate(sim, 256, 1)  # warm-up replay
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    theta, E, G = S.generate(sim, count, 2)
+    torch.cuda.synchronize()
+    out["labels_per_s"] = round(count / (time.perf_counter() - t0), 1)
+    del sim
+    net = MLP(320, 512, 512, 512)
+    S.init_params(net, 3)
+    mu, sd = float(E.mean()), float(E.std())
+    x = theta.float().contiguous()
+    e = ((E - mu) / sd).float().contiguous()
+    g = (G / sd).float().contiguous()
+    nb = count // 512
+
+    def train_steps(k):
+        for i in range(k):
+            s = (i % nb) * 512
+            net.backward(x[s:s + 512], e[s:s + 512], g[s:s + 512], 1.0)
+            net.adam(1e-3)
+    train_steps(4)
+    torch.cuda.synchronize()
+    steps = 64
+    t0 = time.perf_counter()
+    train_steps(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["train_ms_per_step"] = round(1e3 * dt / steps, 4)
+    out["train_samples_per_s"] = round(512 * steps / dt, 1)
+    gem = {}
+    for name, (M, N, K) in (("layer2_512x512x512", (512, 512, 512)), ("square_4096", (4096, 4096, 4096))):
+        gen = torch.Generator(device="cpu").manual_seed(M + K)
+        A = torch.randn(M, K, generator=gen).cuda()
+        Bm = torch.randn(K, N, generator=gen).cuda()
+        C = torch.zeros(M, N, dtype=torch.float32, device="cuda")
+        reps = 20 if M < 4096 else 5
+        gemm_bf16(A, Bm, C=C)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            gemm_bf16(A, Bm, C=C)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        tf = 2.0 * M * N * K / (ms * 1e-3) / 1e12
+        gem[name] = {"ms": round(ms, 4), "TFLOP_per_s": round(tf, 2), "frac": round(tf / BF16_MFMA_PEAK_TFLOPS, 4)}
+    out["gemm_bf16"] = gem
+    out["gemm_peak_TFLOP_per_s"] = BF16_MFMA_PEAK_TFLOPS
+    del net
     return out
 
 
@@ -356,6 +425,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_noisy:
         rec["noisy_backward"] = noisy_backward(torch, not args.no_cpu)
+        torch.cuda.empty_cache()
+    if not args.no_surrogate:
+        rec["surrogate"] = surrogate_leg(torch)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_seconds)

@@ -12,7 +12,6 @@
 
 namespace vqc {
 
-typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 // FP32 -> BF16 with round-to-nearest-even (NaN kept quiet)
@@ -25,50 +24,142 @@ __device__ __forceinline__ short f2bf(float f) {
 
 // C[M x N] = alpha * op(A) op(B) + beta * C, op(A)[m][k] = A[m*lda + k] (ta = 0)
 // or A[k*lda + m] (ta = 1); op(B)[k][n] = B[k*ldb + n] (tb = 0) or B[n*ldb + k].
-// Block tile 64 x 64, K step 16, four waves each owning a 32 x 32 quadrant
-// made of 2 x 2 MFMA 16x16x16 tiles.
-constexpr int GT = 64, GK = 16;
+//
+// Block tile BT x BT (32, 64 or 128, chosen by the launcher so that the grid
+// fills the chip), K step 32, four waves in a 2 x 2 arrangement, each owning a
+// (BT/2) x (BT/2) quadrant of 16 x 16 MFMA tiles (v_mfma_f32_16x16x32_bf16:
+// eight consecutive k per lane, the same k assignment for both operands, so
+// each MFMA sums all 32 products of its k step).  The K loop is software
+// pipelined: the FP32 slab of step k+1 is loaded into registers while step k
+// runs from LDS, then rounded to BF16 into the other of two LDS buffers; one
+// barrier per step.  Global loads follow the operand's contiguous dimension
+// (float4 when the leading dimension and base are 16-byte aligned, otherwise
+// four bounds-checked scalars), so every layout reads coalesced.
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short s16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short s16x4;
 
-__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const float *__restrict__ A, int lda, int ta,
-                                                   const float *__restrict__ B, int ldb, int tb,
-                                                   float *__restrict__ C, int ldc, float alpha, float beta) {
-  __shared__ short As[GT][GK + 4];  // [m][k]
-  __shared__ short Bs[GT][GK + 4];  // [n][k]
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  f32x4 acc[2][2];
-  for (int i = 0; i < 2; i++)
-    for (int j = 0; j < 2; j++) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += GK) {
-    // stage 64 x 16 of op(A) and 16 x 64 of op(B): 1024 elements each, 4 per thread
-    for (int e = t; e < GT * GK; e += 256) {
-      const int r = e / GK, c = e % GK;  // r: m or n, c: k
-      const int gm = m0 + r, gk = k0 + c, gn = n0 + r;
-      float av = 0.f, bv = 0.f;
-      if (gm < M && gk < K) av = ta ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-      if (gn < N && gk < K) bv = tb ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
-      As[r][c] = f2bf(av);
-      Bs[r][c] = f2bf(bv);
+constexpr int GK = 32, GKP = GK + 8;  // LDS row pitch 80 B: 16-byte aligned, conflict-free row reads
+
+// one operand slab, BT rows (m for A, n for B) x GK k values, held as float4
+// groups in registers between the global load and the LDS store.  KC: the
+// operand is contiguous along k (A with ta = 0, B with tb = 1).
+template <int BT, bool KC>
+struct Slab {
+  static constexpr int NG = BT * GK / 4 / 256;  // float4 groups per thread
+  float4 v[NG];
+
+  __device__ __forceinline__ void load(const float *__restrict__ X, int ld, int rows, int K, int r0, int k0, bool vec,
+                                       int t) {
+#pragma unroll
+    for (int i = 0; i < NG; i++) {
+      const int q = t + 256 * i;
+      int r, k;
+      if constexpr (KC) {
+        r = q / (GK / 4);
+        k = 4 * (q % (GK / 4));
+      } else {
+        k = q / (BT / 4);
+        r = 4 * (q % (BT / 4));
+      }
+      const int gr = r0 + r, gk = k0 + k;
+      float e[4];
+      if constexpr (KC) {
+        if (vec && gr < rows && gk + 3 < K) {
+          const float4 w = *(const float4 *)(X + (int64_t)gr * ld + gk);
+          e[0] = w.x, e[1] = w.y, e[2] = w.z, e[3] = w.w;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; j++) e[j] = (gr < rows && gk + j < K) ? X[(int64_t)gr * ld + gk + j] : 0.f;
+        }
+      } else {
+        if (vec && gk < K && gr + 3 < rows) {
+          const float4 w = *(const float4 *)(X + (int64_t)gk * ld + gr);
+          e[0] = w.x, e[1] = w.y, e[2] = w.z, e[3] = w.w;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; j++) e[j] = (gk < K && gr + j < rows) ? X[(int64_t)gk * ld + gr + j] : 0.f;
+        }
+      }
+      v[i] = make_float4(e[0], e[1], e[2], e[3]);
     }
-    __syncthreads();
-    // lane layout of mfma_f32_16x16x16bf16_1k: A row = lane % 16, k = 4 (lane / 16) + i;
-    // B column = lane % 16, same k; D row = 4 (lane / 16) + i, column = lane % 16
-    const int r16 = lane & 15, kb = (lane >> 4) * 4;
-    bf16x4 a[2], b[2];
-    for (int i = 0; i < 2; i++) {
-      for (int q = 0; q < 4; q++) {
-        a[i][q] = As[wm + 16 * i + r16][kb + q];
-        b[i][q] = Bs[wn + 16 * i + r16][kb + q];
+  }
+
+  // rounded to BF16 into Xs[row][k]
+  __device__ __forceinline__ void store(short (*Xs)[GKP], int t) const {
+#pragma unroll
+    for (int i = 0; i < NG; i++) {
+      const int q = t + 256 * i;
+      if constexpr (KC) {
+        const int r = q / (GK / 4), k = 4 * (q % (GK / 4));
+        s16x4 h = {f2bf(v[i].x), f2bf(v[i].y), f2bf(v[i].z), f2bf(v[i].w)};
+        *(s16x4 *)&Xs[r][k] = h;
+      } else {
+        const int k = q / (BT / 4), r = 4 * (q % (BT / 4));
+        Xs[r][k] = f2bf(v[i].x);
+        Xs[r + 1][k] = f2bf(v[i].y);
+        Xs[r + 2][k] = f2bf(v[i].z);
+        Xs[r + 3][k] = f2bf(v[i].w);
       }
     }
-    for (int i = 0; i < 2; i++)
-      for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+};
+
+template <int BT, bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const float *__restrict__ A, int lda,
+                                                   const float *__restrict__ B, int ldb, float *__restrict__ C,
+                                                   int ldc, float alpha, float beta, int avec, int bvec) {
+  constexpr int WT = BT / 2, MI = WT / 16;  // wave quadrant, MFMA tiles per side
+  __shared__ __attribute__((aligned(16))) short As[2][BT][GKP];  // [buf][m][k]
+  __shared__ __attribute__((aligned(16))) short Bs[2][BT][GKP];  // [buf][n][k]
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
+  const int wm = (wave >> 1) * WT, wn = (wave & 1) * WT;
+  f32x4 acc[MI][MI];
+#pragma unroll
+  for (int i = 0; i < MI; i++)
+#pragma unroll
+    for (int j = 0; j < MI; j++) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  Slab<BT, !TA> sa;
+  Slab<BT, TB> sb;
+  sa.load(A, lda, M, K, m0, 0, avec, t);
+  sb.load(B, ldb, N, K, n0, 0, bvec, t);
+  sa.store(As[0], t);
+  sb.store(Bs[0], t);
+  __syncthreads();
+  // operand fragments: row (m or n) = lane % 16, k = 8 (lane / 16) + i
+  const int r16 = lane & 15, kb = (lane >> 4) * 8;
+  const int nsteps = (K + GK - 1) / GK;
+  for (int s = 0; s < nsteps; s++) {
+    const int cur = s & 1;
+    const bool more = s + 1 < nsteps;
+    if (more) {
+      sa.load(A, lda, M, K, m0, (s + 1) * GK, avec, t);
+      sb.load(B, ldb, N, K, n0, (s + 1) * GK, bvec, t);
+    }
+    bf16x8v a[MI], b[MI];
+#pragma unroll
+    for (int i = 0; i < MI; i++) {
+      a[i] = __builtin_bit_cast(bf16x8v, *(const s16x8 *)&As[cur][wm + 16 * i + r16][kb]);
+      b[i] = __builtin_bit_cast(bf16x8v, *(const s16x8 *)&Bs[cur][wn + 16 * i + r16][kb]);
+    }
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+      for (int j = 0; j < MI; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (more) {
+      sa.store(As[cur ^ 1], t);
+      sb.store(Bs[cur ^ 1], t);
+    }
     __syncthreads();
   }
+  // D layout: row = 4 (lane / 16) + q, column = lane % 16
   const int c16 = lane & 15, rb = (lane >> 4) * 4;
-  for (int i = 0; i < 2; i++)
-    for (int j = 0; j < 2; j++)
+#pragma unroll
+  for (int i = 0; i < MI; i++)
+#pragma unroll
+    for (int j = 0; j < MI; j++)
+#pragma unroll
       for (int q = 0; q < 4; q++) {
         const int gm = m0 + wm + 16 * i + rb + q, gn = n0 + wn + 16 * j + c16;
         if (gm < M && gn < N) {
@@ -137,13 +228,25 @@ __global__ void __launch_bounds__(256) k_rowdot(int M, int N, const float *__res
   if (t == 0) y[m] = sh[0] + (b ? b[0] : 0.f);
 }
 
-// out[j] (+)= scale * sum_m X[m][j] (column sums, fixed order per column)
-__global__ void k_colsum(int M, int N, const float *__restrict__ X, float scale, int accumulate, float *__restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
+// out[j] (+)= scale * sum_m X[m][j] (column sums in a fixed order): a block
+// covers 64 columns (one per lane, coalesced rows); its 16 waves take rows
+// w, w + 16, ... and their partial sums are added in wave order
+constexpr int kColWaves = 16;
+__global__ void __launch_bounds__(64 * kColWaves) k_colsum(int M, int N, const float *__restrict__ X, float scale,
+                                                           int accumulate, float *__restrict__ out) {
+  __shared__ float part[kColWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int m = 0; m < M; m++) s += X[(int64_t)m * N + j];
-  out[j] = accumulate ? out[j] + scale * s : scale * s;
+  if (j < N)
+    for (int m = w; m < M; m += kColWaves) s += X[(int64_t)m * N + j];
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < N) {
+    float r = 0.f;
+    for (int v = 0; v < kColWaves; v++) r += part[v][lane];
+    out[j] = accumulate ? out[j] + scale * r : scale * r;
+  }
 }
 
 // out[m][j] = a[m] * w[j]  (outer product of a column vector and a row)
@@ -401,11 +504,34 @@ vqc_status vqc_mlp_descend_inputs(vqc_mlp m, int batch, float *x, float lr, int 
 
 namespace vqc {
 
+template <int BT>
+static void launch_gemm_t(int M, int N, int K, const float *A, int lda, int ta, const float *B, int ldb, int tb,
+                          float *C, int ldc, float alpha, float beta, int avec, int bvec, hipStream_t st) {
+  dim3 grid((N + BT - 1) / BT, (M + BT - 1) / BT);
+#define VQC_GEMM_LAUNCH(TA, TB)                                                                                    \
+  hipLaunchKernelGGL((k_gemm_bf16<BT, TA, TB>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, \
+                     avec, bvec)
+  if (!ta && !tb) VQC_GEMM_LAUNCH(false, false);
+  else if (ta && !tb) VQC_GEMM_LAUNCH(true, false);
+  else if (!ta && tb) VQC_GEMM_LAUNCH(false, true);
+  else VQC_GEMM_LAUNCH(true, true);
+#undef VQC_GEMM_LAUNCH
+}
+
 hipError_t mlp_gemm(int M, int N, int K, const float *A, int lda, int ta, const float *B, int ldb, int tb, float *C,
                     int ldc, float alpha, float beta, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta);
+  // float4 loads need a 16-byte aligned base and a leading dimension that keeps every row aligned
+  const int avec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
+  const int bvec = ((uintptr_t)B % 16 == 0) && (ldb % 4 == 0);
+  // the largest tile whose grid still gives every compute unit a block
+  auto blocks = [&](int bt) { return (int64_t)((M + bt - 1) / bt) * ((N + bt - 1) / bt); };
+  if (blocks(128) >= 256)
+    launch_gemm_t<128>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, avec, bvec, st);
+  else if (blocks(64) >= 128)
+    launch_gemm_t<64>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, avec, bvec, st);
+  else
+    launch_gemm_t<32>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, avec, bvec, st);
   return hipGetLastError();
 }
 hipError_t mlp_bias_gelu(int M, int N, float *Z, const float *b, float *H, hipStream_t st) {
@@ -422,7 +548,8 @@ hipError_t mlp_rowdot(int M, int N, const float *H, const float *w, const float 
   return hipGetLastError();
 }
 hipError_t mlp_colsum(int M, int N, const float *X, float scale, int acc, float *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_colsum, dim3(blocks_for(N)), dim3(256), 0, st, M, N, X, scale, acc, out);
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64), dim3(64 * kColWaves), 0, st, M, N, X, scale, acc, out);
   return hipGetLastError();
 }
 hipError_t mlp_outer(int M, int N, const float *a, const float *w, float *out, hipStream_t st) {

@@ -22,7 +22,11 @@ def bf(x):
     return torch.as_tensor(x).to(torch.bfloat16).to(torch.float64)
 
 
-@pytest.mark.parametrize("M,N,K", [(70, 130, 45), (64, 64, 16), (1, 512, 37), (513, 3, 320), (5, 7, 1)])
+# shapes reach all three block tiles (32: small grids; 64: (768, 770, 96);
+# 128: the two 2048-wide cases), aligned float4 and scalar loads, and K
+# tails inside and beyond a 32-wide k step
+@pytest.mark.parametrize("M,N,K", [(70, 130, 45), (64, 64, 16), (1, 512, 37), (513, 3, 320), (5, 7, 1),
+                                   (768, 770, 96), (2050, 2048, 64), (2048, 2052, 36)])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_gemm_bf16_layouts(M, N, K, ta, tb):
     g = torch.Generator().manual_seed(M * 131 + N * 7 + K + 1000 * ta + 2000 * tb)
