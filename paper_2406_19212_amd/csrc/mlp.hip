@@ -14,36 +14,37 @@ namespace vqc {
 
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-// FP32 -> BF16 with round-to-nearest-even (NaN kept quiet)
-__device__ __forceinline__ short f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (short)((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
+// FP32 -> BF16, round to nearest even: v_cvt_pk_bf16_f32 (two per instruction)
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
+  const bf16x2v r = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, r);
 }
 
 // C[M x N] = alpha * op(A) op(B) + beta * C, op(A)[m][k] = A[m*lda + k] (ta = 0)
 // or A[k*lda + m] (ta = 1); op(B)[k][n] = B[k*ldb + n] (tb = 0) or B[n*ldb + k].
 //
 // Block tile BT x BT (32, 64 or 128, chosen by the launcher so that the grid
-// fills the chip), K step 32, four waves in a 2 x 2 arrangement, each owning a
-// (BT/2) x (BT/2) quadrant of 16 x 16 MFMA tiles (v_mfma_f32_16x16x32_bf16:
-// eight consecutive k per lane, the same k assignment for both operands, so
-// each MFMA sums all 32 products of its k step).  The K loop is software
+// fills the chip), K step 64 (two MFMA k blocks), four waves in a 2 x 2
+// arrangement, each owning a (BT/2) x (BT/2) quadrant of 16 x 16 MFMA tiles
+// (v_mfma_f32_16x16x32_bf16: eight consecutive k per lane, the same k
+// assignment for both operands, so each MFMA sums all 32 products of its k
+// block).  The K loop is software
 // pipelined: the FP32 slab of step k+1 is loaded into registers while step k
 // runs from LDS, then rounded to BF16 into the other of two LDS buffers; one
 // barrier per step.  Global loads follow the operand's contiguous dimension
 // (float4 when the leading dimension and base are 16-byte aligned, otherwise
-// four bounds-checked scalars), so every layout reads coalesced.
+// four bounds-checked scalars), so every layout reads coalesced, and every
+// layout stores 8-byte runs of k into LDS.
 typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short s16x8;
-typedef __attribute__((__vector_size__(4 * sizeof(short)))) short s16x4;
 
-constexpr int GK = 32, GKP = GK + 8;  // LDS row pitch 80 B: 16-byte aligned, conflict-free row reads
+constexpr int GK = 64, GKP = GK + 8;  // LDS row pitch 144 B: 16-byte aligned, conflict-free row reads
 
-// one operand slab, BT rows (m for A, n for B) x GK k values, held as float4
-// groups in registers between the global load and the LDS store.  KC: the
-// operand is contiguous along k (A with ta = 0, B with tb = 1).
+// one operand slab, BT rows (m for A, n for B) x GK k values, held in
+// registers between the global load and the LDS store.  KC: the operand is
+// contiguous along k (A with ta = 0, B with tb = 1); each thread moves float4
+// groups of four consecutive k of one row.
 template <int BT, bool KC>
 struct Slab {
   static constexpr int NG = BT * GK / 4 / 256;  // float4 groups per thread
@@ -54,32 +55,16 @@ struct Slab {
 #pragma unroll
     for (int i = 0; i < NG; i++) {
       const int q = t + 256 * i;
-      int r, k;
-      if constexpr (KC) {
-        r = q / (GK / 4);
-        k = 4 * (q % (GK / 4));
-      } else {
-        k = q / (BT / 4);
-        r = 4 * (q % (BT / 4));
-      }
-      const int gr = r0 + r, gk = k0 + k;
+      const int gr = r0 + q / (GK / 4), gk = k0 + 4 * (q % (GK / 4));
+      // (both branches fill e: assigning the float4 straight to v[i] made the
+      // compiler split the vector load into a 12-byte and a 4-byte load)
       float e[4];
-      if constexpr (KC) {
-        if (vec && gr < rows && gk + 3 < K) {
-          const float4 w = *(const float4 *)(X + (int64_t)gr * ld + gk);
-          e[0] = w.x, e[1] = w.y, e[2] = w.z, e[3] = w.w;
-        } else {
-#pragma unroll
-          for (int j = 0; j < 4; j++) e[j] = (gr < rows && gk + j < K) ? X[(int64_t)gr * ld + gk + j] : 0.f;
-        }
+      if (vec && gr < rows && gk + 3 < K) {
+        const float4 w = *(const float4 *)(X + (int64_t)gr * ld + gk);
+        e[0] = w.x, e[1] = w.y, e[2] = w.z, e[3] = w.w;
       } else {
-        if (vec && gk < K && gr + 3 < rows) {
-          const float4 w = *(const float4 *)(X + (int64_t)gk * ld + gr);
-          e[0] = w.x, e[1] = w.y, e[2] = w.z, e[3] = w.w;
-        } else {
 #pragma unroll
-          for (int j = 0; j < 4; j++) e[j] = (gk < K && gr + j < rows) ? X[(int64_t)gk * ld + gr + j] : 0.f;
-        }
+        for (int j = 0; j < 4; j++) e[j] = (gr < rows && gk + j < K) ? X[(int64_t)gr * ld + gk + j] : 0.f;
       }
       v[i] = make_float4(e[0], e[1], e[2], e[3]);
     }
@@ -90,17 +75,63 @@ struct Slab {
 #pragma unroll
     for (int i = 0; i < NG; i++) {
       const int q = t + 256 * i;
-      if constexpr (KC) {
-        const int r = q / (GK / 4), k = 4 * (q % (GK / 4));
-        s16x4 h = {f2bf(v[i].x), f2bf(v[i].y), f2bf(v[i].z), f2bf(v[i].w)};
-        *(s16x4 *)&Xs[r][k] = h;
-      } else {
-        const int k = q / (BT / 4), r = 4 * (q % (BT / 4));
-        Xs[r][k] = f2bf(v[i].x);
-        Xs[r + 1][k] = f2bf(v[i].y);
-        Xs[r + 2][k] = f2bf(v[i].z);
-        Xs[r + 3][k] = f2bf(v[i].w);
+      *(uint2 *)&Xs[q / (GK / 4)][4 * (q % (GK / 4))] =
+          make_uint2(bf16_pair(v[i].x, v[i].y), bf16_pair(v[i].z, v[i].w));
+    }
+  }
+};
+
+// Rows contiguous (A with ta = 1, B with tb = 0): each thread moves 4 x 4
+// blocks (four float4 loads of four consecutive rows, at four consecutive k)
+// and transposes them in registers, so that its LDS stores are 8-byte runs
+// of k like the other layout's.  Eight consecutive threads take consecutive
+// row groups (128 contiguous bytes per k), the next eight the next k group.
+template <int BT>
+struct Slab<BT, false> {
+  static constexpr int RG = BT / 4, KG = GK / 4;    // 4 x 4 blocks per slab side
+  static constexpr int NB = (RG * KG + 255) / 256;  // blocks per thread (the 32-row slab leaves half idle)
+  float v[NB][4][4];                                // [block][k][row]
+
+  __device__ __forceinline__ static bool at(int q, int &rg, int &kg) {
+    const int hi = q >> 3;
+    kg = hi % KG;
+    rg = (q & 7) + 8 * (hi / KG);
+    return q < RG * KG;
+  }
+
+  __device__ __forceinline__ void load(const float *__restrict__ X, int ld, int rows, int K, int r0, int k0, bool vec,
+                                       int t) {
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      int rg, kg;
+      if (!at(t + 256 * b, rg, kg)) continue;
+      const int gr = r0 + 4 * rg;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int gk = k0 + 4 * kg + j;
+        float e[4];  // filled by both branches, which keeps the load one float4
+        if (vec && gk < K && gr + 3 < rows) {
+          const float4 w = *(const float4 *)(X + (int64_t)gk * ld + gr);
+          e[0] = w.x, e[1] = w.y, e[2] = w.z, e[3] = w.w;
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; r++) e[r] = (gk < K && gr + r < rows) ? X[(int64_t)gk * ld + gr + r] : 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) v[b][j][r] = e[r];
       }
+    }
+  }
+
+  __device__ __forceinline__ void store(short (*Xs)[GKP], int t) const {
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      int rg, kg;
+      if (!at(t + 256 * b, rg, kg)) continue;
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+        *(uint2 *)&Xs[4 * rg + r][4 * kg] =
+            make_uint2(bf16_pair(v[b][0][r], v[b][1][r]), bf16_pair(v[b][2][r], v[b][3][r]));
     }
   }
 };
@@ -137,16 +168,20 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const fl
       sa.load(A, lda, M, K, m0, (s + 1) * GK, avec, t);
       sb.load(B, ldb, N, K, n0, (s + 1) * GK, bvec, t);
     }
-    bf16x8v a[MI], b[MI];
 #pragma unroll
-    for (int i = 0; i < MI; i++) {
-      a[i] = __builtin_bit_cast(bf16x8v, *(const s16x8 *)&As[cur][wm + 16 * i + r16][kb]);
-      b[i] = __builtin_bit_cast(bf16x8v, *(const s16x8 *)&Bs[cur][wn + 16 * i + r16][kb]);
+    for (int kk = 0; kk < GK; kk += 32) {
+      bf16x8v a[MI], b[MI];
+#pragma unroll
+      for (int i = 0; i < MI; i++) {
+        a[i] = __builtin_bit_cast(bf16x8v, *(const s16x8 *)&As[cur][wm + 16 * i + r16][kk + kb]);
+        b[i] = __builtin_bit_cast(bf16x8v, *(const s16x8 *)&Bs[cur][wn + 16 * i + r16][kk + kb]);
+      }
+#pragma unroll
+      for (int i = 0; i < MI; i++)
+#pragma unroll
+        for (int j = 0; j < MI; j++)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-#pragma unroll
-    for (int i = 0; i < MI; i++)
-#pragma unroll
-      for (int j = 0; j < MI; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     if (more) {
       sa.store(As[cur ^ 1], t);
       sb.store(Bs[cur ^ 1], t);
