@@ -25,7 +25,7 @@ __device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
 // or A[k*lda + m] (ta = 1); op(B)[k][n] = B[k*ldb + n] (tb = 0) or B[n*ldb + k].
 //
 // Block tile BT x BT (32, 64 or 128, chosen by the launcher so that the grid
-// fills the chip), K step 64 (two MFMA k blocks), four waves in a 2 x 2
+// fills the chip), K step 64 or 128 (MFMA k blocks of 32), four waves in a 2 x 2
 // arrangement, each owning a (BT/2) x (BT/2) quadrant of 16 x 16 MFMA tiles
 // (v_mfma_f32_16x16x32_bf16: eight consecutive k per lane, the same k
 // assignment for both operands, so each MFMA sums all 32 products of its k
@@ -39,7 +39,11 @@ __device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
 typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short s16x8;
 
-constexpr int GK = 64, GKP = GK + 8;  // LDS row pitch 144 B: 16-byte aligned, conflict-free row reads
+// K step per tile: 128 for the 32 x 32 tile (small grids, where the number of
+// dependent steps sets the time), 64 otherwise.  LDS rows are padded by 8
+// (pitch 272 or 144 B): 16-byte aligned, and the 16 rows of an MFMA fragment
+// read fall on distinct banks.
+constexpr int kstep(int bt) { return bt == 32 ? 128 : 64; }
 
 // one operand slab, BT rows (m for A, n for B) x GK k values, held in
 // registers between the global load and the LDS store.  KC: the operand is
@@ -47,6 +51,7 @@ constexpr int GK = 64, GKP = GK + 8;  // LDS row pitch 144 B: 16-byte aligned, c
 // groups of four consecutive k of one row.
 template <int BT, bool KC>
 struct Slab {
+  static constexpr int GK = kstep(BT), GKP = GK + 8;
   static constexpr int NG = BT * GK / 4 / 256;  // float4 groups per thread
   float4 v[NG];
 
@@ -88,8 +93,9 @@ struct Slab {
 // row groups (128 contiguous bytes per k), the next eight the next k group.
 template <int BT>
 struct Slab<BT, false> {
+  static constexpr int GK = kstep(BT), GKP = GK + 8;
   static constexpr int RG = BT / 4, KG = GK / 4;    // 4 x 4 blocks per slab side
-  static constexpr int NB = (RG * KG + 255) / 256;  // blocks per thread (the 32-row slab leaves half idle)
+  static constexpr int NB = (RG * KG + 255) / 256;  // blocks per thread
   float v[NB][4][4];                                // [block][k][row]
 
   __device__ __forceinline__ static bool at(int q, int &rg, int &kg) {
@@ -141,6 +147,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const fl
                                                    const float *__restrict__ B, int ldb, float *__restrict__ C,
                                                    int ldc, float alpha, float beta, int avec, int bvec) {
   constexpr int WT = BT / 2, MI = WT / 16;  // wave quadrant, MFMA tiles per side
+  constexpr int GK = kstep(BT), GKP = GK + 8;
   __shared__ __attribute__((aligned(16))) short As[2][BT][GKP];  // [buf][m][k]
   __shared__ __attribute__((aligned(16))) short Bs[2][BT][GKP];  // [buf][n][k]
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -265,7 +272,8 @@ __global__ void __launch_bounds__(256) k_rowdot(int M, int N, const float *__res
 
 // out[j] (+)= scale * sum_m X[m][j] (column sums in a fixed order): a block
 // covers 64 columns (one per lane, coalesced rows); its 16 waves take rows
-// w, w + 16, ... and their partial sums are added in wave order
+// w, w + 16, ... into four running sums (independent loads in flight), and
+// the waves' partial sums are added in wave order
 constexpr int kColWaves = 16;
 __global__ void __launch_bounds__(64 * kColWaves) k_colsum(int M, int N, const float *__restrict__ X, float scale,
                                                            int accumulate, float *__restrict__ out) {
@@ -273,8 +281,19 @@ __global__ void __launch_bounds__(64 * kColWaves) k_colsum(int M, int N, const f
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane;
   float s = 0.f;
-  if (j < N)
-    for (int m = w; m < M; m += kColWaves) s += X[(int64_t)m * N + j];
+  if (j < N) {
+    constexpr int S = kColWaves;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int m = w;
+    for (; m + 3 * S < M; m += 4 * S) {
+      s0 += X[(int64_t)m * N + j];
+      s1 += X[(int64_t)(m + S) * N + j];
+      s2 += X[(int64_t)(m + 2 * S) * N + j];
+      s3 += X[(int64_t)(m + 3 * S) * N + j];
+    }
+    for (; m < M; m += S) s0 += X[(int64_t)m * N + j];
+    s = (s0 + s1) + (s2 + s3);
+  }
   part[w][lane] = s;
   __syncthreads();
   if (w == 0 && j < N) {
