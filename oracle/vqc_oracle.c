@@ -313,7 +313,7 @@ void or_superop(int m, int nk, const cplx *K, cplx *S) {
 
 /* ----------------------------------------------------------- application */
 
-/* Eq. (3) / Eq. (twoqubitgate) / Alg. 1, for any m: for every assignment of
+/* Eq. (3) / Eq. (twoqubitgate) / Alg. 1, for m up to 6: for every assignment of
  * the untouched bits, gather the 2^m amplitudes addressed by the op's qubits,
  * multiply by G, scatter back.  The outer loop over untouched bits is the
  * paper's s1, s2, s3 loops merged into one counter t with zero bits inserted
@@ -333,8 +333,8 @@ void or_apply(cplx *v, int nbits, int m, const int *q, const cplx *G) {
       uint64_t low = base & ((1ull << srt[i]) - 1);
       base = ((base >> srt[i]) << (srt[i] + 1)) | low;
     }
-    cplx in[16], out[16];
-    uint64_t idx[16];
+    cplx in[64], out[64];
+    uint64_t idx[64];
     for (int l = 0; l < d; l++) {
       uint64_t x = base;
       for (int k = 0; k < m; k++)
@@ -398,13 +398,24 @@ int or_apply_op(cplx *st, int n, int mixed, const or_op *op, const double *theta
     cplx G[256];
     if (is_channel(op->code) || or_gate_matrix(op, theta, G) < 0) return -1;
     or_apply(st, n, op->m, op->q, G);
+  } else if (op->m == 3 && is_channel(op->code)) {
+    /* three-qubit Kraus set: its 64 x 64 superoperator (Eq. (channel2)) on
+     * the ket bits and the bra bits of vec(rho) */
+    static cplx K[64 * 64], S[64 * 64];
+    int qq[6];
+    if (op->code != OR_KRAUS || op->n_data > 64 * 64) return -1;
+    int nk = or_channel_kraus(op, K);
+    if (nk < 1) return -1;
+    or_superop(3, nk, K, S);
+    super_qubits(op, n, qq);
+    or_apply(st, 2 * n, 6, qq, S);
   } else if (op->m == 3) {
     /* three-qubit gates: rho -> U rho U^dagger as U on the ket bits and
      * conj(U) on the bra bits (the superoperator conj(U) (x) U, applied by
-     * factors); there are no three-qubit channels */
+     * factors) */
     cplx G[64], Gc[64];
     int qq[3];
-    if (is_channel(op->code) || or_gate_matrix(op, theta, G) != 8) return -1;
+    if (or_gate_matrix(op, theta, G) != 8) return -1;
     for (int i = 0; i < 64; i++) Gc[i] = conj(G[i]);
     for (int k = 0; k < 3; k++) qq[k] = op->q[k] + n;
     or_apply(st, 2 * n, 3, op->q, G);

@@ -302,6 +302,57 @@ def test_superop_path_matches_direct_kraus_sum(oracle_mod):
         assert np.max(np.abs(out - ref)) < 1e-14
 
 
+def test_three_qubit_channels(oracle_mod):
+    """Three-qubit Kraus sets on vec(rho) (64 x 64 superoperator): the direct
+    Kraus sum on the dense matrix, the three-qubit depolarizing closed form,
+    a product channel as three one-qubit channels in sequence, and one
+    unitary Kraus operator as the three-qubit gate path."""
+    from types import SimpleNamespace as NS
+    n = 4
+    rho = W.random_density(n, 9)
+    # (a) brute force: sum_s K_s rho K_s^dagger with K_s embedded densely
+    for k, (qs, cnt) in enumerate([((2, 0, 3), 3), ((3, 1, 0), 64), ((0, 1, 2), 1)]):
+        K = W.random_kraus(8, cnt, 70 + k)
+        out = unvec(oracle_mod.run(n, [NS(name="kraus", qubits=qs, params=(), var=(), data=K)],
+                                   mixed=True, init=vec(rho)), n)
+        ref = sum(dense_op(n, list(qs), Ks) @ rho @ dense_op(n, list(qs), Ks).conj().T for Ks in K)
+        assert np.max(np.abs(out - ref)) < 1e-14
+    # (b) 64 weighted Paulis on qubits (0, 2, 3): rho -> (1-p) rho + p Tr_{0,2,3}(rho) (x) I/8
+    p = 0.37
+    paulis = [I2, np.array([[0, 1], [1, 0]], complex), np.array([[0, -1j], [1j, 0]]), np.diag([1.0, -1.0])]
+    K = []
+    for a in range(4):
+        for b in range(4):
+            for c in range(4):
+                w = math.sqrt(1 - 63 * p / 64) if a == b == c == 0 else math.sqrt(p / 64)
+                K.append(w * np.kron(paulis[c], np.kron(paulis[b], paulis[a])))  # local bit 0 = qubit 0
+    out = unvec(oracle_mod.run(n, [NS(name="kraus", qubits=(0, 2, 3), params=(), var=(), data=K)],
+                               mixed=True, init=vec(rho)), n)
+    T = rho.reshape([2] * 8)  # (q3, q2, q1, q0, q3', q2', q1', q0')
+    red = np.einsum("abicabjc->ij", T)  # the qubit-1 block
+    repl = np.einsum("ij,ad,be,cf->abicdejf", red, I2, I2, I2).reshape(16, 16) / 8
+    assert np.max(np.abs(out - ((1 - p) * rho + p * repl))) < 1e-15
+    # (c) product of one-qubit Kraus sets = the three channels one after another
+    A = oracle_mod.kraus("amplitude_damping", (0.3,))
+    Bk = oracle_mod.kraus("depolarizing", (0.2,))
+    C = oracle_mod.kraus("phase_damping", (0.4,))
+    qs = (3, 0, 2)
+    K = [np.kron(c, np.kron(b, a)) for a in A for b in Bk for c in C]
+    out = oracle_mod.run(n, [NS(name="kraus", qubits=qs, params=(), var=(), data=K)], mixed=True, init=vec(rho))
+    seq = oracle_mod.run(n, [NS(name="amplitude_damping", qubits=(3,), params=(0.3,), var=(), data=None),
+                             NS(name="depolarizing", qubits=(0,), params=(0.2,), var=(), data=None),
+                             NS(name="phase_damping", qubits=(2,), params=(0.4,), var=(), data=None)],
+                         mixed=True, init=vec(rho))
+    assert np.max(np.abs(out - seq)) < 1e-15
+    # (d) one unitary Kraus operator = the three-qubit gate applied to ket and bra
+    U = W.random_unitary(8, 77)
+    out = oracle_mod.run(n, [NS(name="kraus", qubits=(1, 3, 2), params=(), var=(), data=[U])], mixed=True,
+                         init=vec(rho))
+    gate = oracle_mod.run(n, [NS(name="matrix", qubits=(1, 3, 2), params=(), var=(), data=U)], mixed=True,
+                          init=vec(rho))
+    assert np.max(np.abs(out - gate)) < 1e-14
+
+
 def test_noiseless_density_equals_outer_product(oracle_mod):
     n = 4
     ops, th = W.brickwall(n, 3, 12)
