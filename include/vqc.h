@@ -194,7 +194,12 @@ vqc_status vqc_apply_op(vqc_state s, const vqc_op *op);
 
 /* QuantumMap(positions, kraus) on a MIXED state (Sec. 2.2, Eq. (channel));
  * applied as the superoperator sum_s conj(K_s) (x) K_s on bits
- * (qubits, qubits + n) of vec(rho) (Eq. (channel2)).  m = 1, 2. */
+ * (qubits, qubits + n) of vec(rho) (Eq. (channel2)).  m = 1, 2, 3; kraus:
+ * n_kraus (1..64) column-major 2^m x 2^m blocks, qubits[0] = bit 0 of their
+ * index, complete to 1e-12 (else VQC_ERR_NOT_CPTP).  m = 3 applies
+ * sum_s K_s rho K_s^dagger term by term on each 8 x 8 block of rho and
+ * synchronises the stream; three-qubit channels are single ops only
+ * (vqc_circuit_create refuses them with VQC_ERR_UNSUPPORTED). */
 vqc_status vqc_apply_channel(vqc_state s, int m, const int *qubits, int n_kraus,
                              const vqc_c128 *kraus);
 

@@ -175,7 +175,8 @@ vqc_status validate_op(const vqc_op &op, int n, vqc_kind kind, int n_params) {
   const int ar = op_arity(op.type);
   const int m = op.n_qubits;
   if (m < 1 || m > 3) return VQC_ERR_UNSUPPORTED;
-  if (m == 3 && op.type != VQC_MATRIX && ar != 3) return VQC_ERR_UNSUPPORTED;  // no three-qubit channels
+  // three qubits: the named gates, general matrices and Kraus sets (the last two as single ops only)
+  if (m == 3 && op.type != VQC_MATRIX && op.type != VQC_KRAUS && ar != 3) return VQC_ERR_UNSUPPORTED;
   if (ar && ar != m) return VQC_ERR_ARG;
   vqc_status st = check_qubits(m, op.qubits, n);
   if (st) return st;
@@ -1460,6 +1461,11 @@ static vqc_status apply_channel_dev(vqc_state s, int m, const int *q, int type, 
     VQC_TRY(hipMemcpyAsync(kd, kraus_rm.data(), kraus_rm.size() * sizeof(c128), hipMemcpyHostToDevice, s->stream));
     VQC_TRY(hipStreamSynchronize(s->stream));
   }
+  if (m == 3) {  // Kraus sets only (validated): applied term by term, no 64 x 64 superoperator
+    VQC_TRY(launch_kraus3(s->buf, s->nbits, s->n, q, kd, (int)(kraus_rm.size() / 64), s->stream));
+    VQC_TRY(hipStreamSynchronize(s->stream));  // scratch reuse
+    return VQC_OK;
+  }
   DRecipe r;
   std::memset(&r, 0, sizeof(r));
   r.type = type;
@@ -1483,7 +1489,7 @@ static vqc_status apply_channel_dev(vqc_state s, int m, const int *q, int type, 
 vqc_status vqc_apply_channel(vqc_state s, int m, const int *qubits, int n_kraus, const vqc_c128 *kraus) {
   if (!s || !qubits || !kraus || n_kraus < 1) return VQC_ERR_ARG;
   if (s->kind != VQC_MIXED) return VQC_ERR_KIND;
-  if (m < 1 || m > 2) return VQC_ERR_UNSUPPORTED;
+  if (m < 1 || m > 3) return VQC_ERR_UNSUPPORTED;
   vqc_op o;
   std::memset(&o, 0, sizeof(o));
   o.type = VQC_KRAUS;

@@ -660,6 +660,53 @@ __global__ void __launch_bounds__(256) k_gm(c128 *__restrict__ psi, int nbits, i
   }
 }
 
+// three-qubit Kraus channel on vec(rho), Eq. (channel2) applied term by term:
+// rho' = sum_s K_s rho K_s^dagger on the 8 x 8 block of ket bits (q0, q1, q2)
+// and bra bits (q0 + n, q1 + n, q2 + n), q0 = bit 0 of the local index.  One
+// wave per block: lane a + 8 b holds rho[a][b]; the block goes through LDS so
+// each lane forms sum_{c,d} K_s[a][c] rho[c][d] conj(K_s[b][d]) for its own
+// (a, b).  K: n_kraus row-major 8 x 8 matrices.  The loop trip count is
+// block-uniform (waves past the last block idle through the barriers).
+__global__ void __launch_bounds__(256) k_kraus3(c128 *__restrict__ v, int nbits, int n, int4 q,
+                                                const c128 *__restrict__ K, int nk) {
+  __shared__ c128 xs[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a = lane & 7, b = lane >> 3;
+  const int pos[6] = {q.x, q.y, q.z, q.x + n, q.y + n, q.z + n};
+  int srt[6];
+  for (int i = 0; i < 6; i++) srt[i] = pos[i];
+  for (int i = 0; i < 6; i++)
+    for (int j = i + 1; j < 6; j++)
+      if (srt[j] < srt[i]) { const int tmp = srt[i]; srt[i] = srt[j]; srt[j] = tmp; }
+  uint64_t off = 0;
+  for (int k = 0; k < 3; k++) {
+    if ((a >> k) & 1) off |= 1ull << pos[k];
+    if ((b >> k) & 1) off |= 1ull << pos[3 + k];
+  }
+  const uint64_t blocks = 1ull << (nbits - 6);
+  for (uint64_t g0 = (uint64_t)blockIdx.x * 4; g0 < blocks; g0 += (uint64_t)gridDim.x * 4) {
+    const uint64_t g = g0 + w;
+    const bool ok = g < blocks;
+    uint64_t base = g;
+    for (int k = 0; k < 6; k++) base = ins0<uint64_t>(base, srt[k]);
+    if (ok) xs[w][lane] = v[base | off];
+    __syncthreads();
+    c128 y = make_double2(0.0, 0.0);
+    if (ok) {
+      for (int s = 0; s < nk; s++) {
+        const c128 *Ks = K + 64 * s;
+        for (int c = 0; c < 8; c++) {
+          c128 t = make_double2(0.0, 0.0);
+          for (int d = 0; d < 8; d++) t = cfma(xs[w][c + 8 * d], cconj(Ks[8 * b + d]), t);
+          y = cfma(Ks[8 * a + c], t, y);
+        }
+      }
+    }
+    __syncthreads();  // every lane has read the block before the next one is staged
+    if (ok) v[base | off] = y;
+  }
+}
+
 // ------------------------------------------------------------------ misc
 
 __global__ void k_init_basis0(c128 *__restrict__ v, uint64_t N) {
@@ -1011,6 +1058,14 @@ hipError_t launch_gm(c128 *psi, int nbits, int m, const int *q, const c128 *M, h
   if (m == 3) hipLaunchKernelGGL(k_gm<3>, grid, dim3(256), 0, st, psi, nbits, qq, M);
   else if (m == 4) hipLaunchKernelGGL(k_gm<4>, grid, dim3(256), 0, st, psi, nbits, qq, M);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_kraus3(c128 *v, int nbits, int n, const int *q, const c128 *K, int nk, hipStream_t st) {
+  if (nbits < 6 || nk < 1) return hipErrorInvalidValue;
+  const int4 qq = make_int4(q[0], q[1], q[2], 0);
+  const dim3 grid(grid_for(1ull << (nbits - 6), 4));
+  hipLaunchKernelGGL(k_kraus3, grid, dim3(256), 0, st, v, nbits, n, qq, K, nk);
   return hipGetLastError();
 }
 

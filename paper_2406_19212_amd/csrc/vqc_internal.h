@@ -235,6 +235,7 @@ hipError_t launch_grad_reduce(const DGradJob *jobs, int n_items, int max_params,
 hipError_t launch_g1(c128 *psi, int nbits, int q, const c128 *M, int kind, hipStream_t st);
 hipError_t launch_g2(c128 *psi, int nbits, int q0, int q1, const c128 *M, int kind, hipStream_t st);
 hipError_t launch_gm(c128 *psi, int nbits, int m, const int *q, const c128 *M, hipStream_t st);
+hipError_t launch_kraus3(c128 *v, int nbits, int n, const int *q, const c128 *K, int nk, hipStream_t st);
 hipError_t launch_init_basis0(c128 *v, uint64_t N, hipStream_t st);
 hipError_t launch_fill_zero(c128 *v, uint64_t N, hipStream_t st);
 hipError_t launch_copy(c128 *dst, const c128 *src, uint64_t N, hipStream_t st);
