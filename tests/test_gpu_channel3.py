@@ -21,7 +21,7 @@ def maxdiff(a, b):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b))))
 
 
-@pytest.mark.parametrize("n", [3, 4, 6])
+@pytest.mark.parametrize("n", [3, 4, 6, 9])
 def test_three_qubit_kraus_matches_oracle(n):
     v = W.random_density(n, 90 + n).reshape(-1, order="F").copy()
     perms = list(itertools.permutations(range(n), 3))
