@@ -125,3 +125,16 @@ def test_new_entry_points_reject_bad_arguments_on_host(L):
         th = np.zeros(2)
         assert L.vqc_fuse_gates(3, arr.n, arr.ptr(), 2, th.ctypes.data, ctypes.cast(out, P), data.ctypes.data,
                                 ctypes.byref(n_out)) == code
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU only: --gpus above 1 exits with status 2
+    and a message, before any GPU work."""
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(here, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
