@@ -55,7 +55,8 @@ typedef enum {
   VQC_ERR_HIP = -8,           /* HIP runtime error */
   VQC_ERR_NOT_HERMITIAN = -9, /* gradient asked for a complex-coefficient H */
   VQC_ERR_NOT_UNITARY = -10,  /* backward through a non-unitary gate matrix */
-  VQC_ERR_ILL_CONDITIONED = -11 /* a channel's inverse exceeds the condition bound */
+  VQC_ERR_ILL_CONDITIONED = -11, /* a channel's inverse exceeds the condition bound */
+  VQC_ERR_SCRATCH_LIMIT = -12   /* input larger than the allocation-free call's fixed scratch */
 } vqc_status;
 
 typedef enum { VQC_PURE = 0, VQC_MIXED = 1 } vqc_kind;
@@ -207,6 +208,21 @@ vqc_status vqc_apply_channel(vqc_state s, int m, const int *qubits, int n_kraus,
  * written to *out_host (synchronises the stream).  Deterministic FP64 two-stage
  * reduction. */
 vqc_status vqc_expectation(vqc_state s, const vqc_pauli_sum *H, vqc_c128 *out_host);
+
+/* vqc_expectation for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result, with every intermediate (first-stage
+ * partial sums, the Pauli terms, the job record, the result) in one fixed
+ * device array of the library, 1 MiB + 33 KiB, that each GPU holds until the
+ * process ends.  No device or host heap allocation happens on this path; the
+ * first call on a GPU looks up that GPU's copy of the array.  Limits: at most
+ * 1024 terms and 2^28 summed amplitudes (PURE n <= 28; every MIXED size), else
+ * VQC_ERR_SCRATCH_LIMIT with nothing queued.  Every call on one GPU shares the
+ * array: calls that overlap on one GPU (several streams or host threads) race
+ * and must be serialised by the caller.  Nothing in the array needs to start
+ * at zero (every partial sum is written before it is read).  Synchronises the
+ * state's stream; other errors as in vqc_expectation. */
+vqc_status vqc_expectation_noalloc(vqc_state s, const vqc_pauli_sum *H, vqc_c128 *out_host);
 
 /* sum |psi_x|^2 (PURE) or Tr(rho) (MIXED) into *out_host (synchronises). */
 vqc_status vqc_norm(vqc_state s, double *out_host);

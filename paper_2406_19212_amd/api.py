@@ -122,6 +122,14 @@ class State:
         check(lib().vqc_expectation(self.h, ps.ref(), ctypes.byref(out)), "vqc_expectation")
         return complex(out.re, out.im)
 
+    def expectation_noalloc(self, terms) -> complex:
+        """expectation() through the allocation-free entry point (fixed library
+        scratch; at most 1024 terms and 2^28 summed amplitudes)."""
+        ps = B.PauliSum(terms)
+        out = B.vqc_c128()
+        check(lib().vqc_expectation_noalloc(self.h, ps.ref(), ctypes.byref(out)), "vqc_expectation_noalloc")
+        return complex(out.re, out.im)
+
     def norm(self) -> float:
         out = ctypes.c_double()
         check(lib().vqc_norm(self.h, ctypes.byref(out)), "vqc_norm")

@@ -38,7 +38,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "qubit out of range or repeated",
           -5: "Kraus operators are not trace preserving", -6: "non-finite input",
           -7: "device out of memory", -8: "HIP runtime error",
           -9: "observable must have real coefficients", -10: "gate matrix is not unitary",
-          -11: "channel inverse exceeds the condition-number bound"}
+          -11: "channel inverse exceeds the condition-number bound",
+          -12: "input exceeds the fixed scratch of the allocation-free call"}
 
 
 class VQCError(RuntimeError):
@@ -89,6 +90,7 @@ _SIGS = {
     "vqc_apply_op": (c_int, [c_void_p, ctypes.POINTER(vqc_op)]),
     "vqc_apply_channel": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p]),
     "vqc_expectation": (c_int, [c_void_p, ctypes.POINTER(vqc_pauli_sum), ctypes.POINTER(vqc_c128)]),
+    "vqc_expectation_noalloc": (c_int, [c_void_p, ctypes.POINTER(vqc_pauli_sum), ctypes.POINTER(vqc_c128)]),
     "vqc_norm": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
     "vqc_gather": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     "vqc_circuit_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_int, c_void_p, c_int,

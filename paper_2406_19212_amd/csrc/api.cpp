@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1097,24 +1098,34 @@ vqc_status upload_const(vqc_circuit c) {
 }
 
 // terms with i^{|Y|} folded into the coefficient
+// term t of H with i^{|Y|} folded into its coefficient
+vqc_status make_term(const vqc_pauli_sum *H, int t, int nbits_q, bool need_real, DTerm &d) {
+  const uint64_t xm = H->x_mask[t], zm = H->z_mask[t];
+  if (nbits_q < 64 && ((xm | zm) >> nbits_q)) return VQC_ERR_QUBIT;
+  double cr = H->coeff_re[t], ci = H->coeff_im ? H->coeff_im[t] : 0.0;
+  if (!is_finite_d(cr) || !is_finite_d(ci)) return VQC_ERR_NONFINITE;
+  if (need_real && ci != 0.0) return VQC_ERR_NOT_HERMITIAN;
+  const int ny = popc(xm & zm) & 3;
+  double r = cr, i = ci;
+  for (int k = 0; k < ny; k++) { const double tr = -i; i = r; r = tr; }  // multiply by i
+  d.xm = xm;
+  d.zm = zm;
+  d.cre = r;
+  d.cim = i;
+  return VQC_OK;
+}
+
+bool pauli_sum_ok(const vqc_pauli_sum *H) {
+  return H && H->n_terms >= 0 && (H->n_terms == 0 || (H->x_mask && H->z_mask && H->coeff_re));
+}
+
 vqc_status make_terms(const vqc_pauli_sum *H, int nbits_q, std::vector<DTerm> &out, bool need_real) {
-  if (!H || H->n_terms < 0 || (H->n_terms > 0 && (!H->x_mask || !H->z_mask || !H->coeff_re)))
-    return VQC_ERR_ARG;
+  if (!pauli_sum_ok(H)) return VQC_ERR_ARG;
   out.clear();
   for (int t = 0; t < H->n_terms; t++) {
-    const uint64_t xm = H->x_mask[t], zm = H->z_mask[t];
-    if (nbits_q < 64 && ((xm | zm) >> nbits_q)) return VQC_ERR_QUBIT;
-    double cr = H->coeff_re[t], ci = H->coeff_im ? H->coeff_im[t] : 0.0;
-    if (!is_finite_d(cr) || !is_finite_d(ci)) return VQC_ERR_NONFINITE;
-    if (need_real && ci != 0.0) return VQC_ERR_NOT_HERMITIAN;
-    const int ny = popc(xm & zm) & 3;
-    double r = cr, i = ci;
-    for (int k = 0; k < ny; k++) { const double tr = -i; i = r; r = tr; }  // multiply by i
     DTerm d;
-    d.xm = xm;
-    d.zm = zm;
-    d.cre = r;
-    d.cim = i;
+    const vqc_status st = make_term(H, t, nbits_q, need_real, d);
+    if (st) return st;
     out.push_back(d);
   }
   return VQC_OK;
@@ -1199,6 +1210,51 @@ uint64_t state_len(vqc_kind kind, int n) { return kind == VQC_MIXED ? (1ull << (
 
 // ===================================================================== C ABI
 
+// ------------------------------------------- scratch of the allocation-free
+// expectation (vqc_expectation_noalloc).  One fixed array per GPU, held for
+// the life of the process: first-stage partial sums, the Pauli terms, the
+// job record and the result.  In host code `scratch` names a host-side
+// stand-in; kernels get the device address returned by hipGetSymbolAddress.
+constexpr int64_t kNaMaxUnits = int64_t(1) << 16;  // partials: 2^16 x 4096 = 2^28 amplitudes
+constexpr int kNaMaxTerms = 1024;
+constexpr size_t kNaTermOff = size_t(kNaMaxUnits) * sizeof(double2);
+constexpr size_t kNaJobOff = kNaTermOff + size_t(kNaMaxTerms) * sizeof(DTerm);
+constexpr size_t kNaResOff = kNaJobOff + 256;
+constexpr size_t kNaBytes = kNaResOff + 256;
+static_assert(sizeof(DEJob) <= 256, "job record must fit its slot");
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+char *g_na_ptr[kNaMaxDevices] = {};
+
+// device address of `scratch` on the GPU that runs `st`, looked up once per
+// device with that device current
+hipError_t na_scratch(hipStream_t st, char **out) {
+  int dev = 0;
+  hipError_t e = hipStreamGetDevice(st, &dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kNaMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    int cur = 0;
+    e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    const hipError_t e2 = (cur != dev) ? hipSetDevice(cur) : hipSuccess;
+    if (e != hipSuccess) return e;
+    if (e2 != hipSuccess) return e2;
+    if (!p) return hipErrorInvalidSymbol;
+    g_na_ptr[dev] = static_cast<char *>(p);
+  }
+  *out = g_na_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 const char *vqc_status_string(int st) {
@@ -1215,6 +1271,7 @@ const char *vqc_status_string(int st) {
     case VQC_ERR_NOT_HERMITIAN: return "observable must have real coefficients";
     case VQC_ERR_NOT_UNITARY: return "gate matrix is not unitary";
     case VQC_ERR_ILL_CONDITIONED: return "channel inverse exceeds the condition-number bound";
+    case VQC_ERR_SCRATCH_LIMIT: return "input exceeds the fixed scratch of the allocation-free call";
     default: return "unknown status";
   }
 }
@@ -1539,6 +1596,44 @@ vqc_status vqc_expectation(vqc_state s, const vqc_pauli_sum *H, vqc_c128 *out) {
   vqc_status st = make_terms(H, s->n, terms, false);
   if (st) return st;
   return expect_into(s, terms, out);
+}
+
+vqc_status vqc_expectation_noalloc(vqc_state s, const vqc_pauli_sum *H, vqc_c128 *out) {
+  if (!s || !out || !pauli_sum_ok(H)) return VQC_ERR_ARG;
+  const int64_t units = expect_units(s->n);
+  if (H->n_terms > kNaMaxTerms || units > kNaMaxUnits) return VQC_ERR_SCRATCH_LIMIT;
+  // terms staged in host memory that outlives the copy (the call ends with a
+  // stream synchronisation); no heap allocation on this path
+  DTerm terms[kNaMaxTerms];
+  for (int t = 0; t < H->n_terms; t++) {
+    const vqc_status st = make_term(H, t, s->n, false, terms[t]);
+    if (st) return st;
+  }
+  char *sc = nullptr;
+  VQC_TRY(na_scratch(s->stream, &sc));
+  DTerm *dterms = reinterpret_cast<DTerm *>(sc + kNaTermOff);
+  DEJob *djob = reinterpret_cast<DEJob *>(sc + kNaJobOff);
+  double2 *dres = reinterpret_cast<double2 *>(sc + kNaResOff);
+  DEJob j;
+  std::memset(&j, 0, sizeof(j));
+  j.psi = s->buf;
+  j.out = nullptr;
+  j.partial = reinterpret_cast<double2 *>(sc);  // every unit writes its own entry
+  j.unit0 = 0;
+  j.n_units = units;
+  j.nbits = s->n;
+  j.mixed = s->kind == VQC_MIXED;
+  if (H->n_terms > 0)
+    VQC_TRY(hipMemcpyAsync(dterms, terms, size_t(H->n_terms) * sizeof(DTerm), hipMemcpyHostToDevice, s->stream));
+  VQC_TRY(hipMemcpyAsync(djob, &j, sizeof(j), hipMemcpyHostToDevice, s->stream));
+  VQC_TRY(launch_expect(djob, 1, units, dterms, H->n_terms, s->stream));
+  VQC_TRY(launch_reduce_partials(djob, 1, dres, s->stream));
+  double2 r;
+  VQC_TRY(hipMemcpyAsync(&r, dres, sizeof(r), hipMemcpyDeviceToHost, s->stream));
+  VQC_TRY(hipStreamSynchronize(s->stream));
+  out->re = r.x;
+  out->im = r.y;
+  return VQC_OK;
 }
 
 vqc_status vqc_norm(vqc_state s, double *out) {
