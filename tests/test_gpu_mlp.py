@@ -2,17 +2,20 @@
 
 GEMM: inputs rounded to BF16 exactly as the kernel rounds them, products
 exact in FP32, so |C - C_ref| <= (K-1) 2^-24 sum_k |a_k b_k| (FP32
-accumulation bound) element by element.  Network: the device also rounds
-intermediate activations to BF16 before each product, which the FP64 oracle
-does not, so outputs and gradients are compared relative to their largest
-magnitude per parameter block with 2e-2 -- a wrong transpose, index or
-dropped term gives O(1) relative errors."""
+accumulation bound) element by element.  Network: the output, the input
+gradient and every parameter-gradient entry are compared element by element
+with the bounds of tests/mlp_bounds.py -- the device's steps walked in
+float64 with the BF16 roundings where the kernels round, FP32 accumulation
+bounds and flips of a BF16 rounding allowed only where the bound straddles
+a rounding boundary -- whose values equal oracle.mlp's BF16 mode (autograd
+of the network's definition)."""
 import numpy as np
 import pytest
 import torch
 
 from oracle import mlp as omlp
 from paper_2406_19212_amd import workloads as W
+from tests import mlp_bounds as MB
 from paper_2406_19212_amd.mlp import MLP, gemm_bf16
 
 pytestmark = pytest.mark.gpu
@@ -73,17 +76,24 @@ def test_mlp_forward_and_gradients(lam):
     g = (0.1 * rng.normal(size=(B, dims[0]))).astype(np.float32)
     xt, et, gt = (torch.tensor(v, device="cuda") for v in (x, e, g))
     y, gx = net.forward(xt, want_grad=True)
-    L, dP, y_ref, gx_ref = omlp.loss_and_grads(p32, x, e, g, lam, dims)
-    y_bf = omlp.forward(p32, x, dims, bf16=True).numpy()
-    assert np.max(np.abs(y.cpu().numpy() - y_bf)) <= 2e-2 * np.max(np.abs(y_bf))
+    grads = net.backward(xt, et, gt if lam else None, lam).double().cpu().numpy()
+    m = MB.model(p32, x, e, g, lam, dims)
+    # the bound's values are the rounding oracle's (autograd of the definition)
+    _, dP_bf, y_bf, gx_bf = omlp.loss_and_grads(p32, x, e, g, lam, dims, bf16=True)
+    for want, ref in ((y_bf, m["y"]), (gx_bf, m["gx"]), (dP_bf, MB.flat_grad(m))):
+        diff = np.abs(np.asarray(want).reshape(-1) - ref.v.numpy().reshape(-1))
+        assert np.all(diff <= 1e-3 * ref.d.numpy().reshape(-1) + 1e-300), float(diff.max())
+    # the device within the element-wise bounds (<= 1 passes)
+    ex = {"y": MB.excess(y.double().cpu(), m["y"]), "gx": MB.excess(gx.double().cpu(), m["gx"])}
+    got = _blocks(dims, grads)
+    for pk, gk in zip(omlp.LAYOUT, MB.BLOCKS):
+        ex[gk] = MB.excess(got[pk].reshape(-1), MB.V(m[gk].v.reshape(-1), m[gk].d.reshape(-1)))
+    print("bound excess (<= 1 passes):", {k: round(v, 4) for k, v in ex.items()})
+    assert max(ex.values()) <= 1.0, ex
+    # and the BF16 network stays close to the float64 definition
+    _, dP, y_ref, gx_ref = omlp.loss_and_grads(p32, x, e, g, lam, dims)
     assert np.max(np.abs(y.cpu().numpy() - y_ref)) <= 2e-2 * np.max(np.abs(y_ref))
     assert np.max(np.abs(gx.cpu().numpy() - gx_ref)) <= 2e-2 * np.max(np.abs(gx_ref))
-    grads = net.backward(xt, et, gt if lam else None, lam).double().cpu().numpy()
-    got, ref = _blocks(dims, grads), _blocks(dims, dP)
-    for k in ref:
-        scale = np.max(np.abs(ref[k]))
-        err = np.max(np.abs(got[k] - ref[k]))
-        assert err <= 2e-2 * scale + 1e-7, (k, err, scale)
 
 
 def test_adam_step_and_input_descent():
