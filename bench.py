@@ -54,7 +54,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # sources still have the digest recorded with the counters
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "rqc28_fused_pass_traffic.txt")
 KERNEL_SOURCES = ["paper_2406_19212_amd/csrc/pass_kernels.h", "paper_2406_19212_amd/csrc/vqc_internal.h",
-                  "paper_2406_19212_amd/csrc/inst_lds.hip", "paper_2406_19212_amd/build.py"]
+                  "paper_2406_19212_amd/csrc/inst_lds.hip", "paper_2406_19212_amd/csrc/jit_pass.h",
+                  "paper_2406_19212_amd/csrc/jit.cpp", "paper_2406_19212_amd/csrc/api.cpp",
+                  "paper_2406_19212_amd/build.py"]
 
 
 def parse():
@@ -370,7 +372,9 @@ def main():
     seed = W.CONFIG_SEED[1]
     ops = W.rqc_grid(rows, cols, cycles, seed)
     idx = W.rqc_bitstrings(n, 1000, seed + 1)
-    circ = Circuit(n, ops)
+    t0 = time.perf_counter()
+    circ = Circuit(n, ops)  # plans the fused passes and compiles them for this circuit
+    create_s = time.perf_counter() - t0
     stats = circ.stats()
     st = State(n)
 
@@ -402,7 +406,9 @@ def main():
     traffic = measured_traffic()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_pass_lds<%d,%d,0>" % (stats["tile_bits"], stats["reg_bits"]),
+            "kernel": ("vqc_jf0..%d (k_pass_lds<%d,%d,0> driver specialised per pass)"
+                       % (stats["n_passes"] - 1, stats["tile_bits"], stats["reg_bits"])
+                       if stats["n_jit_passes"] else "k_pass_lds<%d,%d,0>" % (stats["tile_bits"], stats["reg_bits"])),
             "avg_pass_ms": round(avg_ms, 4), "passes": stats["n_passes"], "bytes_per_pass": pass_bytes,
             "kernel_digest": kernel_digest()}
 
@@ -413,7 +419,10 @@ def main():
            "config": {"workload": "rqc-4x7-28q-20cycles", "n_qubits": n, "gates": len(ops),
                       "fsim": sum(1 for o in ops if o.name == "fsim"), "seed": seed,
                       "passes": stats["n_passes"], "tile_bits": stats["tile_bits"],
-                      "low_bits": stats["low_bits"], "norm_minus_1": float(nrm - 1.0),
+                      "low_bits": stats["low_bits"], "reg_bits": stats["reg_bits"],
+                      "specialised_passes": stats["n_jit_passes"], "compile_s": round(stats["jit_ms"] / 1e3, 2),
+                      "code_cached": stats["jit_cached"], "circuit_create_s": round(create_s, 2),
+                      "norm_minus_1": float(nrm - 1.0),
                       "mean_2n_abs2": float(np.mean(np.abs(amps) ** 2) * amps_n)},
            "roofline": roof}
     rec["sampling"] = sampling(torch, st, n)

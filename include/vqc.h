@@ -36,8 +36,10 @@
 #ifndef VQC_ABI_INCLUDED
 #define VQC_ABI_INCLUDED
 
+#ifndef __HIPCC_RTC__
 #include <stddef.h>
 #include <stdint.h>
+#endif
 
 #ifdef __cplusplus
 extern "C" {
@@ -132,13 +134,23 @@ typedef struct {
  * pass (the state ends in the standard layout; the circuit then holds a
  * second state buffer of the same size, two for the gradient plan, and a
  * batch one or two per item): 1 on, -1 off, 0 default (on from 12 qubits,
- * pure states; the gradient plan moves qubits up to 30 qubits). */
+ * pure states; the gradient plan moves qubits up to 30 qubits).
+ * jit: the forward passes of a pure-state circuit run as kernels compiled at
+ * circuit creation for this circuit's op sequence (hipRTC; the fused-pass
+ * driver with every op's kind and register bits fixed at compile time, the
+ * parameters still read from device memory, so one compile serves every
+ * theta; code objects are cached on disk): 1 on (creation fails with
+ * VQC_ERR_HIP if the compile fails), -1 off, 0 default (on from 20 qubits
+ * with tiles of at most 11 qubits, silently off if the compile fails).  The
+ * environment variable VQC_JIT=0 (or 1) turns them off (on) for every
+ * eligible circuit. */
 typedef struct {
   int tile_bits;
   int low_bits;
   int reg_bits;
   int grid_blocks;
   int remap;
+  int jit;
 } vqc_tune;
 
 typedef struct {
@@ -153,6 +165,9 @@ typedef struct {
   int n_adj_passes;   /* HBM passes of the adjoint (gradient) plan */
   int n_fwd_moves;    /* forward passes that move qubits (run out of place) */
   int n_adj_moves;    /* adjoint passes that move qubits */
+  int n_jit_passes;   /* forward passes running as circuit-specialised kernels */
+  int jit_cached;     /* 1: their code object came from the on-disk cache */
+  double jit_ms;      /* compile (or cache load) and module load time */
 } vqc_circuit_stats;
 
 /* ------------------------------------------------------------------ misc */

@@ -172,7 +172,7 @@ class Circuit:
         t = None
         if tune is not None:
             t = B.vqc_tune(*[int(tune.get(k, 0)) for k in ("tile_bits", "low_bits", "reg_bits", "grid_blocks",
-                                                           "remap")])
+                                                           "remap", "jit")])
         h = ctypes.c_void_p()
         check(lib().vqc_circuit_create(ctypes.byref(h), self.n, B.VQC_MIXED if self.mixed else B.VQC_PURE,
                                        arr.n, arr.ptr(), self.n_params,
@@ -192,7 +192,9 @@ class Circuit:
                 "n_stages": s.n_stages, "n_var": s.n_var, "n_params": s.n_params,
                 "tile_bits": s.tune.tile_bits, "low_bits": s.tune.low_bits, "reg_bits": s.tune.reg_bits,
                 "grid_blocks": s.tune.grid_blocks, "remap": s.tune.remap, "alg_bytes_per_amp": s.alg_bytes_per_amp,
-                "n_adj_passes": s.n_adj_passes, "n_fwd_moves": s.n_fwd_moves, "n_adj_moves": s.n_adj_moves}
+                "n_adj_passes": s.n_adj_passes, "n_fwd_moves": s.n_fwd_moves, "n_adj_moves": s.n_adj_moves,
+                "jit": s.tune.jit, "n_jit_passes": s.n_jit_passes, "jit_cached": bool(s.jit_cached),
+                "jit_ms": s.jit_ms}
 
     def _theta(self, theta):
         if self.n_params == 0:

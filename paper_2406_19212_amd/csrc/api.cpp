@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/vqc.h"
+#include "jit.h"
 #include "vqc_internal.h"
 
 using namespace vqc;
@@ -37,6 +38,10 @@ constexpr int kAdjRemapMaxBits = 30;
 // inverse-form adjoint on 11-bit LDS tiles (the 16x16 superoperator kind is
 // compiled into that instantiation only)
 constexpr int kMixedLdsMinBits = 12;
+// pure-state plans with at least this many qubits get circuit-specialised
+// forward passes compiled at run time (vqc_tune.jit = 0); below it a pass is
+// too short for the compile to pay off and the interpreting kernel runs
+constexpr int kJitMinBits = 20;
 constexpr int kMixedTile = 11;
 constexpr int kR = 4;
 
@@ -253,6 +258,7 @@ struct PassH {
   std::vector<int> tq_out;  // physical bit of tile-local bit i in the output layout
   bool moves = false;       // output layout differs from the input layout
   int src = 0, dst = 0;     // 0: the state's buffer, 1: the circuit's scratch state
+  int lowfree = 0;          // DPass.lowfree as uploaded
   struct Stage {
     int rbit[4];
     std::vector<int> elems;  // indices into elems
@@ -277,6 +283,9 @@ struct Plan {
   int n_gates = 0;
   const DGate *d_gates = nullptr;
   const DDeriv *d_derivs = nullptr;
+  // circuit-specialised kernels of the passes (forward plans of pure states);
+  // empty: the interpreting kernels run
+  std::unique_ptr<JitModule> jit;
 };
 
 int popc(uint64_t v) { return __builtin_popcountll(v); }
@@ -296,6 +305,7 @@ void reset_plan(Plan &P) {
   P.d_jobs1 = nullptr;
   P.d_gates = nullptr;
   P.d_derivs = nullptr;
+  P.jit.reset();
 }
 
 // First-fit fusion: walk the remaining ops in order; an op joins the pass if
@@ -561,6 +571,8 @@ struct vqc_state_s {
 };
 
 struct vqc_circuit_s {
+  double jit_ms = 0;        // run-time compile (or cache load) of the specialised passes
+  bool jit_cached = false;
   int n, nbits;
   vqc_kind kind;
   int n_params;
@@ -850,6 +862,7 @@ vqc_status lower(vqc_circuit c) {
 // upload pass tables of a plan; single-item jobs reference no buffers (the
 // kernel arguments supply them)
 vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
+  P.jit.reset();
   std::vector<DPass> passes(P.passes.size());
   std::vector<DStage> stages;
   std::vector<DGate> gates;
@@ -922,6 +935,7 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
       dp.lowfree = ((lowfree(ph.stages.front()) && !out_front) ? 1 : 0) |
                    ((lowfree(ph.stages.back()) && !out_back) ? 2 : 0);
     }
+    P.passes[p].lowfree = dp.lowfree;
     for (int i = 0; i < ph.K; i++) dp.tq[i] = (int8_t)ph.tq[i];
     // output order: tile-local bits by ascending output position
     std::vector<int> ord(ph.K);
@@ -975,6 +989,149 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
   return VQC_OK;
 }
 
+// Source of the circuit-specialised forward passes of a pure-state LDS plan:
+// for pass p a description JP<p> (tile and stage bit layouts, each op's kind
+// and register bits, in program order) and the kernel vqc_jf<p>, which
+// instantiates jit_pass.h's driver for it.  The op parameters stay in the
+// item's op program, so one compiled plan serves every theta.
+std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist) {
+  std::string s = "#include \"jit_pass.h\"\nnamespace vqc {\n";
+  char buf[512];
+  auto arr = [&](const char *name, const std::vector<int> &v) {
+    std::string r = std::string("  static constexpr int ") + name + "[" + std::to_string(v.size()) + "] = {";
+    for (size_t i = 0; i < v.size(); i++) r += (i ? ", " : "") + std::to_string(v[i]);
+    return r + "};\n";
+  };
+  int g = 0;  // op index in the plan's program (upload_plan's order)
+  for (size_t p = 0; p < P.passes.size(); p++) {
+    const PassH &ph = P.passes[p];
+    const int K = ph.K, R = P.R, nst = (int)ph.stages.size();
+    int loc[64];
+    for (int i = 0; i < (int)ph.lq.size(); i++) loc[ph.lq[i]] = i;
+    std::vector<int> ord(K), tqo(K), lbo(K), tq(ph.tq.begin(), ph.tq.end());
+    for (int i = 0; i < K; i++) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int x, int y) { return ph.tq_out[x] < ph.tq_out[y]; });
+    for (int i = 0; i < K; i++) {
+      lbo[i] = ord[i];
+      tqo[i] = ph.tq_out[ord[i]];
+    }
+    std::snprintf(buf, sizeof(buf),
+                  "struct JP%zu {\n  static constexpr int K = %d, R = %d, NST = %d, PROG = %d, G0 = %d;\n"
+                  "  static constexpr bool DOUT = %s;\n",
+                  p, K, R, nst, P.prog, g, (ph.lowfree & 2) ? "true" : "false");
+    s += buf;
+    s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo);
+    const int rows = std::max(nst, 1);  // a pass without ops only moves qubits
+    std::string rb = "  static constexpr int RBIT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
+    std::string sr = "  static constexpr int SRT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
+    if (nst == 0) {
+      rb += "{0}";
+      sr += "{0}";
+    }
+    for (int si = 0; si < nst; si++) {
+      int srt[4];
+      for (int i = 0; i < R; i++) srt[i] = ph.stages[si].rbit[i];
+      std::sort(srt, srt + R);
+      rb += si ? ", {" : "{";
+      sr += si ? ", {" : "{";
+      for (int i = 0; i < R; i++) {
+        rb += (i ? ", " : "") + std::to_string(ph.stages[si].rbit[i]);
+        sr += (i ? ", " : "") + std::to_string(srt[i]);
+      }
+      rb += "}";
+      sr += "}";
+    }
+    s += rb + "};\n" + sr + "};\n";
+    std::snprintf(buf, sizeof(buf),
+                  "  template <int S>\n  __device__ static __forceinline__ DOp stage(c128 (&a)[%d], DOp E, "
+                  "const DOp *prog, cmat *M) {\n",
+                  1 << R);
+    s += buf;
+    for (int si = 0; si < nst; si++) {
+      const PassH::Stage &S = ph.stages[si];
+      int regpos[64];
+      for (int i = 0; i < R; i++) regpos[S.rbit[i]] = i;
+      s += si ? "    else if constexpr (S == " : "    if constexpr (S == ";
+      s += std::to_string(si) + ") {\n";
+      for (int ei : S.elems) {
+        const Elem &e = c->elems[ei];
+        const int b0 = e.nq > 0 ? regpos[loc[e.q[0]]] : 0, b1 = e.nq > 1 ? regpos[loc[e.q[1]]] : 0;
+        std::snprintf(buf, sizeof(buf), "      E = jop<%d, %d, %d, %d>(a, E, prog + %d, M);\n", R, e.kind, b0, b1,
+                      g + 1);
+        s += buf;
+        g++;
+      }
+      s += "      return E;\n    }\n";
+    }
+    s += nst ? "    else return E;\n  }\n};\n" : "    return E;\n  }\n};\n";
+    std::snprintf(buf, sizeof(buf),
+                  "extern \"C\" __global__ void __launch_bounds__(%d) vqc_jf%zu(const DJob *__restrict__ jobs, "
+                  "int n_jobs, int64_t total_units, DOverride ov) {\n  jit_pass_fwd<JP%zu, %s>(jobs, n_jobs, "
+                  "total_units, ov);\n}\n",
+                  1 << (K - R), p, p, persist ? "true" : "false");
+    s += buf;
+  }
+  return s + "}  // namespace vqc\n";
+}
+
+// whether a pure-state circuit asks for circuit-specialised forward passes
+// (vqc_tune.jit; VQC_JIT=0 / 1 in the environment turns them off / on for
+// every eligible plan)
+bool jit_default_on(vqc_circuit c) {
+  if (c->kind != VQC_PURE) return false;
+  if (const char *e = std::getenv("VQC_JIT")) {
+    if (e[0] == '0') return false;
+    if (e[0] == '1') return true;
+  }
+  if (c->tune.jit < 0) return false;
+  return c->tune.jit > 0 || c->nbits >= kJitMinBits;
+}
+
+bool jit_wanted(vqc_circuit c) {
+  const Plan &P = c->fwd;
+  if (c->kind != VQC_PURE || P.reg_only || P.d4 || P.passes.empty() || P.K > 11) return false;
+  return jit_default_on(c);
+}
+
+// compile (or load from the cache) the forward plan's specialised passes;
+// a failure leaves the interpreting kernels in charge unless the caller
+// asked for these kernels (vqc_tune.jit = 1)
+vqc_status jit_prepare(vqc_circuit c) {
+  Plan &P = c->fwd;
+  P.jit.reset();
+  c->jit_ms = 0;
+  if (!jit_wanted(c)) return VQC_OK;
+  std::vector<std::string> names;
+  for (size_t p = 0; p < P.passes.size(); p++) names.push_back("vqc_jf" + std::to_string(p));
+  std::unique_ptr<JitModule> m(new (std::nothrow) JitModule());
+  if (!m) return VQC_ERR_OOM;
+  std::string log;
+  std::vector<int> threads;
+  for (const PassH &ph : P.passes) threads.push_back(1 << (ph.K - P.R));
+  // persistent grids when the caller asked for a grid size (vqc_tune.grid_blocks)
+  const bool persist = c->tune.grid_blocks > 0;
+  const std::string src = jit_source_fwd(c, P, persist);
+  if (const char *dump = std::getenv("VQC_JIT_DUMP")) {  // keep the generated source for inspection
+    if (FILE *f = std::fopen((std::string(dump) + "/vqc_jit_" + std::to_string(c->n) + ".hip").c_str(), "w")) {
+      std::fputs(src.c_str(), f);
+      std::fclose(f);
+    }
+  }
+  const hipError_t e = jit_build(src, names, threads, *m, &log);
+  if (e != hipSuccess) {
+    if (std::getenv("VQC_JIT_VERBOSE")) std::fprintf(stderr, "vqc: run-time compile failed:\n%s\n", log.c_str());
+    return c->tune.jit > 0 ? VQC_ERR_HIP : VQC_OK;
+  }
+  if (persist)
+    for (int &r : m->resident) r = std::min(r, c->tune.grid_blocks);
+  else
+    for (int &r : m->resident) r = 0x7fffffff;  // one block per tile
+  c->jit_ms = m->ms;
+  c->jit_cached = m->cached;
+  P.jit = std::move(m);
+  return VQC_OK;
+}
+
 vqc_status make_plans(vqc_circuit c) {
   const bool mixed = c->kind == VQC_MIXED;
   const int nb = c->nbits;
@@ -993,6 +1150,10 @@ vqc_status make_plans(vqc_circuit c) {
     R = 3;
     Radj = 3;
   }
+  // specialised forward passes run best with three register bits (more waves
+  // per SIMD; measured on the 28-qubit circuit: 45.6 ms against 48.8 ms with
+  // four), the interpreting kernel with four
+  if (!reg_only && !mixed && c->tune.reg_bits == 0 && jit_default_on(c)) R = 3;
   // op programs follow the recipe outputs in each item's matrix buffer
   reset_plan(c->fwd_reg);
   reset_plan(c->adj_lds);
@@ -1160,6 +1321,19 @@ hipError_t build_mats(vqc_circuit c, const double *const *thetas, c128 *const *m
   return launch_assemble(c->adj.d_gates, c->adj.d_derivs, c->adj.n_gates, c->adj.prog, mats, B, mats0, st);
 }
 
+// one specialised pass: a block per tile of every job (the driver is not
+// persistent), static LDS
+hipError_t launch_jit_pass(const JitModule &m, size_t p, const Plan &P, const DJob *jobs, int n_jobs, int64_t total,
+                           const DOverride &ov, hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  if (p >= m.fn.size() || p >= m.resident.size()) return hipErrorInvalidValue;
+  const int64_t grid = std::min<int64_t>(total, m.resident[p]);
+  DOverride o = ov;
+  void *args[] = {&jobs, &n_jobs, &total, &o};
+  return hipModuleLaunchKernel(m.fn[p], (unsigned)grid, 1, 1, 1u << (P.passes[p].K - P.R), 1, 1, 0, st, args,
+                               nullptr);
+}
+
 // run passes [p0, p1) of a plan on one item (dir > 0: forward order)
 // mode 0: forward in place (b == nullptr) or a -> b; 1: pure adjoint; 2: mixed adjoint
 hipError_t run_passes(vqc_circuit c, Plan &P, int mode, c128 *a, c128 *b, const c128 *mats, double *partials,
@@ -1197,7 +1371,8 @@ hipError_t run_passes(vqc_circuit c, Plan &P, int mode, c128 *a, c128 *b, const 
       ov.mode = ph.src != ph.dst ? 1 : 0;
     }
     hipError_t e;
-    if (P.reg_only) e = launch_pass_reg(P.R, mode, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
+    if (mode == 0 && P.jit) e = launch_jit_pass(*P.jit, p, P, P.d_jobs1 + p, 1, P.units_per_item, ov, st);
+    else if (P.reg_only) e = launch_pass_reg(P.R, mode, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
     else e = launch_pass_lds(P.K, P.R, mode != 0, P.d4, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
     if (e != hipSuccess) return e;
   }
@@ -1980,7 +2155,7 @@ vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops,
   if (n < 1 || (kind == VQC_PURE && n > 33) || (kind == VQC_MIXED && n > 16)) return VQC_ERR_ARG;
   if (tune && (tune->tile_bits < 0 || tune->tile_bits > kMaxTile || tune->low_bits < 0 || tune->grid_blocks < 0 ||
                (tune->reg_bits != 0 && tune->reg_bits != 3 && tune->reg_bits != 4) || tune->remap < -1 ||
-               tune->remap > 1))
+               tune->remap > 1 || tune->jit < -1 || tune->jit > 1))
     return VQC_ERR_ARG;
   for (int j = 0; j < n_ops; j++) {
     vqc_status st = validate_op(ops[j], n, kind, n_params);
@@ -2009,6 +2184,8 @@ vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops,
   st = make_plans(c.get());
   if (st) return st;
   st = upload_const(c.get());
+  if (st) return st;
+  st = jit_prepare(c.get());
   if (st) return st;
   *out = c.release();
   return VQC_OK;
@@ -2046,6 +2223,9 @@ vqc_status vqc_circuit_stats_get(vqc_circuit c, vqc_circuit_stats *out) {
   out->n_adj_passes = (int)c->adj.passes.size();
   for (const PassH &ph : c->fwd.passes) out->n_fwd_moves += ph.moves;
   for (const PassH &ph : c->adj.passes) out->n_adj_moves += ph.moves;
+  out->n_jit_passes = c->fwd.jit ? (int)c->fwd.jit->fn.size() : 0;
+  out->jit_ms = c->jit_ms;
+  out->jit_cached = c->jit_cached ? 1 : 0;
   return VQC_OK;
 }
 
@@ -2303,6 +2483,8 @@ vqc_status vqc_circuit_autotune(vqc_circuit c, vqc_state s, const double *theta,
   c->tune = best;
   vqc_status st = make_plans(c);
   if (st) return st;
+  st = jit_prepare(c);
+  if (st) return st;
   *out = c->tune;
   return VQC_OK;
 }
@@ -2499,11 +2681,15 @@ static vqc_status batch_forward_on(vqc_batch b, hipStream_t st) {
   DOverride ov;
   std::memset(&ov, 0, sizeof(ov));
   vqc_circuit c0 = b->circ[0];
+  // every item runs the same circuit: step sI is that circuit's pass sI
+  bool same = true;
+  for (int i = 1; i < b->B; i++) same = same && b->circ[i] == c0;
   for (int sI = 0; sI < b->max_passes; sI++) {
     const int64_t units = b->fwd_units[sI];
     const int grid = grid_of(c0, units);
     const DJob *jobs = b->d_fwd_jobs + b->fwd_first[sI];
-    if (b->reg_only) VQC_TRY(launch_pass_reg(c0->fwd.R, 0, jobs, b->fwd_count[sI], units, grid, ov, st));
+    if (same && c0->fwd.jit) VQC_TRY(launch_jit_pass(*c0->fwd.jit, sI, c0->fwd, jobs, b->fwd_count[sI], units, ov, st));
+    else if (b->reg_only) VQC_TRY(launch_pass_reg(c0->fwd.R, 0, jobs, b->fwd_count[sI], units, grid, ov, st));
     else VQC_TRY(launch_pass_lds(c0->fwd.K, c0->fwd.R, false, c0->fwd.d4, jobs, b->fwd_count[sI], units, grid, ov,
                                  st));
   }

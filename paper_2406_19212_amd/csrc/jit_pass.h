@@ -1,0 +1,243 @@
+// Circuit-specialised fused passes (pure states, LDS tiles).
+//
+// The interpreting pass kernel (k_pass_lds) reads each op's kind and register
+// bits from its program and branches to the matching code: about 40 scalar
+// instructions and a few branches per op, next to 50-60 FP64 FMAs.  Here the
+// host planner emits, for each pass of a circuit, a small description -- the
+// tile's qubits, each stage's register bits and the kind and register bits of
+// every op -- and this driver is compiled against it at run time (hipRTC).
+// Every index of the tile, the stages and the ops is then a compile-time
+// constant; only the op parameters (rotation records, matrix offsets) and the
+// state pointers are read at run time, from the same op program and job
+// tables the interpreter uses, and the same register-level op templates
+// (pass_kernels.h) do the arithmetic.
+//
+// A pass description P provides
+//   K, R                   tile bits and register bits
+//   NST                    stages
+//   TQ[K]                  physical bit of tile-local bit i (input layout)
+//   TQO[K], LBO[K]         output layout: physical bits in ascending order and
+//                          the tile-local bit stored at each
+//   RBIT[NST][R]           tile-local bit held in register bit i of a stage
+//   DOUT                   the last stage holds none of the low bits and the
+//                          pass does not move qubits: it stores straight to HBM
+//   PROG                   c128 offset of the op program in the item's matrices
+//   G0                     program index of the pass's first op
+//   template <int S> static DOp stage(c128 (&a)[1 << R], DOp E, const DOp *prog, cmat *M)
+//                          the ops of stage S in order (calls of jop below);
+//                          E is the entry of the stage's first op, the result
+//                          the entry of the op after the stage
+#pragma once
+#include "pass_kernels.h"
+
+namespace vqc {
+
+// One op of kind KIND on register bits B0 (and B1).  E is its program entry,
+// loaded by the previous op; the entry at `next` is loaded here, after the
+// wait for E and before E's arithmetic, so its scalar load overlaps this op.
+// The scheduling barriers keep the compiler from hoisting every op's load to
+// the top of the pass (which would need far more scalar registers than there
+// are) and from starting the next load before the wait (scalar loads return
+// out of order, so a wait is a wait for all of them).
+template <int R, int KIND, int B0, int B1>
+__device__ __forceinline__ DOp jop(c128 (&a)[1 << R], const DOp &E, const DOp *next, cmat *mats) {
+  constexpr int NR = 1 << R;
+  lgkm_wait();
+  const DOp En = ldc(next);
+  __builtin_amdgcn_sched_barrier(0);
+  SRec r;
+  r.neg = E.neg;
+  r.pad = 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) r.ab[i] = E.ab[i];
+  cmat *M = mats + E.g.mat;
+  const uint32_t n = E.neg;
+  if constexpr (KIND == GK_SXR1) {
+    if (n & 1) rg_sxr1<NR, B0, false, true>(a, r); else rg_sxr1<NR, B0, false, false>(a, r);
+  } else if constexpr (KIND == GK_SRR1) {
+    if (n & 1) rg_srr1<NR, B0, false, true>(a, r); else rg_srr1<NR, B0, false, false>(a, r);
+  } else if constexpr (KIND == GK_SPH1) {
+    if (n & 1) rg_sph1<NR, B0, false, true>(a, r); else rg_sph1<NR, B0, false, false>(a, r);
+  } else if constexpr (KIND == GK_SDG1) {
+    switch (n & 3) {
+      case 0: rg_sdg1<NR, B0, false, false, false>(a, r); break;
+      case 1: rg_sdg1<NR, B0, false, true, false>(a, r); break;
+      case 2: rg_sdg1<NR, B0, false, false, true>(a, r); break;
+      default: rg_sdg1<NR, B0, false, true, true>(a, r); break;
+    }
+  } else if constexpr (KIND == GK_SRD1) {
+    if (n & 2) rg_srd1<NR, B0, false, true>(a, r); else rg_srd1<NR, B0, false, false>(a, r);
+  } else if constexpr (KIND == GK_SFX) {
+    switch (n & 3) {
+      case 0: rg_sfx<NR, B0, B1, false, false, false>(a, r); break;
+      case 1: rg_sfx<NR, B0, B1, false, true, false>(a, r); break;
+      case 2: rg_sfx<NR, B0, B1, false, false, true>(a, r); break;
+      default: rg_sfx<NR, B0, B1, false, true, true>(a, r); break;
+    }
+  } else if constexpr (KIND == GK_DENSE1) {
+    rg_dense1<NR, B0, false>(a, M);
+  } else if constexpr (KIND == GK_DIAG1) {
+    rg_diag1<NR, B0, false>(a, M);
+  } else if constexpr (KIND == GK_XROT1) {
+    rg_xrot1<NR, B0, false>(a, M);
+  } else if constexpr (KIND == GK_REAL1) {
+    rg_real1<NR, B0, false>(a, M);
+  } else if constexpr (KIND == GK_RDIAG1) {
+    rg_rdiag1<NR, B0, false>(a, M);
+  } else if constexpr (KIND == GK_PHASE1) {
+    rg_phase1<NR, B0, false>(a, M);
+  } else if constexpr (KIND == GK_FSIMX) {
+    rg_fsimx<NR, B0, B1, false>(a, M);
+  } else if constexpr (KIND == GK_DENSE2) {
+    rg_dense2<NR, B0, B1, false>(a, M);
+  } else if constexpr (KIND == GK_DIAG2) {
+    rg_diag2<NR, B0, B1, false>(a, M);
+  } else if constexpr (KIND == GK_FSIM) {
+    rg_fsim<NR, B0, B1, false>(a, M);
+  } else if constexpr (KIND == GK_CX) {
+    rg_cx<NR, B0, B1>(a);
+  }
+  // GK_NONE: nothing
+  __builtin_amdgcn_sched_barrier(0);
+  return En;
+}
+
+// stages S .. NST-1 of one tile (template recursion keeps every stage's bit
+// layout a compile-time constant)
+template <class P, int S>
+__device__ __forceinline__ void jit_stages(c128 *la, DOp E, const DOp *prog, cmat *MT, int t, uint64_t gbase,
+                                           gc128 *dst) {
+  if constexpr (S < P::NST) {
+    constexpr int K = P::K, R = P::R, NR = 1 << R;
+    int base = t;
+#pragma unroll
+    for (int i = 0; i < R; i++) base = ins0<int>(base, P::SRT[S][i]);
+    c128 a[NR];
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+      int o = 0;
+#pragma unroll
+      for (int i = 0; i < R; i++)
+        if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
+      a[j] = la[swz(base | o)];
+    }
+    E = P::template stage<S>(a, E, prog, MT);
+    if constexpr (S == P::NST - 1 && P::DOUT) {
+      // the last stage's lanes run over the low tile bits: store to HBM
+      uint64_t gb = gbase;
+#pragma unroll
+      for (int i = 0; i < K; i++)
+        if ((base >> i) & 1) gb |= 1ull << P::TQ[i];
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        uint64_t go = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) go |= 1ull << P::TQ[P::RBIT[S][i]];
+        stg(&dst[gb | go], a[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        int o = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
+        la[swz(base | o)] = a[j];
+      }
+      __syncthreads();
+      jit_stages<P, S + 1>(la, E, prog, MT, t, gbase, dst);
+    }
+  }
+}
+
+// the 2^R amplitudes lane t holds of tile u (input layout), read from HBM:
+// lanes run over the tile's lowest bits, so the loads are coalesced
+template <class P>
+__device__ __forceinline__ void jit_load_tile(c128 (&r)[1 << P::R], const DJob *__restrict__ jobs, int n_jobs,
+                                              int64_t u, const DOverride &ov, int t) {
+  constexpr int K = P::K, R = P::R, NR = 1 << R;
+  const DJob J = ldc(&jobs[n_jobs > 1 ? find_job(jobs, n_jobs, u) : 0]);
+  const gc128 *A = (const gc128 *)(ov.use ? ov.a : J.a);
+  uint64_t g = (uint64_t)(u - J.unit0);
+#pragma unroll
+  for (int i = 0; i < K; i++) g = ins0<uint64_t>(g, P::TQ[i]);
+#pragma unroll
+  for (int i = 0; i < K - R; i++) g |= (uint64_t)((t >> i) & 1) << P::TQ[i];
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    uint64_t oj = 0;
+#pragma unroll
+    for (int i = 0; i < R; i++)
+      if ((j >> i) & 1) oj |= 1ull << P::TQ[K - R + i];
+    r[j] = ldg(&A[g | oj]);
+  }
+}
+
+// One forward pass of pass description P over every tile of 2^K amplitudes
+// of every job, 2^(K-R) threads per block.  PERSIST = false: one block per
+// tile.  PERSIST = true: at most as many blocks as the chip holds at once,
+// block b taking tiles b, b + grid, ..., each block reading its next tile
+// from HBM into registers while the current tile's stages run.
+template <class P, bool PERSIST>
+__device__ __forceinline__ void jit_pass_fwd(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units,
+                                             const DOverride &ov) {
+  constexpr int K = P::K, R = P::R, NR = 1 << R, T = 1 << (K - R);
+  __shared__ c128 la[1 << K];
+  const int t = threadIdx.x;
+  int64_t u = blockIdx.x;
+  if (u >= total_units) return;
+  c128 pf[NR];
+  jit_load_tile<P>(pf, jobs, n_jobs, u, ov, t);
+  for (; u < total_units; u += PERSIST ? gridDim.x : total_units) {
+    const DJob J = ldc(&jobs[n_jobs > 1 ? find_job(jobs, n_jobs, u) : 0]);
+    const int64_t tile = u - J.unit0;
+    gc128 *A = (gc128 *)(ov.use ? ov.a : J.a);
+    gc128 *Bv = (gc128 *)(ov.use ? ov.b : J.b);
+    cmat *MT = (cmat *)(ov.use ? ov.mats : J.mats);
+    const DOp *prog = (const DOp *)(MT + P::PROG) + 1;
+    const int mode = ov.use ? ov.mode : J.mode;
+    gc128 *dst = mode == 1 ? Bv : A;
+    uint64_t gbase = (uint64_t)tile;
+#pragma unroll
+    for (int i = 0; i < K; i++) gbase = ins0<uint64_t>(gbase, P::TQ[i]);
+#pragma unroll
+    for (int j = 0; j < NR; j++) la[swz(j * T + t)] = pf[j];
+    __syncthreads();
+    if constexpr (PERSIST) {
+      const int64_t un = u + gridDim.x;
+      if (un < total_units) jit_load_tile<P>(pf, jobs, n_jobs, un, ov, t);
+    }
+    const DOp E = ldc(prog + P::G0);
+    jit_stages<P, 0>(la, E, prog, MT, t, gbase, dst);
+    if constexpr (!P::DOUT) {
+      // LDS -> HBM in the output layout
+      uint64_t gbo = (uint64_t)tile;
+#pragma unroll
+      for (int i = 0; i < K; i++) gbo = ins0<uint64_t>(gbo, P::TQO[i]);
+      uint64_t so = 0;
+      int sl = 0;
+#pragma unroll
+      for (int i = 0; i < K - R; i++)
+        if ((t >> i) & 1) {
+          so |= 1ull << P::TQO[i];
+          sl |= 1 << P::LBO[i];
+        }
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        uint64_t oj = 0;
+        int ol = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) {
+            oj |= 1ull << P::TQO[K - R + i];
+            ol |= 1 << P::LBO[K - R + i];
+          }
+        stg(&dst[gbo | so | oj], la[swz(sl | ol)]);
+      }
+    }
+    __syncthreads();  // the next tile overwrites la
+  }
+}
+
+}  // namespace vqc

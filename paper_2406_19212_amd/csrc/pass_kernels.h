@@ -1192,6 +1192,7 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
 }
 
 
+#ifndef __HIPCC_RTC__  // host launchers
 template <int K, int R, int MODE>
 hipError_t launch_lds_t(const DJob *jobs, int n_jobs, int64_t total, int grid, const DOverride &ov,
                         hipStream_t st) {
@@ -1229,4 +1230,5 @@ hipError_t launch_reg_t(const DJob *jobs, int n_jobs, int64_t total, int grid, c
   return hipGetLastError();
 }
 
+#endif  // __HIPCC_RTC__
 }  // namespace vqc

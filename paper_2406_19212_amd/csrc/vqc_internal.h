@@ -1,8 +1,21 @@
 // Internal tables shared by the host planner (api.cpp) and the gfx950
 // kernels (kernels.hip).  Not part of the C ABI.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#else
+// compiled at run time (hipRTC) for circuit-specialised pass kernels: the
+// fixed-width integer types are declared in a namespace there
+using __hip_internal::int8_t;
+using __hip_internal::int16_t;
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint8_t;
+using __hip_internal::uint16_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+#endif
 
 namespace vqc {
 
@@ -214,6 +227,7 @@ struct DGradJob {
 };
 
 // launchers (kernels.hip)
+#ifndef __HIPCC_RTC__  // host launchers
 hipError_t launch_pass_lds(int K, int R, bool adj, bool d4, const DJob *jobs, int n_jobs, int64_t total, int grid,
                            const DOverride &ov, hipStream_t st);
 hipError_t launch_pass_reg(int R, int mode, const DJob *jobs, int n_jobs, int64_t total, int grid,
@@ -259,4 +273,5 @@ hipError_t launch_set_mat(c128 *dst, const c128 *m, int count, hipStream_t st);
 enum SingleKind { SK_DENSE1 = 0, SK_DIAG1, SK_PHASE1, SK_DENSE2, SK_DIAG2, SK_PHASE11, SK_FSIM, SK_CX, SK_CTRL };
 constexpr int kEChunkHost = 4096;
 
+#endif  // __HIPCC_RTC__
 }  // namespace vqc
