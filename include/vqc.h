@@ -135,8 +135,8 @@ typedef struct {
  * second state buffer of the same size, two for the gradient plan, and a
  * batch one or two per item): 1 on, -1 off, 0 default (on from 12 qubits,
  * pure states; the gradient plan moves qubits up to 30 qubits).
- * jit: the forward passes of a pure-state circuit run as kernels compiled at
- * circuit creation for this circuit's op sequence (hipRTC; the fused-pass
+ * jit: the forward and adjoint passes of a pure-state circuit run as kernels
+ * compiled at circuit creation for this circuit's op sequence (hipRTC; the fused-pass
  * driver with every op's kind and register bits fixed at compile time, the
  * parameters still read from device memory, so one compile serves every
  * theta; code objects are cached on disk): 1 on (creation fails with
@@ -168,6 +168,7 @@ typedef struct {
   int n_jit_passes;   /* forward passes running as circuit-specialised kernels */
   int jit_cached;     /* 1: their code object came from the on-disk cache */
   double jit_ms;      /* compile (or cache load) and module load time */
+  int n_jit_adj_passes; /* adjoint (gradient) passes running as specialised kernels */
 } vqc_circuit_stats;
 
 /* ------------------------------------------------------------------ misc */

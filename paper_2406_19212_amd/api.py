@@ -194,7 +194,7 @@ class Circuit:
                 "grid_blocks": s.tune.grid_blocks, "remap": s.tune.remap, "alg_bytes_per_amp": s.alg_bytes_per_amp,
                 "n_adj_passes": s.n_adj_passes, "n_fwd_moves": s.n_fwd_moves, "n_adj_moves": s.n_adj_moves,
                 "jit": s.tune.jit, "n_jit_passes": s.n_jit_passes, "jit_cached": bool(s.jit_cached),
-                "jit_ms": s.jit_ms}
+                "jit_ms": s.jit_ms, "n_jit_adj_passes": s.n_jit_adj_passes}
 
     def _theta(self, theta):
         if self.n_params == 0:

@@ -72,7 +72,8 @@ class vqc_circuit_stats(ctypes.Structure):
     _fields_ = [("n_ops", c_int), ("n_elementary", c_int), ("n_passes", c_int), ("n_stages", c_int),
                 ("n_var", c_int), ("n_params", c_int), ("tune", vqc_tune),
                 ("alg_bytes_per_amp", c_double), ("n_adj_passes", c_int), ("n_fwd_moves", c_int),
-                ("n_adj_moves", c_int), ("n_jit_passes", c_int), ("jit_cached", c_int), ("jit_ms", c_double)]
+                ("n_adj_moves", c_int), ("n_jit_passes", c_int), ("jit_cached", c_int), ("jit_ms", c_double),
+                ("n_jit_adj_passes", c_int)]
 
 
 _lib = None

@@ -283,9 +283,10 @@ struct Plan {
   int n_gates = 0;
   const DGate *d_gates = nullptr;
   const DDeriv *d_derivs = nullptr;
-  // circuit-specialised kernels of the passes (forward plans of pure states);
-  // empty: the interpreting kernels run
-  std::unique_ptr<JitModule> jit;
+  // circuit-specialised kernels of the passes (pure states): kernel p of this
+  // plan is jit->fn[jit_base + p]; empty: the interpreting kernels run
+  std::shared_ptr<JitModule> jit;
+  int jit_base = 0;
 };
 
 int popc(uint64_t v) { return __builtin_popcountll(v); }
@@ -994,8 +995,7 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
 // and register bits, in program order) and the kernel vqc_jf<p>, which
 // instantiates jit_pass.h's driver for it.  The op parameters stay in the
 // item's op program, so one compiled plan serves every theta.
-std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist) {
-  std::string s = "#include \"jit_pass.h\"\nnamespace vqc {\n";
+std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::string s) {
   char buf[512];
   auto arr = [&](const char *name, const std::vector<int> &v) {
     std::string r = std::string("  static constexpr int ") + name + "[" + std::to_string(v.size()) + "] = {";
@@ -1071,7 +1071,137 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist) {
                   1 << (K - R), p, p, persist ? "true" : "false");
     s += buf;
   }
-  return s + "}  // namespace vqc\n";
+  return s;
+}
+
+// Source of the specialised adjoint passes of a pure-state LDS plan (Alg. 2):
+// description JA<p> with its stages' ops in reverse program order, each op
+// with its derivative reductions (generator form before Phi is uncomputed,
+// derivative matrices after), and the kernel vqc_ja<p>.
+std::string jit_source_adj(vqc_circuit c, const Plan &P, std::string s) {
+  char buf[512];
+  auto arr = [&](const char *name, const std::vector<int> &v) {
+    std::string r = std::string("  static constexpr int ") + name + "[" + std::to_string(std::max<size_t>(1, v.size())) +
+                    "] = {";
+    for (size_t i = 0; i < v.size(); i++) r += (i ? ", " : "") + std::to_string(v[i]);
+    if (v.empty()) r += "0";
+    return r + "};\n";
+  };
+  int g = 0;  // program index of the next op (upload_plan's order)
+  for (size_t p = 0; p < P.passes.size(); p++) {
+    const PassH &ph = P.passes[p];
+    const int K = ph.K, R = P.R, nst = (int)ph.stages.size(), T = 1 << (K - R);
+    const int WS = T < 64 ? T : 64, NW = (T + 63) / 64;
+    int loc[64];
+    for (int i = 0; i < (int)ph.lq.size(); i++) loc[ph.lq[i]] = i;
+    std::vector<int> ord(K), tqo(K), lbo(K), tq(ph.tq.begin(), ph.tq.end());
+    for (int i = 0; i < K; i++) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int x, int y) { return ph.tq_out[x] < ph.tq_out[y]; });
+    for (int i = 0; i < K; i++) {
+      lbo[i] = ord[i];
+      tqo[i] = ph.tq_out[ord[i]];
+    }
+    // derivative slots in forward order, as the uploaded tables number them
+    std::vector<int> vslot;
+    std::vector<std::vector<int>> slots;  // per op of the pass, in program order
+    int n_ops = 0;
+    for (const auto &S : ph.stages)
+      for (int ei : S.elems) {
+        slots.emplace_back();
+        for (const Deriv &dv : c->elems[ei].d) {
+          slots.back().push_back((int)vslot.size());
+          vslot.push_back(dv.gslot);
+        }
+        n_ops++;
+      }
+    const int g0 = g;
+    std::snprintf(buf, sizeof(buf),
+                  "struct JA%zu {\n  static constexpr int K = %d, R = %d, NST = %d, PROG = %d, GLAST = %d, NVAR = %d;\n"
+                  "  static constexpr int WS = %d, NW = %d;\n"
+                  "  static constexpr bool DIN = %s, DOUT = %s;\n",
+                  p, K, R, nst, P.prog, g0 + n_ops - 1, (int)vslot.size(), WS, NW,
+                  (ph.lowfree & 2) ? "true" : "false", (ph.lowfree & 1) ? "true" : "false");
+    s += buf;
+    s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("VSLOT", vslot);
+    const int rows = std::max(nst, 1);
+    std::string rb = "  static constexpr int RBIT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
+    std::string sr = "  static constexpr int SRT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
+    if (nst == 0) {
+      rb += "{0}";
+      sr += "{0}";
+    }
+    for (int si = 0; si < nst; si++) {
+      int srt[4];
+      for (int i = 0; i < R; i++) srt[i] = ph.stages[si].rbit[i];
+      std::sort(srt, srt + R);
+      rb += si ? ", {" : "{";
+      sr += si ? ", {" : "{";
+      for (int i = 0; i < R; i++) {
+        rb += (i ? ", " : "") + std::to_string(ph.stages[si].rbit[i]);
+        sr += (i ? ", " : "") + std::to_string(srt[i]);
+      }
+      rb += "}";
+      sr += "}";
+    }
+    s += rb + "};\n" + sr + "};\n";
+    std::snprintf(buf, sizeof(buf),
+                  "  template <int S>\n  __device__ static __forceinline__ DOp astage(c128 (&a)[%d], c128 (&b)[%d], "
+                  "DOp E, const DOp *prog, cmat *M, double (*red)[%d], int lane, int wave) {\n",
+                  1 << R, 1 << R, NW);
+    s += buf;
+    int k = 0;  // op of the pass in program order
+    std::vector<int> first_k(nst + 1, 0);
+    for (int si = 0; si < nst; si++) first_k[si + 1] = first_k[si] + (int)ph.stages[si].elems.size();
+    for (int si = 0; si < nst; si++) {
+      const PassH::Stage &S = ph.stages[si];
+      int regpos[64];
+      for (int i = 0; i < R; i++) regpos[S.rbit[i]] = i;
+      s += si ? "    else if constexpr (S == " : "    if constexpr (S == ";
+      s += std::to_string(si) + ") {\n";
+      for (int q = (int)S.elems.size() - 1; q >= 0; q--) {
+        const Elem &e = c->elems[S.elems[q]];
+        k = first_k[si] + q;
+        const int gi = g0 + k;
+        const int b0 = e.nq > 0 ? regpos[loc[e.q[0]]] : 0, b1 = e.nq > 1 ? regpos[loc[e.q[1]]] : 0;
+        const bool gen = !e.d.empty() && e.d[0].kind >= GK_GENX && e.d[0].kind <= GK_GENZ;
+        std::snprintf(buf, sizeof(buf),
+                      "      {\n        lgkm_wait();\n        const DOp En = ldc(prog + %d);\n"
+                      "        __builtin_amdgcn_sched_barrier(0);\n",
+                      gi - 1);
+        s += buf;
+        if (gen) {
+          std::snprintf(buf, sizeof(buf),
+                        "        jred<WS, NW>(red, %d, jgrad<R, %d, %d, 0>(a, b, M), lane, wave);\n", slots[k][0],
+                        (int)e.d[0].kind, b0);
+          s += buf;
+        }
+        std::snprintf(buf, sizeof(buf), "        japply<R, true, %d, %d, %d>(a, E, M);\n", e.kind, b0, b1);
+        s += buf;
+        if (!gen)
+          for (size_t d = 0; d < e.d.size(); d++) {
+            std::snprintf(buf, sizeof(buf),
+                          "        jred<WS, NW>(red, %d, jgrad<R, %d, %d, %d>(a, b, M + %d), lane, wave);\n",
+                          slots[k][d], (int)e.d[d].kind, b0, b1, e.d[d].mat);
+            s += buf;
+          }
+        std::snprintf(buf, sizeof(buf),
+                      "        japply<R, true, %d, %d, %d>(b, E, M);\n        E = En;\n"
+                      "        __builtin_amdgcn_sched_barrier(0);\n      }\n",
+                      e.kind, b0, b1);
+        s += buf;
+      }
+      s += "      return E;\n    }\n";
+    }
+    s += nst ? "    else return E;\n  }\n};\n" : "    return E;\n  }\n};\n";
+    g = g0 + n_ops;
+    std::snprintf(buf, sizeof(buf),
+                  "extern \"C\" __global__ void __launch_bounds__(%d) vqc_ja%zu(const DJob *__restrict__ jobs, "
+                  "int n_jobs, int64_t total_units, DOverride ov) {\n  jit_pass_adj<JA%zu>(jobs, n_jobs, total_units, "
+                  "ov);\n}\n",
+                  T, p, p);
+    s += buf;
+  }
+  return s;
 }
 
 // whether a pure-state circuit asks for circuit-specialised forward passes
@@ -1093,42 +1223,63 @@ bool jit_wanted(vqc_circuit c) {
   return jit_default_on(c);
 }
 
-// compile (or load from the cache) the forward plan's specialised passes;
-// a failure leaves the interpreting kernels in charge unless the caller
-// asked for these kernels (vqc_tune.jit = 1)
+bool jit_plan_ok(const Plan &P) { return !P.reg_only && !P.d4 && !P.passes.empty() && P.K <= 11; }
+
+// compile (or load from the cache) the specialised forward and adjoint passes
+// of a pure-state circuit, one module for both plans; a failure leaves the
+// interpreting kernels in charge unless the caller asked for these kernels
+// (vqc_tune.jit = 1)
 vqc_status jit_prepare(vqc_circuit c) {
-  Plan &P = c->fwd;
-  P.jit.reset();
+  c->fwd.jit.reset();
+  c->adj.jit.reset();
   c->jit_ms = 0;
   if (!jit_wanted(c)) return VQC_OK;
-  std::vector<std::string> names;
-  for (size_t p = 0; p < P.passes.size(); p++) names.push_back("vqc_jf" + std::to_string(p));
-  std::unique_ptr<JitModule> m(new (std::nothrow) JitModule());
-  if (!m) return VQC_ERR_OOM;
-  std::string log;
-  std::vector<int> threads;
-  for (const PassH &ph : P.passes) threads.push_back(1 << (ph.K - P.R));
   // persistent grids when the caller asked for a grid size (vqc_tune.grid_blocks)
   const bool persist = c->tune.grid_blocks > 0;
-  const std::string src = jit_source_fwd(c, P, persist);
+  const bool adj = jit_plan_ok(c->adj) && c->adj.K <= 10 + (c->adj.R == 3 ? 1 : 0);
+  std::vector<std::string> names;
+  std::vector<int> threads;
+  std::string src = "#include \"jit_pass.h\"\nnamespace vqc {\n";
+  src = jit_source_fwd(c, c->fwd, persist, src);
+  for (size_t p = 0; p < c->fwd.passes.size(); p++) {
+    names.push_back("vqc_jf" + std::to_string(p));
+    threads.push_back(1 << (c->fwd.passes[p].K - c->fwd.R));
+  }
+  if (adj) {
+    src = jit_source_adj(c, c->adj, src);
+    for (size_t p = 0; p < c->adj.passes.size(); p++) {
+      names.push_back("vqc_ja" + std::to_string(p));
+      threads.push_back(1 << (c->adj.passes[p].K - c->adj.R));
+    }
+  }
+  src += "}  // namespace vqc\n";
   if (const char *dump = std::getenv("VQC_JIT_DUMP")) {  // keep the generated source for inspection
     if (FILE *f = std::fopen((std::string(dump) + "/vqc_jit_" + std::to_string(c->n) + ".hip").c_str(), "w")) {
       std::fputs(src.c_str(), f);
       std::fclose(f);
     }
   }
+  std::shared_ptr<JitModule> m(new (std::nothrow) JitModule());
+  if (!m) return VQC_ERR_OOM;
+  std::string log;
   const hipError_t e = jit_build(src, names, threads, *m, &log);
   if (e != hipSuccess) {
     if (std::getenv("VQC_JIT_VERBOSE")) std::fprintf(stderr, "vqc: run-time compile failed:\n%s\n", log.c_str());
     return c->tune.jit > 0 ? VQC_ERR_HIP : VQC_OK;
   }
-  if (persist)
-    for (int &r : m->resident) r = std::min(r, c->tune.grid_blocks);
-  else
-    for (int &r : m->resident) r = 0x7fffffff;  // one block per tile
+  const size_t nf = c->fwd.passes.size();
+  for (size_t k = 0; k < m->resident.size(); k++) {
+    if (k < nf && persist) m->resident[k] = std::min(m->resident[k], c->tune.grid_blocks);
+    else m->resident[k] = 0x7fffffff;  // one block per tile
+  }
   c->jit_ms = m->ms;
   c->jit_cached = m->cached;
-  P.jit = std::move(m);
+  c->fwd.jit = m;
+  c->fwd.jit_base = 0;
+  if (adj) {
+    c->adj.jit = m;
+    c->adj.jit_base = (int)nf;
+  }
   return VQC_OK;
 }
 
@@ -1326,11 +1477,12 @@ hipError_t build_mats(vqc_circuit c, const double *const *thetas, c128 *const *m
 hipError_t launch_jit_pass(const JitModule &m, size_t p, const Plan &P, const DJob *jobs, int n_jobs, int64_t total,
                            const DOverride &ov, hipStream_t st) {
   if (total <= 0) return hipSuccess;
-  if (p >= m.fn.size() || p >= m.resident.size()) return hipErrorInvalidValue;
-  const int64_t grid = std::min<int64_t>(total, m.resident[p]);
+  const size_t k = P.jit_base + p;
+  if (p >= P.passes.size() || k >= m.fn.size() || k >= m.resident.size()) return hipErrorInvalidValue;
+  const int64_t grid = std::min<int64_t>(total, m.resident[k]);
   DOverride o = ov;
   void *args[] = {&jobs, &n_jobs, &total, &o};
-  return hipModuleLaunchKernel(m.fn[p], (unsigned)grid, 1, 1, 1u << (P.passes[p].K - P.R), 1, 1, 0, st, args,
+  return hipModuleLaunchKernel(m.fn[k], (unsigned)grid, 1, 1, 1u << (P.passes[p].K - P.R), 1, 1, 0, st, args,
                                nullptr);
 }
 
@@ -1371,7 +1523,7 @@ hipError_t run_passes(vqc_circuit c, Plan &P, int mode, c128 *a, c128 *b, const 
       ov.mode = ph.src != ph.dst ? 1 : 0;
     }
     hipError_t e;
-    if (mode == 0 && P.jit) e = launch_jit_pass(*P.jit, p, P, P.d_jobs1 + p, 1, P.units_per_item, ov, st);
+    if ((mode == 0 || mode == 1) && P.jit) e = launch_jit_pass(*P.jit, p, P, P.d_jobs1 + p, 1, P.units_per_item, ov, st);
     else if (P.reg_only) e = launch_pass_reg(P.R, mode, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
     else e = launch_pass_lds(P.K, P.R, mode != 0, P.d4, P.d_jobs1 + p, 1, P.units_per_item, grid, ov, st);
     if (e != hipSuccess) return e;
@@ -2223,7 +2375,8 @@ vqc_status vqc_circuit_stats_get(vqc_circuit c, vqc_circuit_stats *out) {
   out->n_adj_passes = (int)c->adj.passes.size();
   for (const PassH &ph : c->fwd.passes) out->n_fwd_moves += ph.moves;
   for (const PassH &ph : c->adj.passes) out->n_adj_moves += ph.moves;
-  out->n_jit_passes = c->fwd.jit ? (int)c->fwd.jit->fn.size() : 0;
+  out->n_jit_passes = c->fwd.jit ? (int)c->fwd.passes.size() : 0;
+  out->n_jit_adj_passes = c->adj.jit ? (int)c->adj.passes.size() : 0;
   out->jit_ms = c->jit_ms;
   out->jit_cached = c->jit_cached ? 1 : 0;
   return VQC_OK;
@@ -2762,12 +2915,18 @@ static vqc_status batch_backward_pure_on(vqc_batch b, double *energies, hipStrea
   DOverride ov;
   std::memset(&ov, 0, sizeof(ov));
   vqc_circuit c0 = b->circ[0];
+  bool same = true;  // every item runs the same circuit: step r is its pass PA - 1 - r
+  for (int i = 1; i < b->B; i++) same = same && b->circ[i] == c0;
   for (int r = 0; r < b->max_adj; r++) {
     if (b->adj_count[r] == 0) continue;
     const int64_t units = b->adj_units[r];
     const int grid = grid_of(c0, units);
     const DJob *jobs = b->d_adj_jobs + b->adj_first[r];
-    VQC_TRY(launch_pass_lds(c0->adj.K, c0->adj.R, true, false, jobs, b->adj_count[r], units, grid, ov, st));
+    const int PA = (int)c0->adj.passes.size();
+    if (same && c0->adj.jit && r < PA)
+      VQC_TRY(launch_jit_pass(*c0->adj.jit, PA - 1 - r, c0->adj, jobs, b->adj_count[r], units, ov, st));
+    else
+      VQC_TRY(launch_pass_lds(c0->adj.K, c0->adj.R, true, false, jobs, b->adj_count[r], units, grid, ov, st));
   }
   VQC_TRY(launch_grad_reduce(b->d_gjobs, b->B, b->max_params, st));
   return VQC_OK;

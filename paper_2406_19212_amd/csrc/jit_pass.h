@@ -32,19 +32,11 @@
 
 namespace vqc {
 
-// One op of kind KIND on register bits B0 (and B1).  E is its program entry,
-// loaded by the previous op; the entry at `next` is loaded here, after the
-// wait for E and before E's arithmetic, so its scalar load overlaps this op.
-// The scheduling barriers keep the compiler from hoisting every op's load to
-// the top of the pass (which would need far more scalar registers than there
-// are) and from starting the next load before the wait (scalar loads return
-// out of order, so a wait is a wait for all of them).
-template <int R, int KIND, int B0, int B1>
-__device__ __forceinline__ DOp jop(c128 (&a)[1 << R], const DOp &E, const DOp *next, cmat *mats) {
+// op of kind KIND on register bits B0 (and B1) from its program entry E, or
+// its adjoint (ADJ)
+template <int R, bool ADJ, int KIND, int B0, int B1>
+__device__ __forceinline__ void japply(c128 (&a)[1 << R], const DOp &E, cmat *mats) {
   constexpr int NR = 1 << R;
-  lgkm_wait();
-  const DOp En = ldc(next);
-  __builtin_amdgcn_sched_barrier(0);
   SRec r;
   r.neg = E.neg;
   r.pad = 0;
@@ -53,51 +45,66 @@ __device__ __forceinline__ DOp jop(c128 (&a)[1 << R], const DOp &E, const DOp *n
   cmat *M = mats + E.g.mat;
   const uint32_t n = E.neg;
   if constexpr (KIND == GK_SXR1) {
-    if (n & 1) rg_sxr1<NR, B0, false, true>(a, r); else rg_sxr1<NR, B0, false, false>(a, r);
+    if (n & 1) rg_sxr1<NR, B0, ADJ, true>(a, r); else rg_sxr1<NR, B0, ADJ, false>(a, r);
   } else if constexpr (KIND == GK_SRR1) {
-    if (n & 1) rg_srr1<NR, B0, false, true>(a, r); else rg_srr1<NR, B0, false, false>(a, r);
+    if (n & 1) rg_srr1<NR, B0, ADJ, true>(a, r); else rg_srr1<NR, B0, ADJ, false>(a, r);
   } else if constexpr (KIND == GK_SPH1) {
-    if (n & 1) rg_sph1<NR, B0, false, true>(a, r); else rg_sph1<NR, B0, false, false>(a, r);
+    if (n & 1) rg_sph1<NR, B0, ADJ, true>(a, r); else rg_sph1<NR, B0, ADJ, false>(a, r);
   } else if constexpr (KIND == GK_SDG1) {
     switch (n & 3) {
-      case 0: rg_sdg1<NR, B0, false, false, false>(a, r); break;
-      case 1: rg_sdg1<NR, B0, false, true, false>(a, r); break;
-      case 2: rg_sdg1<NR, B0, false, false, true>(a, r); break;
-      default: rg_sdg1<NR, B0, false, true, true>(a, r); break;
+      case 0: rg_sdg1<NR, B0, ADJ, false, false>(a, r); break;
+      case 1: rg_sdg1<NR, B0, ADJ, true, false>(a, r); break;
+      case 2: rg_sdg1<NR, B0, ADJ, false, true>(a, r); break;
+      default: rg_sdg1<NR, B0, ADJ, true, true>(a, r); break;
     }
   } else if constexpr (KIND == GK_SRD1) {
-    if (n & 2) rg_srd1<NR, B0, false, true>(a, r); else rg_srd1<NR, B0, false, false>(a, r);
+    if (n & 2) rg_srd1<NR, B0, ADJ, true>(a, r); else rg_srd1<NR, B0, ADJ, false>(a, r);
   } else if constexpr (KIND == GK_SFX) {
     switch (n & 3) {
-      case 0: rg_sfx<NR, B0, B1, false, false, false>(a, r); break;
-      case 1: rg_sfx<NR, B0, B1, false, true, false>(a, r); break;
-      case 2: rg_sfx<NR, B0, B1, false, false, true>(a, r); break;
-      default: rg_sfx<NR, B0, B1, false, true, true>(a, r); break;
+      case 0: rg_sfx<NR, B0, B1, ADJ, false, false>(a, r); break;
+      case 1: rg_sfx<NR, B0, B1, ADJ, true, false>(a, r); break;
+      case 2: rg_sfx<NR, B0, B1, ADJ, false, true>(a, r); break;
+      default: rg_sfx<NR, B0, B1, ADJ, true, true>(a, r); break;
     }
   } else if constexpr (KIND == GK_DENSE1) {
-    rg_dense1<NR, B0, false>(a, M);
+    rg_dense1<NR, B0, ADJ>(a, M);
   } else if constexpr (KIND == GK_DIAG1) {
-    rg_diag1<NR, B0, false>(a, M);
+    rg_diag1<NR, B0, ADJ>(a, M);
   } else if constexpr (KIND == GK_XROT1) {
-    rg_xrot1<NR, B0, false>(a, M);
+    rg_xrot1<NR, B0, ADJ>(a, M);
   } else if constexpr (KIND == GK_REAL1) {
-    rg_real1<NR, B0, false>(a, M);
+    rg_real1<NR, B0, ADJ>(a, M);
   } else if constexpr (KIND == GK_RDIAG1) {
-    rg_rdiag1<NR, B0, false>(a, M);
+    rg_rdiag1<NR, B0, ADJ>(a, M);
   } else if constexpr (KIND == GK_PHASE1) {
-    rg_phase1<NR, B0, false>(a, M);
+    rg_phase1<NR, B0, ADJ>(a, M);
   } else if constexpr (KIND == GK_FSIMX) {
-    rg_fsimx<NR, B0, B1, false>(a, M);
+    rg_fsimx<NR, B0, B1, ADJ>(a, M);
   } else if constexpr (KIND == GK_DENSE2) {
-    rg_dense2<NR, B0, B1, false>(a, M);
+    rg_dense2<NR, B0, B1, ADJ>(a, M);
   } else if constexpr (KIND == GK_DIAG2) {
-    rg_diag2<NR, B0, B1, false>(a, M);
+    rg_diag2<NR, B0, B1, ADJ>(a, M);
   } else if constexpr (KIND == GK_FSIM) {
-    rg_fsim<NR, B0, B1, false>(a, M);
+    rg_fsim<NR, B0, B1, ADJ>(a, M);
   } else if constexpr (KIND == GK_CX) {
     rg_cx<NR, B0, B1>(a);
   }
   // GK_NONE: nothing
+}
+
+// One op of the forward pass; E is its program entry, loaded by the previous
+// op.  The entry at `next` is loaded here, after the wait for E and before
+// E's arithmetic, so its scalar load overlaps this op.  The scheduling
+// barriers keep the compiler from hoisting every op's load to the top of the
+// pass (which would need far more scalar registers than there are) and from
+// starting the next load before the wait (scalar loads return out of order,
+// so a wait is a wait for all of them).
+template <int R, int KIND, int B0, int B1>
+__device__ __forceinline__ DOp jop(c128 (&a)[1 << R], const DOp &E, const DOp *next, cmat *mats) {
+  lgkm_wait();
+  const DOp En = ldc(next);
+  __builtin_amdgcn_sched_barrier(0);
+  japply<R, false, KIND, B0, B1>(a, E, mats);
   __builtin_amdgcn_sched_barrier(0);
   return En;
 }
@@ -237,6 +244,186 @@ __device__ __forceinline__ void jit_pass_fwd(const DJob *__restrict__ jobs, int 
       }
     }
     __syncthreads();  // the next tile overwrites la
+  }
+}
+
+// ------------------------------------------------------------ adjoint pass
+// Alg. 2 for one pass, as k_pass_lds<K,R,1> does it: the pass's ops in
+// reverse, Phi <- Q^dagger Phi and Psi <- Q^dagger Psi, and for every
+// parameter of an op the partial inner product Re<Psi| dQ |Phi> of the tile,
+// summed over a wave and written to the pass's reduction slot.  The pass
+// description P adds
+//   NVAR, VSLOT[NVAR]      the pass's derivative slots and their rows in the
+//                          partials array
+//   DIN                    the first stage (in reverse order) holds none of the
+//                          low bits: it reads HBM directly (DOUT likewise for
+//                          the last one)
+//   template <int S> static DOp astage(a, b, E, prog, M, red, lane, wave)
+//                          stage S's ops in reverse (calls of the helpers below)
+
+// wave sum of a tile's partial, stored by lane 0 into the reduction slot
+template <int WS, int NW>
+__device__ __forceinline__ void jred(double (*red)[NW], int slot, double v, int lane, int wave) {
+  v = wave_sum<WS>(v);
+  if (lane == 0) red[slot][wave] = v;
+}
+
+// Re<b| D |a> over the lane's groups for a derivative matrix D of kind DK
+template <int R, int DK, int B0, int B1>
+__device__ __forceinline__ double jgrad(const c128 (&a)[1 << R], const c128 (&b)[1 << R], cmat *D) {
+  constexpr int NR = 1 << R;
+  if constexpr (DK == GK_DENSE1) return gr_dense1<NR, B0>(a, b, D);
+  else if constexpr (DK == GK_DIAG1) return gr_diag1<NR, B0>(a, b, D);
+  else if constexpr (DK == GK_DENSE2) return gr_dense2<NR, B0, B1>(a, b, D);
+  else if constexpr (DK == GK_GENX || DK == GK_GENY || DK == GK_GENZ) return gr_gen<NR, B0, DK>(a, b);
+  else return 0.0;
+}
+
+template <class P, int S, int NW>
+__device__ __forceinline__ void jit_astages(c128 *la, c128 *lb, DOp E, const DOp *prog, cmat *MT, int t,
+                                            uint64_t gbase, const gc128 *src, const gc128 *srcb, gc128 *dst,
+                                            gc128 *dstb, double (*red)[NW]) {
+  if constexpr (S >= 0) {
+    constexpr int K = P::K, R = P::R, NR = 1 << R;
+    const int lane = t & 63, wave = t >> 6;
+    int base = t;
+#pragma unroll
+    for (int i = 0; i < R; i++) base = ins0<int>(base, P::SRT[S][i]);
+    uint64_t gb = gbase;
+#pragma unroll
+    for (int i = 0; i < K; i++)
+      if ((base >> i) & 1) gb |= 1ull << P::TQ[i];
+    c128 a[NR], b[NR];
+    if constexpr (S == P::NST - 1 && P::DIN) {
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        uint64_t go = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) go |= 1ull << P::TQ[P::RBIT[S][i]];
+        a[j] = ldg(&src[gb | go]);
+        b[j] = ldg(&srcb[gb | go]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        int o = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
+        a[j] = la[swz(base | o)];
+        b[j] = lb[swz(base | o)];
+      }
+    }
+    E = P::template astage<S>(a, b, E, prog, MT, red, lane, wave);
+    if constexpr (S == 0 && P::DOUT) {
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        uint64_t go = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) go |= 1ull << P::TQ[P::RBIT[S][i]];
+        stg(&dst[gb | go], a[j]);
+        stg(&dstb[gb | go], b[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        int o = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
+        la[swz(base | o)] = a[j];
+        lb[swz(base | o)] = b[j];
+      }
+      __syncthreads();
+      jit_astages<P, S - 1, NW>(la, lb, E, prog, MT, t, gbase, src, srcb, dst, dstb, red);
+    }
+  }
+}
+
+// One adjoint pass of description P: a block per tile (Phi and Psi tiles in
+// LDS), the per-tile partial of each derivative slot written to the item's
+// partials array (summed over tiles afterwards in a fixed order).
+template <class P>
+__device__ __forceinline__ void jit_pass_adj(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units,
+                                             const DOverride &ov) {
+  constexpr int K = P::K, R = P::R, NR = 1 << R, T = 1 << (K - R);
+  constexpr int NW = (T + 63) / 64;
+  __shared__ c128 la[1 << K];
+  __shared__ c128 lb[1 << K];
+  __shared__ double red[P::NVAR > 0 ? P::NVAR : 1][NW];
+  const int t = threadIdx.x;
+  const int64_t u = blockIdx.x;
+  if (u >= total_units) return;
+  const DJob J = ldc(&jobs[n_jobs > 1 ? find_job(jobs, n_jobs, u) : 0]);
+  const int64_t tile = u - J.unit0;
+  const gc128 *src = (const gc128 *)(ov.use ? ov.a : J.a);
+  const gc128 *srcb = (const gc128 *)(ov.use ? ov.b : J.b);
+  gc128 *dst = (gc128 *)(ov.use ? ov.a : J.a);
+  gc128 *dstb = (gc128 *)(ov.use ? ov.b : J.b);
+  if ((ov.use ? ov.mode : J.mode) == 1) {
+    dst = (gc128 *)(ov.use ? ov.a2 : J.a2);
+    dstb = (gc128 *)(ov.use ? ov.b2 : J.b2);
+  }
+  cmat *MT = (cmat *)(ov.use ? ov.mats : J.mats);
+  const DOp *prog = (const DOp *)(MT + P::PROG) + 1;
+  double *PT = ov.use ? ov.partials : J.partials;
+  uint64_t gbase = (uint64_t)tile;
+#pragma unroll
+  for (int i = 0; i < K; i++) gbase = ins0<uint64_t>(gbase, P::TQ[i]);
+  const DOp E = ldc(prog + P::GLAST);  // the pass's last op runs first
+  if constexpr (!P::DIN) {
+    uint64_t st = 0;
+#pragma unroll
+    for (int i = 0; i < K - R; i++) st |= (uint64_t)((t >> i) & 1) << P::TQ[i];
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+      uint64_t oj = 0;
+#pragma unroll
+      for (int i = 0; i < R; i++)
+        if ((j >> i) & 1) oj |= 1ull << P::TQ[K - R + i];
+      la[swz(j * T + t)] = ldg(&src[gbase | st | oj]);
+      lb[swz(j * T + t)] = ldg(&srcb[gbase | st | oj]);
+    }
+    __syncthreads();
+  }
+  jit_astages<P, P::NST - 1, NW>(la, lb, E, prog, MT, t, gbase, src, srcb, dst, dstb, red);
+  if constexpr (!P::DOUT) {
+    uint64_t gbo = (uint64_t)tile;
+#pragma unroll
+    for (int i = 0; i < K; i++) gbo = ins0<uint64_t>(gbo, P::TQO[i]);
+    uint64_t so = 0;
+    int sl = 0;
+#pragma unroll
+    for (int i = 0; i < K - R; i++)
+      if ((t >> i) & 1) {
+        so |= 1ull << P::TQO[i];
+        sl |= 1 << P::LBO[i];
+      }
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+      uint64_t oj = 0;
+      int ol = 0;
+#pragma unroll
+      for (int i = 0; i < R; i++)
+        if ((j >> i) & 1) {
+          oj |= 1ull << P::TQO[K - R + i];
+          ol |= 1 << P::LBO[K - R + i];
+        }
+      stg(&dst[gbo | so | oj], la[swz(sl | ol)]);
+      stg(&dstb[gbo | so | oj], lb[swz(sl | ol)]);
+    }
+  } else {
+    __syncthreads();  // every wave's reduction entries are written
+  }
+  if constexpr (P::NVAR > 0) {
+    for (int v = t; v < P::NVAR; v += T) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; w++) sum += red[v][w];
+      PT[(int64_t)P::VSLOT[v] * J.n_units + tile] = sum;
+    }
   }
 }
 

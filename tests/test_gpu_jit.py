@@ -1,5 +1,5 @@
-"""Circuit-specialised forward passes (compiled at run time for the circuit's
-op sequence) against the oracle: every gate kind fused in one circuit, the
+"""Circuit-specialised forward and adjoint passes (compiled at run time for
+the circuit's op sequence) against the oracle: every gate kind fused in one circuit, the
 rotation kinds at edge angles, qubit moves between passes, both register
 widths, a persistent grid, batched items of one circuit, and the on-disk code
 cache.  Every case asks for the specialised kernels (vqc_tune.jit = 1), so a
@@ -31,6 +31,7 @@ def _jit_circuit(n, ops, **tune):
     c = Circuit(n, ops, n_params=W.count_params(ops), tune=tune)
     s = c.stats()
     assert s["n_jit_passes"] == s["n_passes"] > 0, s
+    assert s["n_jit_adj_passes"] == s["n_adj_passes"] > 0, s
     return c
 
 
@@ -51,7 +52,7 @@ def test_every_kind_specialised(n, n_sqrt, tile, reg, remap):
     si = State(n, init=psi0)
     ci.apply(si, tht)
     assert maxdiff(st.numpy(), si.numpy()) < AMP_TOL
-    # the gradient (specialised forward, interpreted adjoint)
+    # the gradient (specialised adjoint passes, Alg. 2)
     st = State(n)
     c.apply(st, tht)
     terms = W.heisenberg_1d(n, 0.3, 1.0)
