@@ -1078,7 +1078,7 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
 // description JA<p> with its stages' ops in reverse program order, each op
 // with its derivative reductions (generator form before Phi is uncomputed,
 // derivative matrices after), and the kernel vqc_ja<p>.
-std::string jit_source_adj(vqc_circuit c, const Plan &P, std::string s) {
+std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::string s) {
   char buf[512];
   auto arr = [&](const char *name, const std::vector<int> &v) {
     std::string r = std::string("  static constexpr int ") + name + "[" + std::to_string(std::max<size_t>(1, v.size())) +
@@ -1196,9 +1196,9 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, std::string s) {
     g = g0 + n_ops;
     std::snprintf(buf, sizeof(buf),
                   "extern \"C\" __global__ void __launch_bounds__(%d) vqc_ja%zu(const DJob *__restrict__ jobs, "
-                  "int n_jobs, int64_t total_units, DOverride ov) {\n  jit_pass_adj<JA%zu>(jobs, n_jobs, total_units, "
-                  "ov);\n}\n",
-                  T, p, p);
+                  "int n_jobs, int64_t total_units, DOverride ov) {\n  jit_pass_adj<JA%zu, %s>(jobs, n_jobs, "
+                  "total_units, ov);\n}\n",
+                  T, p, p, shared ? "true" : "false");
     s += buf;
   }
   return s;
@@ -1246,7 +1246,9 @@ vqc_status jit_prepare(vqc_circuit c) {
     threads.push_back(1 << (c->fwd.passes[p].K - c->fwd.R));
   }
   if (adj) {
-    src = jit_source_adj(c, c->adj, src);
+    // Phi and Psi share one LDS tile (set VQC_JIT_ADJ_SHARED=0 for one each)
+    const char *sh = std::getenv("VQC_JIT_ADJ_SHARED");
+    src = jit_source_adj(c, c->adj, !(sh && sh[0] == '0'), src);
     for (size_t p = 0; p < c->adj.passes.size(); p++) {
       names.push_back("vqc_ja" + std::to_string(p));
       threads.push_back(1 << (c->adj.passes[p].K - c->adj.R));

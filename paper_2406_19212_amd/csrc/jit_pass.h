@@ -279,44 +279,88 @@ __device__ __forceinline__ double jgrad(const c128 (&a)[1 << R], const c128 (&b)
   else return 0.0;
 }
 
-template <class P, int S, int NW>
-__device__ __forceinline__ void jit_astages(c128 *la, c128 *lb, DOp E, const DOp *prog, cmat *MT, int t,
-                                            uint64_t gbase, const gc128 *src, const gc128 *srcb, gc128 *dst,
-                                            gc128 *dstb, double (*red)[NW]) {
+// LDS index of register j of stage S for lane base `base`
+template <class P, int S>
+__device__ __forceinline__ int jslot(int base, int j) {
+  int o = 0;
+#pragma unroll
+  for (int i = 0; i < P::R; i++)
+    if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
+  return swz(base | o);
+}
+
+template <class P, int S>
+__device__ __forceinline__ int jbase(int t) {
+  int base = t;
+#pragma unroll
+  for (int i = 0; i < P::R; i++) base = ins0<int>(base, P::SRT[S][i]);
+  return base;
+}
+
+// a tile (in LDS) to HBM in the pass's output layout
+template <class P>
+__device__ __forceinline__ void jit_store_out(const c128 *lx, gc128 *dst, int64_t tile, int t) {
+  constexpr int K = P::K, R = P::R, NR = 1 << R;
+  uint64_t gbo = (uint64_t)tile;
+#pragma unroll
+  for (int i = 0; i < K; i++) gbo = ins0<uint64_t>(gbo, P::TQO[i]);
+  uint64_t so = 0;
+  int sl = 0;
+#pragma unroll
+  for (int i = 0; i < K - R; i++)
+    if ((t >> i) & 1) {
+      so |= 1ull << P::TQO[i];
+      sl |= 1 << P::LBO[i];
+    }
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    uint64_t oj = 0;
+    int ol = 0;
+#pragma unroll
+    for (int i = 0; i < R; i++)
+      if ((j >> i) & 1) {
+        oj |= 1ull << P::TQO[K - R + i];
+        ol |= 1 << P::LBO[K - R + i];
+      }
+    stg(&dst[gbo | so | oj], lx[swz(sl | ol)]);
+  }
+}
+
+// a tile from HBM (input layout, lanes over the low tile bits) into LDS
+template <class P>
+__device__ __forceinline__ void jit_load_in(c128 *lx, const gc128 *src, uint64_t gbase, int t) {
+  constexpr int K = P::K, R = P::R, NR = 1 << R, T = 1 << (K - R);
+  uint64_t st = 0;
+#pragma unroll
+  for (int i = 0; i < K - R; i++) st |= (uint64_t)((t >> i) & 1) << P::TQ[i];
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    uint64_t oj = 0;
+#pragma unroll
+    for (int i = 0; i < R; i++)
+      if ((j >> i) & 1) oj |= 1ull << P::TQ[K - R + i];
+    lx[swz(j * T + t)] = ldg(&src[gbase | st | oj]);
+  }
+}
+
+// Stages S .. 0 (reverse order) of one tile; a and b hold stage S's registers
+// on entry.  SH: Phi and Psi share one LDS tile, exchanged one after the
+// other (half the LDS of two tiles, so twice the resident blocks, for two
+// more barriers per stage change).
+template <class P, int S, int NW, bool SH>
+__device__ __forceinline__ void jit_astages(c128 *la, c128 *lb, c128 (&a)[1 << P::R], c128 (&b)[1 << P::R], DOp E,
+                                            const DOp *prog, cmat *MT, int t, uint64_t gbase, int64_t tile,
+                                            gc128 *dst, gc128 *dstb, double (*red)[NW]) {
   if constexpr (S >= 0) {
     constexpr int K = P::K, R = P::R, NR = 1 << R;
     const int lane = t & 63, wave = t >> 6;
-    int base = t;
-#pragma unroll
-    for (int i = 0; i < R; i++) base = ins0<int>(base, P::SRT[S][i]);
-    uint64_t gb = gbase;
-#pragma unroll
-    for (int i = 0; i < K; i++)
-      if ((base >> i) & 1) gb |= 1ull << P::TQ[i];
-    c128 a[NR], b[NR];
-    if constexpr (S == P::NST - 1 && P::DIN) {
-#pragma unroll
-      for (int j = 0; j < NR; j++) {
-        uint64_t go = 0;
-#pragma unroll
-        for (int i = 0; i < R; i++)
-          if ((j >> i) & 1) go |= 1ull << P::TQ[P::RBIT[S][i]];
-        a[j] = ldg(&src[gb | go]);
-        b[j] = ldg(&srcb[gb | go]);
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < NR; j++) {
-        int o = 0;
-#pragma unroll
-        for (int i = 0; i < R; i++)
-          if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
-        a[j] = la[swz(base | o)];
-        b[j] = lb[swz(base | o)];
-      }
-    }
+    const int base = jbase<P, S>(t);
     E = P::template astage<S>(a, b, E, prog, MT, red, lane, wave);
     if constexpr (S == 0 && P::DOUT) {
+      uint64_t gb = gbase;
+#pragma unroll
+      for (int i = 0; i < K; i++)
+        if ((base >> i) & 1) gb |= 1ull << P::TQ[i];
 #pragma unroll
       for (int j = 0; j < NR; j++) {
         uint64_t go = 0;
@@ -326,32 +370,62 @@ __device__ __forceinline__ void jit_astages(c128 *la, c128 *lb, DOp E, const DOp
         stg(&dst[gb | go], a[j]);
         stg(&dstb[gb | go], b[j]);
       }
-    } else {
+      __syncthreads();  // every wave's reduction entries are written
+    } else if constexpr (S == 0) {
 #pragma unroll
-      for (int j = 0; j < NR; j++) {
-        int o = 0;
+      for (int j = 0; j < NR; j++) la[jslot<P, S>(base, j)] = a[j];
+      if constexpr (!SH)
 #pragma unroll
-        for (int i = 0; i < R; i++)
-          if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
-        la[swz(base | o)] = a[j];
-        lb[swz(base | o)] = b[j];
-      }
+        for (int j = 0; j < NR; j++) lb[jslot<P, S>(base, j)] = b[j];
       __syncthreads();
-      jit_astages<P, S - 1, NW>(la, lb, E, prog, MT, t, gbase, src, srcb, dst, dstb, red);
+      jit_store_out<P>(la, dst, tile, t);
+      if constexpr (SH) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NR; j++) la[jslot<P, S>(base, j)] = b[j];
+        __syncthreads();
+        jit_store_out<P>(la, dstb, tile, t);
+      } else {
+        jit_store_out<P>(lb, dstb, tile, t);
+      }
+    } else {
+      const int nb = jbase<P, S - 1>(t);
+#pragma unroll
+      for (int j = 0; j < NR; j++) la[jslot<P, S>(base, j)] = a[j];
+      if constexpr (!SH)
+#pragma unroll
+        for (int j = 0; j < NR; j++) lb[jslot<P, S>(base, j)] = b[j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < NR; j++) a[j] = la[jslot<P, S - 1>(nb, j)];
+      if constexpr (SH) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NR; j++) la[jslot<P, S>(base, j)] = b[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NR; j++) b[j] = la[jslot<P, S - 1>(nb, j)];
+      } else {
+#pragma unroll
+        for (int j = 0; j < NR; j++) b[j] = lb[jslot<P, S - 1>(nb, j)];
+      }
+      // (the next write to LDS, after the next stage's ops, goes to the slots
+      // each lane has just read itself: no barrier needed before it)
+      jit_astages<P, S - 1, NW, SH>(la, lb, a, b, E, prog, MT, t, gbase, tile, dst, dstb, red);
     }
   }
 }
 
-// One adjoint pass of description P: a block per tile (Phi and Psi tiles in
-// LDS), the per-tile partial of each derivative slot written to the item's
-// partials array (summed over tiles afterwards in a fixed order).
-template <class P>
+// One adjoint pass of description P: a block per tile, the per-tile partial
+// of each derivative slot written to the item's partials array (summed over
+// tiles afterwards in a fixed order).
+template <class P, bool SH>
 __device__ __forceinline__ void jit_pass_adj(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units,
                                              const DOverride &ov) {
   constexpr int K = P::K, R = P::R, NR = 1 << R, T = 1 << (K - R);
   constexpr int NW = (T + 63) / 64;
   __shared__ c128 la[1 << K];
-  __shared__ c128 lb[1 << K];
+  __shared__ c128 lb[SH ? 1 : (1 << K)];
   __shared__ double red[P::NVAR > 0 ? P::NVAR : 1][NW];
   const int t = threadIdx.x;
   const int64_t u = blockIdx.x;
@@ -373,49 +447,52 @@ __device__ __forceinline__ void jit_pass_adj(const DJob *__restrict__ jobs, int 
 #pragma unroll
   for (int i = 0; i < K; i++) gbase = ins0<uint64_t>(gbase, P::TQ[i]);
   const DOp E = ldc(prog + P::GLAST);  // the pass's last op runs first
-  if constexpr (!P::DIN) {
-    uint64_t st = 0;
-#pragma unroll
-    for (int i = 0; i < K - R; i++) st |= (uint64_t)((t >> i) & 1) << P::TQ[i];
-#pragma unroll
-    for (int j = 0; j < NR; j++) {
-      uint64_t oj = 0;
-#pragma unroll
-      for (int i = 0; i < R; i++)
-        if ((j >> i) & 1) oj |= 1ull << P::TQ[K - R + i];
-      la[swz(j * T + t)] = ldg(&src[gbase | st | oj]);
-      lb[swz(j * T + t)] = ldg(&srcb[gbase | st | oj]);
-    }
+  if constexpr (P::NST == 0) {
+    // a pass without ops only moves qubits
+    jit_load_in<P>(la, src, gbase, t);
     __syncthreads();
-  }
-  jit_astages<P, P::NST - 1, NW>(la, lb, E, prog, MT, t, gbase, src, srcb, dst, dstb, red);
-  if constexpr (!P::DOUT) {
-    uint64_t gbo = (uint64_t)tile;
-#pragma unroll
-    for (int i = 0; i < K; i++) gbo = ins0<uint64_t>(gbo, P::TQO[i]);
-    uint64_t so = 0;
-    int sl = 0;
-#pragma unroll
-    for (int i = 0; i < K - R; i++)
-      if ((t >> i) & 1) {
-        so |= 1ull << P::TQO[i];
-        sl |= 1 << P::LBO[i];
-      }
-#pragma unroll
-    for (int j = 0; j < NR; j++) {
-      uint64_t oj = 0;
-      int ol = 0;
-#pragma unroll
-      for (int i = 0; i < R; i++)
-        if ((j >> i) & 1) {
-          oj |= 1ull << P::TQO[K - R + i];
-          ol |= 1 << P::LBO[K - R + i];
-        }
-      stg(&dst[gbo | so | oj], la[swz(sl | ol)]);
-      stg(&dstb[gbo | so | oj], lb[swz(sl | ol)]);
-    }
+    jit_store_out<P>(la, dst, tile, t);
+    __syncthreads();
+    jit_load_in<P>(la, srcb, gbase, t);
+    __syncthreads();
+    jit_store_out<P>(la, dstb, tile, t);
   } else {
-    __syncthreads();  // every wave's reduction entries are written
+    constexpr int S = P::NST - 1;
+    c128 a[NR], b[NR];
+    const int base = jbase<P, S>(t);
+    if constexpr (P::DIN) {
+      // the first stage's lanes run over the low tile bits: read HBM directly
+      uint64_t gb = gbase;
+#pragma unroll
+      for (int i = 0; i < K; i++)
+        if ((base >> i) & 1) gb |= 1ull << P::TQ[i];
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        uint64_t go = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) go |= 1ull << P::TQ[P::RBIT[S][i]];
+        a[j] = ldg(&src[gb | go]);
+        b[j] = ldg(&srcb[gb | go]);
+      }
+    } else {
+      jit_load_in<P>(la, src, gbase, t);
+      if constexpr (!SH) jit_load_in<P>(lb, srcb, gbase, t);
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < NR; j++) a[j] = la[jslot<P, S>(base, j)];
+      if constexpr (SH) {
+        __syncthreads();
+        jit_load_in<P>(la, srcb, gbase, t);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NR; j++) b[j] = la[jslot<P, S>(base, j)];
+      } else {
+#pragma unroll
+        for (int j = 0; j < NR; j++) b[j] = lb[jslot<P, S>(base, j)];
+      }
+    }
+    jit_astages<P, S, NW, SH>(la, lb, a, b, E, prog, MT, t, gbase, tile, dst, dstb, red);
   }
   if constexpr (P::NVAR > 0) {
     for (int v = t; v < P::NVAR; v += T) {
