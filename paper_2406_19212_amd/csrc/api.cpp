@@ -1501,6 +1501,7 @@ hipError_t run_passes(vqc_circuit c, Plan &P, int mode, c128 *a, c128 *b, const 
   ov.partials = partials;
   ov.mode = (mode == 0 && b) ? 1 : 0;
   ov.use = 1;
+  ov.job_units = 0;
   const int grid = grid_of(c, P.units_per_item);
   // passes that move qubits alternate between the state and the circuit's
   // scratch state (the plan ends in the state); the adjoint runs the plan
@@ -2843,6 +2844,7 @@ static vqc_status batch_forward_on(vqc_batch b, hipStream_t st) {
     const int64_t units = b->fwd_units[sI];
     const int grid = grid_of(c0, units);
     const DJob *jobs = b->d_fwd_jobs + b->fwd_first[sI];
+    ov.job_units = same ? c0->fwd.units_per_item : 0;
     if (same && c0->fwd.jit) VQC_TRY(launch_jit_pass(*c0->fwd.jit, sI, c0->fwd, jobs, b->fwd_count[sI], units, ov, st));
     else if (b->reg_only) VQC_TRY(launch_pass_reg(c0->fwd.R, 0, jobs, b->fwd_count[sI], units, grid, ov, st));
     else VQC_TRY(launch_pass_lds(c0->fwd.K, c0->fwd.R, false, c0->fwd.d4, jobs, b->fwd_count[sI], units, grid, ov,
@@ -2925,6 +2927,7 @@ static vqc_status batch_backward_pure_on(vqc_batch b, double *energies, hipStrea
     const int grid = grid_of(c0, units);
     const DJob *jobs = b->d_adj_jobs + b->adj_first[r];
     const int PA = (int)c0->adj.passes.size();
+    ov.job_units = same ? c0->adj.units_per_item : 0;
     if (same && c0->adj.jit && r < PA)
       VQC_TRY(launch_jit_pass(*c0->adj.jit, PA - 1 - r, c0->adj, jobs, b->adj_count[r], units, ov, st));
     else

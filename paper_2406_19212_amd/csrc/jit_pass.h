@@ -158,13 +158,21 @@ __device__ __forceinline__ void jit_stages(c128 *la, DOp E, const DOp *prog, cma
   }
 }
 
+// job of unit u: the only one, a division when every job has the same units,
+// else a binary search over the job table
+__device__ __forceinline__ int jit_job(const DJob *__restrict__ jobs, int n_jobs, int64_t u, const DOverride &ov) {
+  if (n_jobs <= 1) return 0;
+  if (ov.job_units > 0) return (int)(u / ov.job_units);
+  return find_job(jobs, n_jobs, u);
+}
+
 // the 2^R amplitudes lane t holds of tile u (input layout), read from HBM:
 // lanes run over the tile's lowest bits, so the loads are coalesced
 template <class P>
 __device__ __forceinline__ void jit_load_tile(c128 (&r)[1 << P::R], const DJob *__restrict__ jobs, int n_jobs,
                                               int64_t u, const DOverride &ov, int t) {
   constexpr int K = P::K, R = P::R, NR = 1 << R;
-  const DJob J = ldc(&jobs[n_jobs > 1 ? find_job(jobs, n_jobs, u) : 0]);
+  const DJob J = ldc(&jobs[jit_job(jobs, n_jobs, u, ov)]);
   const gc128 *A = (const gc128 *)(ov.use ? ov.a : J.a);
   uint64_t g = (uint64_t)(u - J.unit0);
 #pragma unroll
@@ -197,7 +205,7 @@ __device__ __forceinline__ void jit_pass_fwd(const DJob *__restrict__ jobs, int 
   c128 pf[NR];
   jit_load_tile<P>(pf, jobs, n_jobs, u, ov, t);
   for (; u < total_units; u += PERSIST ? gridDim.x : total_units) {
-    const DJob J = ldc(&jobs[n_jobs > 1 ? find_job(jobs, n_jobs, u) : 0]);
+    const DJob J = ldc(&jobs[jit_job(jobs, n_jobs, u, ov)]);
     const int64_t tile = u - J.unit0;
     gc128 *A = (gc128 *)(ov.use ? ov.a : J.a);
     gc128 *Bv = (gc128 *)(ov.use ? ov.b : J.b);
@@ -430,7 +438,7 @@ __device__ __forceinline__ void jit_pass_adj(const DJob *__restrict__ jobs, int 
   const int t = threadIdx.x;
   const int64_t u = blockIdx.x;
   if (u >= total_units) return;
-  const DJob J = ldc(&jobs[n_jobs > 1 ? find_job(jobs, n_jobs, u) : 0]);
+  const DJob J = ldc(&jobs[jit_job(jobs, n_jobs, u, ov)]);
   const int64_t tile = u - J.unit0;
   const gc128 *src = (const gc128 *)(ov.use ? ov.a : J.a);
   const gc128 *srcb = (const gc128 *)(ov.use ? ov.b : J.b);

@@ -169,6 +169,10 @@ struct DOverride {
   double *partials;
   int32_t mode;
   int32_t use;
+  // units of every job when all jobs of a launch have the same count (job j
+  // holds units j * job_units ..): the job of a unit is a division instead
+  // of a search; 0 = search (read by the circuit-specialised kernels)
+  int64_t job_units;
 };
 
 // matrix recipes (built on device from theta)
