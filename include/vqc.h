@@ -58,7 +58,8 @@ typedef enum {
   VQC_ERR_NOT_HERMITIAN = -9, /* gradient asked for a complex-coefficient H */
   VQC_ERR_NOT_UNITARY = -10,  /* backward through a non-unitary gate matrix */
   VQC_ERR_ILL_CONDITIONED = -11, /* a channel's inverse exceeds the condition bound */
-  VQC_ERR_SCRATCH_LIMIT = -12   /* input larger than the allocation-free call's fixed scratch */
+  VQC_ERR_SCRATCH_LIMIT = -12,  /* input larger than the allocation-free call's fixed scratch */
+  VQC_ERR_IN_USE = -13          /* circuit bound to a live batch (destroy, autotune) */
 } vqc_status;
 
 typedef enum { VQC_PURE = 0, VQC_MIXED = 1 } vqc_kind;
@@ -297,6 +298,7 @@ vqc_status vqc_fuse_gates(int n_qubits, int n_ops, const vqc_op *ops, int n_para
  * entries.  tune may be NULL (defaults).  ops and their data are copied. */
 vqc_status vqc_circuit_create(vqc_circuit *out, int n_qubits, vqc_kind kind, int n_ops,
                               const vqc_op *ops, int n_params, const vqc_tune *tune);
+/* VQC_ERR_IN_USE (and nothing freed) while a batch created with c is alive. */
 vqc_status vqc_circuit_destroy(vqc_circuit c);
 vqc_status vqc_circuit_stats_get(vqc_circuit c, vqc_circuit_stats *out);
 
@@ -347,8 +349,24 @@ vqc_status vqc_backward_inverse(vqc_circuit c, const double *theta_dev, vqc_stat
                                 const vqc_pauli_sum *H, double *grad_dev, double *energy_host,
                                 double max_cond);
 
-/* Time candidate tunes for c on the scratch state s (contents destroyed) and
- * re-plan c with the fastest; the chosen tune is written to *out. */
+/* Autotuner: time candidate tunes of c on the scratch state s (its contents
+ * are destroyed), then re-plan c with the fastest and write that tune to
+ * *out.  This replaces the fixed aggregation sizes of Sec. 3.2 (Fig. 3) by a
+ * measured choice.  target VQC_TUNE_FORWARD times vqc_apply_circuit from
+ * |0..0>; VQC_TUNE_GRADIENT times vqc_apply_circuit + vqc_backward with the
+ * observable H (real coefficients).  Candidates: pure states, tile bits
+ * 10..11 (fewer for small n) x low-block bits 3..5 x register bits 3..4 with
+ * the circuit's qubit-move setting, and the current shape with qubit moves
+ * switched (from 12 qubits); density matrices: low-block bits 3..6 and qubit
+ * moves on/off (tiles of 11 bits).  Circuits with specialised passes compile
+ * each candidate (code objects are cached on disk).  A candidate whose plan,
+ * compile or timed runs fail is not chosen; VQC_ERR_HIP if none ran (c keeps
+ * its previous tune).  VQC_ERR_IN_USE while a batch holds c (its tables would
+ * be replaced).  Synchronises the stream. */
+enum { VQC_TUNE_FORWARD = 0, VQC_TUNE_GRADIENT = 1 };
+vqc_status vqc_circuit_autotune_ex(vqc_circuit c, vqc_state s, const double *theta_dev,
+                                   const vqc_pauli_sum *H, int target, vqc_tune *out);
+/* vqc_circuit_autotune_ex with target VQC_TUNE_FORWARD. */
 vqc_status vqc_circuit_autotune(vqc_circuit c, vqc_state s, const double *theta_dev,
                                 vqc_tune *out);
 

@@ -256,12 +256,18 @@ class Circuit:
               "vqc_backward_inverse")
         return grad[: self.n_params], (e.value if energy else None)
 
-    def autotune(self, state: State, theta=None) -> dict:
+    def autotune(self, state: State, theta=None, terms=None) -> dict:
+        """Time candidate tunes on the scratch ``state`` and re-plan with the
+        fastest: the forward pass, or with ``terms`` the forward pass plus the
+        gradient of that observable.  Returns the chosen tune."""
         th = self._theta(theta)
         t = B.vqc_tune()
-        check(lib().vqc_circuit_autotune(self.h, state.h, _dptr(th), ctypes.byref(t)), "vqc_circuit_autotune")
+        ps = B.PauliSum(terms) if terms is not None else None
+        check(lib().vqc_circuit_autotune_ex(self.h, state.h, _dptr(th), ps.ref() if ps else None,
+                                            1 if terms is not None else 0, ctypes.byref(t)),
+              "vqc_circuit_autotune_ex")
         return {"tile_bits": t.tile_bits, "low_bits": t.low_bits, "reg_bits": t.reg_bits,
-                "grid_blocks": t.grid_blocks, "remap": t.remap}
+                "grid_blocks": t.grid_blocks, "remap": t.remap, "jit": t.jit}
 
 
 class Batch:
@@ -312,7 +318,8 @@ class Batch:
     def capture(self, terms, grads, energies=None, budget=0):
         ps = B.PauliSum(terms)
         gp = self._gptrs(grads)
-        self._cap_keep = (ps, gp)
+        # the graph holds these device pointers: keep the tensors alive with it
+        self._cap_keep = (ps, gp, list(grads), energies)
         check(lib().vqc_batch_capture(self.h, ps.ref(), gp, _dptr(energies), int(budget)), "vqc_batch_capture")
 
     def replay(self):

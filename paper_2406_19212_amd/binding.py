@@ -39,7 +39,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "qubit out of range or repeated",
           -7: "device out of memory", -8: "HIP runtime error",
           -9: "observable must have real coefficients", -10: "gate matrix is not unitary",
           -11: "channel inverse exceeds the condition-number bound",
-          -12: "input exceeds the fixed scratch of the allocation-free call"}
+          -12: "input exceeds the fixed scratch of the allocation-free call",
+          -13: "circuit is bound to a live batch"}
 
 
 class VQCError(RuntimeError):
@@ -110,6 +111,8 @@ _SIGS = {
     "vqc_backward_inverse": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(vqc_pauli_sum), c_void_p,
                                      ctypes.POINTER(c_double), c_double]),
     "vqc_circuit_autotune": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(vqc_tune)]),
+    "vqc_circuit_autotune_ex": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(vqc_pauli_sum), c_int,
+                                        ctypes.POINTER(vqc_tune)]),
     "vqc_batch_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "vqc_batch_destroy": (c_int, [c_void_p]),
     "vqc_batch_forward": (c_int, [c_void_p]),

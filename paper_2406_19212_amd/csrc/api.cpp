@@ -574,6 +574,7 @@ struct vqc_state_s {
 struct vqc_circuit_s {
   double jit_ms = 0;        // run-time compile (or cache load) of the specialised passes
   bool jit_cached = false;
+  int live_batches = 0;     // batches holding pointers into this circuit's tables
   int n, nbits;
   vqc_kind kind;
   int n_params;
@@ -1229,14 +1230,14 @@ bool jit_plan_ok(const Plan &P) { return !P.reg_only && !P.d4 && !P.passes.empty
 // of a pure-state circuit, one module for both plans; a failure leaves the
 // interpreting kernels in charge unless the caller asked for these kernels
 // (vqc_tune.jit = 1)
-vqc_status jit_prepare(vqc_circuit c) {
+vqc_status jit_prepare(vqc_circuit c, bool with_adj = true) {
   c->fwd.jit.reset();
   c->adj.jit.reset();
   c->jit_ms = 0;
   if (!jit_wanted(c)) return VQC_OK;
   // persistent grids when the caller asked for a grid size (vqc_tune.grid_blocks)
   const bool persist = c->tune.grid_blocks > 0;
-  const bool adj = jit_plan_ok(c->adj) && c->adj.K <= 10 + (c->adj.R == 3 ? 1 : 0);
+  const bool adj = with_adj && jit_plan_ok(c->adj) && c->adj.K <= 10 + (c->adj.R == 3 ? 1 : 0);
   std::vector<std::string> names;
   std::vector<int> threads;
   std::string src = "#include \"jit_pass.h\"\nnamespace vqc {\n";
@@ -1602,6 +1603,7 @@ const char *vqc_status_string(int st) {
     case VQC_ERR_NOT_UNITARY: return "gate matrix is not unitary";
     case VQC_ERR_ILL_CONDITIONED: return "channel inverse exceeds the condition-number bound";
     case VQC_ERR_SCRATCH_LIMIT: return "input exceeds the fixed scratch of the allocation-free call";
+    case VQC_ERR_IN_USE: return "circuit is bound to a live batch";
     default: return "unknown status";
   }
 }
@@ -2347,6 +2349,7 @@ vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops,
 }
 
 vqc_status vqc_circuit_destroy(vqc_circuit c) {
+  if (c && c->live_batches > 0) return VQC_ERR_IN_USE;
   delete c;
   return VQC_OK;
 }
@@ -2601,48 +2604,114 @@ vqc_status vqc_backward_inverse(vqc_circuit c, const double *theta, vqc_state s,
   return backward_impl(c, theta, s, H, grad, energy_host, nullptr, nullptr, 0, max_cond > 0.0 ? max_cond : 1e8);
 }
 
-vqc_status vqc_circuit_autotune(vqc_circuit c, vqc_state s, const double *theta, vqc_tune *out) {
-  if (!c || !s || !out) return VQC_ERR_ARG;
+// one timed run of an autotune candidate: forward (target 0) or forward +
+// gradient (target 1) from |0..0>, on the scratch state s
+static vqc_status tune_run(vqc_circuit c, vqc_state s, const double *theta, const vqc_pauli_sum *H, int target,
+                           double *grad) {
+  vqc_status st = vqc_state_reset(s);
+  if (st) return st;
+  st = vqc_apply_circuit(s, c, theta);
+  if (st || target == 0) return st;
+  return backward_impl(c, theta, s, H, grad, nullptr, nullptr, nullptr, 0);
+}
+
+vqc_status vqc_circuit_autotune_ex(vqc_circuit c, vqc_state s, const double *theta, const vqc_pauli_sum *H,
+                                   int target, vqc_tune *out) {
+  if (!c || !s || !out || (target != VQC_TUNE_FORWARD && target != VQC_TUNE_GRADIENT)) return VQC_ERR_ARG;
   if (s->kind != c->kind || s->n != c->n) return VQC_ERR_KIND;
   if (c->n_params > 0 && !theta) return VQC_ERR_ARG;
-  if (c->kind == VQC_MIXED || c->nbits < 5) {
+  if (target == VQC_TUNE_GRADIENT && !H) return VQC_ERR_ARG;
+  // a batch holds device pointers into the circuit's plans: re-planning would
+  // leave them dangling
+  if (c->live_batches > 0) return VQC_ERR_IN_USE;
+  const bool mixed = c->kind == VQC_MIXED;
+  if ((mixed && c->nbits < kMixedLdsMinBits) || c->nbits < 5) {  // register-only plans: nothing to choose
     *out = c->tune;
     return VQC_OK;
   }
-  hipEvent_t e0, e1;
-  VQC_TRY(hipEventCreate(&e0));
-  VQC_TRY(hipEventCreate(&e1));
+  if (target == VQC_TUNE_GRADIENT) {
+    std::vector<DTerm> t;
+    const vqc_status st = make_terms(H, c->n, t, true);
+    if (st) return st;
+  }
+  DevBuf gbuf;
+  double *grad = nullptr;
+  if (target == VQC_TUNE_GRADIENT) {
+    VQC_TRY(gbuf.ensure(std::max(1, c->n_params) * sizeof(double)));
+    grad = gbuf.as<double>();
+  }
+  // candidates: tile and low-block bits, register bits; qubit moves on and
+  // off at the default shape (mixed: low-block bits and qubit moves)
   const vqc_tune orig = c->tune;
+  std::vector<vqc_tune> cand;
+  auto add = [&](int K, int low, int R, int remap) {
+    vqc_tune t = orig;
+    t.tile_bits = K;
+    t.low_bits = low;
+    t.reg_bits = R;
+    t.remap = remap;
+    for (const vqc_tune &u : cand)
+      if (u.tile_bits == K && u.low_bits == low && u.reg_bits == R && u.remap == remap) return;
+    cand.push_back(t);
+  };
+  if (mixed) {
+    for (int low = 3; low <= 6; low++) add(kMixedTile, low, 4, orig.remap);
+    add(kMixedTile, orig.low_bits, 4, orig.remap > 0 ? -1 : 1);
+  } else {
+    add(orig.tile_bits, orig.low_bits, orig.reg_bits, orig.remap);
+    for (int K = std::min(11, c->nbits); K >= std::max(8, std::min(10, c->nbits)); K--)
+      for (int low = 3; low <= 5; low++)
+        for (int R = 3; R <= 4; R++)
+          if (low <= K - 2) add(K, low, R, orig.remap);
+    if (c->nbits >= kRemapMinBits) add(orig.tile_bits, orig.low_bits, orig.reg_bits, orig.remap > 0 ? -1 : 1);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_status(he);
+  }
   vqc_tune best = orig;
-  float best_ms = 1e30f;
-  for (int K = 9; K <= kMaxTile; K++) {
-    if (K > c->nbits) break;
-    for (int low = 3; low <= 5; low++) {
-      if (low >= K) continue;
-      c->tune.tile_bits = K;
-      c->tune.low_bits = low;
-      c->tune.grid_blocks = orig.grid_blocks;
-      if (make_plans(c)) continue;
-      vqc_status st = vqc_apply_circuit(s, c, theta);
-      if (st) continue;
-      (void)hipEventRecord(e0, s->stream);
-      for (int r = 0; r < 2; r++) (void)vqc_apply_circuit(s, c, theta);
-      (void)hipEventRecord(e1, s->stream);
-      (void)hipEventSynchronize(e1);
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best_ms) { best_ms = ms; best = c->tune; }
+  float best_ms = 3.0e38f;
+  for (const vqc_tune &t : cand) {
+    c->tune = t;
+    if (make_plans(c) != VQC_OK || jit_prepare(c, target == VQC_TUNE_GRADIENT) != VQC_OK) continue;
+    // warm-up, then enough repetitions for a few milliseconds of work
+    if (tune_run(c, s, theta, H, target, grad) != VQC_OK) continue;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) continue;
+    int reps = 1;
+    float ms = 0;
+    bool ok = true;
+    for (;;) {
+      ok = hipEventRecord(e0, s->stream) == hipSuccess;
+      for (int r = 0; ok && r < reps; r++) ok = tune_run(c, s, theta, H, target, grad) == VQC_OK;
+      ok = ok && hipEventRecord(e1, s->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      if (!ok || ms >= 20.0f || reps >= 64) break;
+      reps *= 4;
+    }
+    if (!ok) continue;
+    ms /= reps;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c->tune;  // as resolved by the planner
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->tune = best;
+  c->tune = best_ms < 3.0e38f ? best : orig;
   vqc_status st = make_plans(c);
+  if (st == VQC_OK) st = upload_const(c);
+  if (st == VQC_OK) st = jit_prepare(c, true);
   if (st) return st;
-  st = jit_prepare(c);
-  if (st) return st;
+  if (best_ms >= 3.0e38f) return VQC_ERR_HIP;  // no candidate ran
   *out = c->tune;
   return VQC_OK;
+}
+
+vqc_status vqc_circuit_autotune(vqc_circuit c, vqc_state s, const double *theta, vqc_tune *out) {
+  return vqc_circuit_autotune_ex(c, s, theta, nullptr, VQC_TUNE_FORWARD, out);
 }
 
 // --------------------------------------------------------------- batches
@@ -2964,12 +3033,14 @@ vqc_status vqc_batch_create(vqc_batch *out, int B, const vqc_circuit *circuits, 
   b->Kadj = circuits[0]->adj.K;
   vqc_status st = batch_build_tables(b.get());
   if (st) return st;
+  for (vqc_circuit c : b->circ) c->live_batches++;
   *out = b.release();
   return VQC_OK;
 }
 
 vqc_status vqc_batch_destroy(vqc_batch b) {
   if (!b) return VQC_OK;
+  for (vqc_circuit c : b->circ) c->live_batches--;
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
