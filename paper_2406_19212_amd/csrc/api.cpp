@@ -111,6 +111,7 @@ bool valid_type(int t) {
 // global phase e^{i pi/4}; `factored` selects that form (pure states only).
 int gate_kind(const vqc_op &op, bool factored) {
   const int type = op.type, m = op.n_qubits;
+  if (m == 3) return GK_DENSE3;  // a general three-qubit matrix (named three-qubit gates are expanded)
   switch (type) {
     case VQC_Z: case VQC_S: case VQC_T: return GK_SPH1;
     case VQC_RZ: return GK_SDG1;
@@ -808,7 +809,8 @@ vqc_status lower(vqc_circuit c) {
       for (int t = 0; t < m; t++) e.q[t] = op.qubits[t];
       const bool fac = phase_factored(op.type);
       n_factored += fac;
-      e.mat = add_gate_recipe(c, gk, op.type, fac ? RF_GATE_F : RF_GATE, m, op, data_off, n_data);
+      e.mat = m == 3 ? add_recipe(c, op.type, RF_COPY, 0, m, op, data_off, n_data, d * d)
+                     : add_gate_recipe(c, gk, op.type, fac ? RF_GATE_F : RF_GATE, m, op, data_off, n_data);
       // Pauli rotations exp(-i theta G / 2): derivative from the generator
       const int gen = op.type == VQC_RX ? GK_GENX : op.type == VQC_RY ? GK_GENY : op.type == VQC_RZ ? GK_GENZ : 0;
       for (int k = 0; k < 5; k++)
@@ -827,10 +829,12 @@ vqc_status lower(vqc_circuit c) {
       e.nq = m;
       e.kind = gk;
       for (int t = 0; t < m; t++) e.q[t] = op.qubits[t];
-      e.mat = add_gate_recipe(c, gk, op.type, RF_GATE, m, op, data_off, n_data);
+      e.mat = m == 3 ? add_recipe(c, op.type, RF_COPY, 0, m, op, data_off, n_data, d * d)
+                     : add_gate_recipe(c, gk, op.type, RF_GATE, m, op, data_off, n_data);
       c->elems.push_back(e);
       for (int t = 0; t < m; t++) e.q[t] = op.qubits[t] + n;
-      e.mat = add_gate_recipe(c, gk, op.type, RF_GATE_CONJ, m, op, data_off, n_data);
+      e.mat = m == 3 ? add_recipe(c, op.type, RF_COPY, 1, m, op, data_off, n_data, d * d)
+                     : add_gate_recipe(c, gk, op.type, RF_GATE_CONJ, m, op, data_off, n_data);
       c->elems.push_back(e);
     } else {
       Elem e;
@@ -1057,8 +1061,9 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
       for (int ei : S.elems) {
         const Elem &e = c->elems[ei];
         const int b0 = e.nq > 0 ? regpos[loc[e.q[0]]] : 0, b1 = e.nq > 1 ? regpos[loc[e.q[1]]] : 0;
-        std::snprintf(buf, sizeof(buf), "      E = jop<%d, %d, %d, %d>(a, E, prog + %d, M);\n", R, e.kind, b0, b1,
-                      g + 1);
+        const int b2 = e.nq > 2 ? regpos[loc[e.q[2]]] : 0;
+        std::snprintf(buf, sizeof(buf), "      E = jop<%d, %d, %d, %d, %d>(a, E, prog + %d, M);\n", R, e.kind, b0, b1,
+                      b2, g + 1);
         s += buf;
         g++;
       }
@@ -1164,6 +1169,7 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::strin
         k = first_k[si] + q;
         const int gi = g0 + k;
         const int b0 = e.nq > 0 ? regpos[loc[e.q[0]]] : 0, b1 = e.nq > 1 ? regpos[loc[e.q[1]]] : 0;
+        const int b2 = e.nq > 2 ? regpos[loc[e.q[2]]] : 0;
         const bool gen = !e.d.empty() && e.d[0].kind >= GK_GENX && e.d[0].kind <= GK_GENZ;
         std::snprintf(buf, sizeof(buf),
                       "      {\n        lgkm_wait();\n        const DOp En = ldc(prog + %d);\n"
@@ -1176,7 +1182,7 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::strin
                         (int)e.d[0].kind, b0);
           s += buf;
         }
-        std::snprintf(buf, sizeof(buf), "        japply<R, true, %d, %d, %d>(a, E, M);\n", e.kind, b0, b1);
+        std::snprintf(buf, sizeof(buf), "        japply<R, true, %d, %d, %d, %d>(a, E, M);\n", e.kind, b0, b1, b2);
         s += buf;
         if (!gen)
           for (size_t d = 0; d < e.d.size(); d++) {
@@ -1186,9 +1192,9 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::strin
             s += buf;
           }
         std::snprintf(buf, sizeof(buf),
-                      "        japply<R, true, %d, %d, %d>(b, E, M);\n        E = En;\n"
+                      "        japply<R, true, %d, %d, %d, %d>(b, E, M);\n        E = En;\n"
                       "        __builtin_amdgcn_sched_barrier(0);\n      }\n",
-                      e.kind, b0, b1);
+                      e.kind, b0, b1, b2);
         s += buf;
       }
       s += "      return E;\n    }\n";
@@ -2297,8 +2303,10 @@ vqc_status expand_gate3(const vqc_op &op, std::vector<vqc_op> &out, std::deque<s
     out.push_back(plain_op(VQC_CONTROL, b, t, Vd.data(), 4));
     out.push_back(plain_op(VQC_CNOT, a, b));
     out.push_back(plain_op(VQC_CONTROL, a, t, V.data(), 4));
+  } else if (op.type == VQC_MATRIX) {
+    out.push_back(op);  // a register op on three bits (GK_DENSE3)
   } else {
-    return VQC_ERR_UNSUPPORTED;  // a general three-qubit matrix: single ops only
+    return VQC_ERR_UNSUPPORTED;  // three-qubit Kraus sets: single ops only
   }
   return VQC_OK;
 }

@@ -34,7 +34,7 @@ namespace vqc {
 
 // op of kind KIND on register bits B0 (and B1) from its program entry E, or
 // its adjoint (ADJ)
-template <int R, bool ADJ, int KIND, int B0, int B1>
+template <int R, bool ADJ, int KIND, int B0, int B1, int B2 = 0>
 __device__ __forceinline__ void japply(c128 (&a)[1 << R], const DOp &E, cmat *mats) {
   constexpr int NR = 1 << R;
   SRec r;
@@ -88,6 +88,14 @@ __device__ __forceinline__ void japply(c128 (&a)[1 << R], const DOp &E, cmat *ma
     rg_fsim<NR, B0, B1, ADJ>(a, M);
   } else if constexpr (KIND == GK_CX) {
     rg_cx<NR, B0, B1>(a);
+  } else if constexpr (KIND == GK_DENSE3) {
+    // bits fixed here: sorted bits and the index map are compile-time
+    constexpr int lo = B0 < B1 ? (B0 < B2 ? B0 : B2) : (B1 < B2 ? B1 : B2);
+    constexpr int hi = B0 > B1 ? (B0 > B2 ? B0 : B2) : (B1 > B2 ? B1 : B2);
+    constexpr int mid = B0 + B1 + B2 - lo - hi;
+    int rm[8];
+    dense3_map(B0, B1, B2, rm);
+    rg_dense3<NR, lo, mid, hi, ADJ>(a, M, rm);
   }
   // GK_NONE: nothing
 }
@@ -99,12 +107,12 @@ __device__ __forceinline__ void japply(c128 (&a)[1 << R], const DOp &E, cmat *ma
 // pass (which would need far more scalar registers than there are) and from
 // starting the next load before the wait (scalar loads return out of order,
 // so a wait is a wait for all of them).
-template <int R, int KIND, int B0, int B1>
+template <int R, int KIND, int B0, int B1, int B2 = 0>
 __device__ __forceinline__ DOp jop(c128 (&a)[1 << R], const DOp &E, const DOp *next, cmat *mats) {
   lgkm_wait();
   const DOp En = ldc(next);
   __builtin_amdgcn_sched_barrier(0);
-  japply<R, false, KIND, B0, B1>(a, E, mats);
+  japply<R, false, KIND, B0, B1, B2>(a, E, mats);
   __builtin_amdgcn_sched_barrier(0);
   return En;
 }

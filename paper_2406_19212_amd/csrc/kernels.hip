@@ -258,6 +258,9 @@ __device__ void build_plain(const DRecipe &R, const c128 *__restrict__ cdata, co
       for (int e = 0; e < d * d; e++) out[e] = G[e];
       break;
     }
+    case RF_COPY:
+      for (int e = 0; e < R.n_data; e++) out[e] = R.k ? cconj(data[e]) : data[e];
+      break;
     case RF_GPHASE: {
       double sn, cs;
       sincospi(0.25 * (R.k & 7), &sn, &cs);

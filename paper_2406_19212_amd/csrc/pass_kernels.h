@@ -209,6 +209,49 @@ __device__ __forceinline__ void rg_dense2(c128 (&a)[NR], cmat *M) {
   }
 }
 
+// 8x8 on register bits S0, S1, S2; the matrix element for the group's local
+// indices (r, c) (l = b_{S0} + 2 b_{S1} + 4 b_{S2}) is M[rm[r]][rm[c]] (or
+// its adjoint's), rm mapping these local indices to the op's own (which
+// orders its qubits differently when rm is not the identity)
+template <int NR, int S0, int S1, int S2, bool ADJ>
+__device__ __forceinline__ void rg_dense3(c128 (&a)[NR], cmat *M, const int (&rm)[8]) {
+  if constexpr (NR >= 8) {
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+      if (j & ((1 << S0) | (1 << S1) | (1 << S2))) continue;
+      int idx[8];
+#pragma unroll
+      for (int l = 0; l < 8; l++) idx[l] = j | ((l & 1) << S0) | (((l >> 1) & 1) << S1) | ((l >> 2) << S2);
+      c128 x[8];
+#pragma unroll
+      for (int l = 0; l < 8; l++) x[l] = a[idx[l]];
+#pragma unroll
+      for (int r = 0; r < 8; r++) {
+        c128 acc = cmul(mel<ADJ, 8>(M, rm[r], rm[0]), x[0]);
+#pragma unroll
+        for (int c = 1; c < 8; c++) acc = cfma(mel<ADJ, 8>(M, rm[r], rm[c]), x[c], acc);
+        a[idx[r]] = acc;
+      }
+    }
+  }
+}
+
+// the op's register bits (any order, distinct) as sorted bits and the local
+// index map of rg_dense3
+__device__ __forceinline__ int dense3_map(int r0, int r1, int r2, int (&rm)[8]) {
+  const int lo = min(r0, min(r1, r2)), hi = max(r0, max(r1, r2)), mid = r0 + r1 + r2 - lo - hi;
+  const int pos[3] = {r0 == lo ? 0 : r0 == mid ? 1 : 2, r1 == lo ? 0 : r1 == mid ? 1 : 2,
+                      r2 == lo ? 0 : r2 == mid ? 1 : 2};
+#pragma unroll
+  for (int l = 0; l < 8; l++) {
+    int o = 0;
+#pragma unroll
+    for (int t = 0; t < 3; t++) o |= ((l >> pos[t]) & 1) << t;
+    rm[l] = o;
+  }
+  return (1 << lo) | (1 << mid) | (1 << hi);
+}
+
 template <int NR, int B0, int B1, bool ADJ>
 __device__ __forceinline__ void rg_diag2(c128 (&a)[NR], cmat *M) {
   c128 d[4];
@@ -625,6 +668,17 @@ __device__ __forceinline__ void rg_apply_generic(c128 (&a)[1 << R], const DGate 
         default: break;
       }
       break;
+    case GK_DENSE3: {
+      int rm[8];
+      switch (dense3_map(g.r[0], g.r[1], g.r[2], rm)) {
+        case 7: rg_dense3<NR, 0, 1, 2, ADJ>(a, M, rm); break;
+        case 11: if constexpr (R > 3) rg_dense3<NR, 0, 1, 3, ADJ>(a, M, rm); break;
+        case 13: if constexpr (R > 3) rg_dense3<NR, 0, 2, 3, ADJ>(a, M, rm); break;
+        case 14: if constexpr (R > 3) rg_dense3<NR, 1, 2, 3, ADJ>(a, M, rm); break;
+        default: break;
+      }
+      break;
+    }
     case GK_DENSE4:
       if constexpr (D4) rg_dense4<NR, ADJ>(a, M);
       break;

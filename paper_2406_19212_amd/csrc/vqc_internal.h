@@ -56,7 +56,10 @@ enum GateKind : int8_t {
   // a two-qubit depolarizing superoperator a I + b |I>><<I| on (q1, q2,
   // q1 + n, q2 + n), register bits 0..3 in order: a = M[1][1], b = M[0][5]
   // of its stored 16x16 (the inverse has the same form)
-  GK_DEPOL4 = 22
+  GK_DEPOL4 = 22,
+  // 8x8 on three register bits (a general three-qubit gate; local index
+  // b_{q0} + 2 b_{q1} + 4 b_{q2})
+  GK_DENSE3 = 23
 };
 // DGate.nd: derivative count in the low byte; this bit set when the op's
 // derivatives are generator kinds (taken on Phi before the op is undone)
@@ -189,7 +192,8 @@ enum RecipeForm : int32_t {
   // product S_{m-1} ... S_0 of the 4x4 superoperators of a run of one-qubit
   // ops (data = index of S_0's recipe in the recipe array, n_data = m)
   RF_FUSED = 9,
-  RF_DFUSED = 10       // the same with S_s replaced by its derivative: k = s * 8 + parameter
+  RF_DFUSED = 10,      // the same with S_s replaced by its derivative: k = s * 8 + parameter
+  RF_COPY = 11         // the op's constant matrix as stored (row-major), conjugated when k = 1
 };
 
 struct DRecipe {

@@ -1,7 +1,9 @@
 """Three-qubit gates (Toffoli, Fredkin, doubly controlled U, general 8x8
-matrices): single ops on pure and mixed states, and circuits (where they run
-as exact one- and two-qubit sequences) forward and backward, against the
-oracle's dense definitions."""
+matrices): single ops on pure and mixed states, and circuits forward and
+backward (the named gates run as exact one- and two-qubit sequences, a
+general 8x8 matrix as one register op on three register bits in any order,
+also in the circuit-specialised kernels), against the oracle's dense
+definitions."""
 import itertools
 
 import numpy as np
@@ -58,8 +60,11 @@ def circuit_with_gate3(n, layers, seed, noisy=False):
             if noisy:
                 ops.append(Op("depolarizing", (q,), (0.02,)))
         a, b, c = (int(v) for v in rng.choice(n, 3, replace=False))
-        ops.append(Op(["toffoli", "fredkin", "ccontrol"][layer % 3], (a, b, c), (), (),
-                      W.random_unitary(2, seed + layer) if layer % 3 == 2 else None))
+        kind = ["toffoli", "fredkin", "ccontrol", "matrix"][layer % 4]
+        data = {"ccontrol": W.random_unitary(2, seed + layer), "matrix": W.random_unitary(8, seed + 50 + layer)}
+        ops.append(Op(kind, (a, b, c), (), (), data.get(kind)))
+        if layer % 2:  # a second general matrix, qubits in another order
+            ops.append(Op("matrix", (c, a, b), (), (), W.random_unitary(8, seed + 70 + layer)))
         for q in range(layer % 2, n - 1, 2):
             ops.append(Op("cz", (q, q + 1)))
             if noisy:
@@ -70,10 +75,15 @@ def circuit_with_gate3(n, layers, seed, noisy=False):
 
 
 @pytest.mark.parametrize("n,tune", [(7, None), (9, {"tile_bits": 6, "low_bits": 2}),
-                                    (13, {"tile_bits": 8, "low_bits": 3, "remap": 1})])
+                                    (13, {"tile_bits": 8, "low_bits": 3, "remap": 1}),
+                                    (13, {"tile_bits": 9, "low_bits": 3, "reg_bits": 4, "jit": 1}),
+                                    (14, {"tile_bits": 10, "low_bits": 4, "reg_bits": 3, "remap": 1, "jit": 1}),
+                                    (3, None)])
 def test_pure_circuit_with_three_qubit_gates(n, tune):
-    ops, th = circuit_with_gate3(n, 6, 80 + n)
+    ops, th = circuit_with_gate3(n, 8, 80 + n)
     c = Circuit(n, ops, tune=tune)
+    if tune and tune.get("jit") == 1:
+        assert c.stats()["n_jit_passes"] == c.stats()["n_passes"]
     st = State(n)
     tht = torch.tensor(th, device="cuda")
     c.apply(st, tht)
@@ -85,9 +95,9 @@ def test_pure_circuit_with_three_qubit_gates(n, tune):
     assert maxdiff(g.cpu().numpy(), g_ref) < GRAD_TOL
 
 
-@pytest.mark.parametrize("n", [3, 5])
+@pytest.mark.parametrize("n", [3, 5, 6])
 def test_noisy_circuit_with_three_qubit_gates(n):
-    ops, th = circuit_with_gate3(n, 4, 90 + n, noisy=True)
+    ops, th = circuit_with_gate3(n, 8, 90 + n, noisy=True)
     c = Circuit(n, ops, mixed=True, n_params=len(th))
     tht = torch.tensor(th, device="cuda")
     st = State(n, mixed=True)
