@@ -269,7 +269,7 @@ def grad_mixed(n: int, ops, theta, terms, init=None, n_params=None, stride: int 
 
 
 def invert(A: np.ndarray) -> np.ndarray:
-    """Inverse of a square matrix (D <= 16) by Gauss-Jordan with partial pivoting."""
+    """Inverse of a square matrix (D <= 64) by Gauss-Jordan with partial pivoting."""
     A = np.ascontiguousarray(A, np.complex128)
     D = A.shape[0]
     out = np.zeros((D, D), np.complex128)

@@ -432,6 +432,40 @@ int or_apply_op(cplx *st, int n, int mixed, const or_op *op, const double *theta
 
 /* vec(rho) -> M^dagger vec(rho) = vec(U^dagger rho U) for a three-qubit gate
  * (also its inverse): U^dagger on the ket bits, U^T on the bra bits */
+int or_invert(int D, const cplx *A, cplx *Ainv);
+
+/* The 64 x 64 superoperator S of a three-qubit Kraus set (Eq. (channel2)),
+ * into a caller buffer of 64 * 64; returns 0 or -1. */
+static int kraus3_superop(const or_op *op, cplx *S) {
+  cplx *K = malloc(64 * 64 * sizeof(cplx));
+  int nk;
+  if (!K) return -1;
+  if (op->code != OR_KRAUS || op->n_data > 64 * 64 || (nk = or_channel_kraus(op, K)) < 1) {
+    free(K);
+    return -1;
+  }
+  or_superop(3, nk, K, S);
+  free(K);
+  return 0;
+}
+
+/* Psi <- S^dagger Psi (adjoint superoperator) or Phi <- S^{-1} Phi (inverse)
+ * for a three-qubit channel on vec(rho) of n qubits. */
+static int kraus3_apply(cplx *v, int n, const or_op *op, int inverse) {
+  cplx *S = malloc(2 * 64 * 64 * sizeof(cplx)), *T = S ? S + 64 * 64 : NULL;
+  int qq[8], rc = 0;
+  if (!S) return -1;
+  if (kraus3_superop(op, S)) rc = -1;
+  else if (inverse) rc = or_invert(64, S, T);
+  else dagger(S, 64, T);
+  if (!rc) {
+    super_qubits(op, n, qq);
+    or_apply(v, 2 * n, 6, qq, T);
+  }
+  free(S);
+  return rc;
+}
+
 static int mixed_gate3_adjoint(cplx *v, int n, const or_op *op, const double *theta) {
   cplx G[64], Gd[64], Gt[64];
   int qq[3];
@@ -593,8 +627,11 @@ int or_grad_mixed(int n, int n_ops, const or_op *ops, const double *theta, const
     for (int j = s1 - 1; j >= s0; j--) {
       const or_op *op = &ops[j];
       int D = 1 << (2 * op->m);
-      if (op->m == 3) {  /* three-qubit gates carry no parameters */
-        if (mixed_gate3_adjoint(psi, n, op, theta)) { rc = -1 - j; goto done; }
+      if (op->m == 3) {  /* three-qubit gates and channels carry no parameters */
+        if (is_channel(op->code) ? kraus3_apply(psi, n, op, 0) : mixed_gate3_adjoint(psi, n, op, theta)) {
+          rc = -1 - j;
+          goto done;
+        }
         continue;
       }
       super_qubits(op, n, qq);
@@ -621,18 +658,20 @@ done:
   return rc;
 }
 
-/* Inverse of a D x D row-major matrix by Gauss-Jordan elimination with
- * partial pivoting (textbook).  Returns 0, or -1 when a pivot is exactly 0. */
+/* Inverse of a D x D row-major matrix (D <= 64) by Gauss-Jordan elimination
+ * with partial pivoting (textbook).  Returns 0, or -1 when a pivot is exactly
+ * 0. */
 int or_invert(int D, const cplx *A, cplx *Ainv) {
-  cplx W[16 * 32];
-  if (D < 1 || D > 16) return -1;
+  if (D < 1 || D > 64) return -1;
+  cplx *W = malloc((size_t)D * 2 * D * sizeof(cplx));
+  if (!W) return -1;
   for (int r = 0; r < D; r++)
     for (int c = 0; c < 2 * D; c++) W[r * 2 * D + c] = c < D ? A[r * D + c] : (c - D == r);
   for (int k = 0; k < D; k++) {
     int p = k;
     for (int r = k + 1; r < D; r++)
       if (cabs(W[r * 2 * D + k]) > cabs(W[p * 2 * D + k])) p = r;
-    if (W[p * 2 * D + k] == 0) return -1;
+    if (W[p * 2 * D + k] == 0) { free(W); return -1; }
     for (int c = 0; c < 2 * D; c++) {
       cplx t = W[k * 2 * D + c];
       W[k * 2 * D + c] = W[p * 2 * D + c];
@@ -648,6 +687,7 @@ int or_invert(int D, const cplx *A, cplx *Ainv) {
   }
   for (int r = 0; r < D; r++)
     for (int c = 0; c < D; c++) Ainv[r * D + c] = W[r * 2 * D + D + c];
+  free(W);
   return 0;
 }
 
@@ -674,6 +714,13 @@ int or_grad_mixed_inverse(int n, int n_ops, const or_op *ops, const double *thet
   for (int j = n_ops - 1; j >= 0; j--) {
     const or_op *op = &ops[j];
     int D = 1 << (2 * op->m);
+    if (op->m == 3 && is_channel(op->code)) {  /* no parameters: Phi <- S^{-1} Phi, Psi <- S^dagger Psi */
+      if (kraus3_apply(phi, n, op, 1) || kraus3_apply(psi, n, op, 0)) {
+        rc = -1 - j;
+        goto done;
+      }
+      continue;
+    }
     if (op->m == 3) {  /* unitary, no parameters: M^{-1} = M^dagger */
       if (mixed_gate3_adjoint(phi, n, op, theta) || mixed_gate3_adjoint(psi, n, op, theta)) {
         rc = -1 - j;

@@ -560,7 +560,7 @@ def test_noiseless_mixed_gradient_equals_pure(oracle_mod):
 
 # ------------------------------------------- noisy gradient, inverse form
 
-@pytest.mark.parametrize("D", [2, 4, 16])
+@pytest.mark.parametrize("D", [2, 4, 16, 64])
 def test_invert_matches_library_inverse(oracle_mod, D):
     rng = np.random.default_rng(90 + D)
     A = rng.normal(size=(D, D)) + 1j * rng.normal(size=(D, D)) + 2 * D * np.eye(D)
@@ -624,6 +624,44 @@ def test_adjoint_mixed_inverse_from_init_and_singular_channel(oracle_mod):
     bad = ops + [NS(name="amplitude_damping", qubits=(1,), params=(1.0,), var=(), data=None)]
     with pytest.raises(ValueError):
         oracle_mod.grad_mixed_inverse(n, bad, th, terms)
+
+
+def weak_kraus3(eps, seed):
+    """A three-qubit channel close to a unitary: K_0 = sqrt(1 - eps) U and
+    K_1, K_2 = sqrt(eps) times the blocks of a random 16 x 8 isometry (so
+    sum K^dagger K = I and the superoperator is well conditioned)."""
+    U = W.random_unitary(8, seed)
+    R = W.random_kraus(8, 2, seed + 1)
+    return [math.sqrt(1 - eps) * U] + [math.sqrt(eps) * r for r in R]
+
+
+def test_three_qubit_channel_gradients_vs_parameter_shift(oracle_mod):
+    """Both noisy gradient forms through three-qubit channels (Psi moves with
+    the adjoint superoperator, Phi with the inverse one in the inverse form)
+    against exact parameter shifts; the inverse form's Phi returns to the
+    initial state."""
+    from paper_2406_19212_amd.workloads import Op
+    n = 4
+    ops, P = [], 0
+    for layer in range(3):
+        for q in range(n):
+            ops.append(Op("ry", (q,), (0.0,), (P,)))
+            P += 1
+        qs = [(0, 2, 3), (3, 1, 0), (1, 2, 0)][layer]
+        ops.append(Op("kraus", qs, (), (), weak_kraus3(0.1, 60 + layer)))
+        ops.append(Op("cz", (layer % n, (layer + 1) % n)))
+        ops.append(Op("rz", (layer % n,), (0.0,), (P,)))
+        P += 1
+    th = np.random.default_rng(8).uniform(-3, 3, P)
+    terms = W.zz(0, 1) + [W.pauli_string({2: "x"}, 0.5), W.pauli_string({1: "y", 3: "y"}, -0.3)]
+    gs = shift_grad(lambda t: loss_mixed(oracle_mod, n, ops, t, terms), th)
+    e, g = oracle_mod.grad_mixed(n, ops, th, terms)
+    assert abs(e - loss_mixed(oracle_mod, n, ops, th, terms)) < 1e-14
+    assert np.max(np.abs(g - gs)) < 1e-12
+    e2, g2, phi = oracle_mod.grad_mixed_inverse(n, ops, th, terms)
+    assert abs(e2 - e) < 1e-14
+    assert np.max(np.abs(g2 - gs)) < 1e-12
+    assert np.max(np.abs(phi - oracle_mod.initial_state(n, mixed=True))) < 1e-12
 
 
 # ------------------------------------------------- measurement and sampling
