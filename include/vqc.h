@@ -80,8 +80,7 @@ enum {
   VQC_RX, VQC_RY, VQC_RZ, VQC_ID,
   VQC_CZ = 20, VQC_CNOT, VQC_SWAP, VQC_ISWAP, VQC_FSIM, VQC_CRX, VQC_CRY, VQC_CRZ,
   VQC_CONTROL, /* CONTROLGate(i, j, U): data = 2x2 target matrix */
-  VQC_MATRIX,  /* QuantumGate(positions, data): data = 2^m x 2^m; m <= 2 in
-                  circuits, m <= 3 in vqc_apply_op / vqc_apply_gate */
+  VQC_MATRIX,  /* QuantumGate(positions, data): data = 2^m x 2^m, m <= 3 */
   /* three-qubit gates (Sec. 2.2), local index b_{q0} + 2 b_{q1} + 4 b_{q2}:
    * TOFFOLI flips qubits[2] when qubits[0] and qubits[1] are 1; FREDKIN swaps
    * qubits[1] and qubits[2] when qubits[0] is 1; CCONTROL is
@@ -106,7 +105,7 @@ enum {
  * parameters (Sec. 2.2). */
 typedef struct {
   int type;
-  int n_qubits;           /* 1, 2, or 3 (three-qubit gates only) */
+  int n_qubits;           /* 1, 2, or 3 */
   int qubits[4];
   double params[5];
   int param_index[5];
@@ -216,8 +215,11 @@ vqc_status vqc_apply_op(vqc_state s, const vqc_op *op);
  * n_kraus (1..64) column-major 2^m x 2^m blocks, qubits[0] = bit 0 of their
  * index, complete to 1e-12 (else VQC_ERR_NOT_CPTP).  m = 3 applies
  * sum_s K_s rho K_s^dagger term by term on each 8 x 8 block of rho and
- * synchronises the stream; three-qubit channels are single ops only
- * (vqc_circuit_create refuses them with VQC_ERR_UNSUPPORTED). */
+ * synchronises the stream.  In circuits a three-qubit channel runs as an HBM
+ * pass of its own (the same block kernel; the adjoint sweep applies the
+ * adjoint Kraus set K_s^dagger to Psi and, in the inverse form, the inverse
+ * of its 64 x 64 superoperator, computed on the host at circuit creation, to
+ * Phi); batches refuse such circuits (VQC_ERR_UNSUPPORTED). */
 vqc_status vqc_apply_channel(vqc_state s, int m, const int *qubits, int n_kraus,
                              const vqc_c128 *kraus);
 

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -241,10 +242,13 @@ struct Deriv {
 struct Elem {
   int kind;
   int nq;
-  int q[4];    // global bits (vec(rho) bits for mixed)
+  int q[8];    // global bits (vec(rho) bits for mixed)
   int mat;     // matrix offset (c128 units), -1 if none
   bool inv = false;  // not unitary: its inverse is stored right after the matrix
   std::vector<Deriv> d;
+  // GK_KRAUS3: offsets in the circuit's constant data of the Kraus set, its
+  // adjoint set (K_s^dagger) and the inverse 64 x 64 superoperator; count
+  int kd = -1, kda = -1, sinv = -1, nk = 0;
   uint64_t mask() const {
     uint64_t m = 0;
     for (int i = 0; i < nq; i++) m |= 1ull << q[i];
@@ -260,6 +264,8 @@ struct PassH {
   bool moves = false;       // output layout differs from the input layout
   int src = 0, dst = 0;     // 0: the state's buffer, 1: the circuit's scratch state
   int lowfree = 0;          // DPass.lowfree as uploaded
+  int special = -1;         // elem of a pass run by its own kernel (GK_KRAUS3), else -1
+  int sk[3] = {0, 0, 0}, sb[3] = {0, 0, 0};  // its ket and bra bits in the pass's layout
   struct Stage {
     int rbit[4];
     std::vector<int> elems;  // indices into elems
@@ -410,13 +416,27 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
     L = Ln;
   };
   while (!rem.empty()) {
+    if (E[rem.front()].kind == GK_KRAUS3) {
+      // a three-qubit channel: a pass of its own, in place, layout unchanged
+      PassH ph;
+      ph.K = 0;
+      ph.special = rem.front();
+      const Elem &e = E[ph.special];
+      for (int t = 0; t < 3; t++) {
+        ph.sk[t] = pos[e.q[t]];
+        ph.sb[t] = pos[e.q[t + 3]];
+      }
+      P.passes.push_back(ph);
+      rem.erase(rem.begin());
+      continue;
+    }
     uint64_t tile = reg_only ? 0 : L;
     uint64_t blocked = 0;
     int nvar = 0;
     std::vector<int> chosen, left;
     for (int i : rem) {
       const uint64_t m = E[i].mask();
-      if (m & blocked) { blocked |= m; left.push_back(i); continue; }
+      if (E[i].kind == GK_KRAUS3 || (m & blocked)) { blocked |= m; left.push_back(i); continue; }
       const uint64_t nt = tile | m;
       const int nd = (int)E[i].d.size();
       if (popc(nt) <= TK && (max_var <= 0 || nvar + nd <= max_var)) {
@@ -542,7 +562,7 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
   if (moving & 1) {
     bool fixed = false;
     for (PassH &ph : P.passes)
-      if (!ph.moves) { ph.moves = true; fixed = true; break; }  // run one in-place pass out of place
+      if (!ph.moves && ph.special < 0) { ph.moves = true; fixed = true; break; }  // run one in-place pass out of place
     if (!fixed) {
       empty_pass();
       P.passes.back().moves = true;
@@ -576,6 +596,8 @@ struct vqc_circuit_s {
   double jit_ms = 0;        // run-time compile (or cache load) of the specialised passes
   bool jit_cached = false;
   int live_batches = 0;     // batches holding pointers into this circuit's tables
+  int n_special = 0;        // three-qubit channels (passes of their own)
+  double special_kappa = 0; // their largest superoperator condition number
   int n, nbits;
   vqc_kind kind;
   int n_params;
@@ -716,6 +738,89 @@ DRecipe sub_recipe(const vqc_op &op, int data_off, int n_data) {
   return r;
 }
 
+// A three-qubit Kraus set K_s (row-major 8 x 8 blocks at cdata[off]) as a
+// special op: its adjoint set K_s^dagger (the adjoint superoperator is the
+// Kraus sum of the K_s^dagger) and the inverse of its 64 x 64 superoperator
+// S[(x + 8 y)][(x' + 8 y')] = sum_s K_s[x][x'] conj(K_s[y][y']) (Gauss-Jordan,
+// partial pivoting), appended to the constant data; the 1-norm condition
+// number ||S|| ||S^-1|| bounds the inverse-form sweep (infinite if singular).
+void lower_kraus3(vqc_circuit c, const vqc_op &op, int off, int n_data, Elem &e) {
+  using cd = std::complex<double>;
+  const int nk = n_data / 64;
+  std::vector<cd> K((size_t)nk * 64);
+  for (int i = 0; i < nk * 64; i++) K[i] = cd(c->cdata[off + i].x, c->cdata[off + i].y);
+  e.kind = GK_KRAUS3;
+  e.nq = 6;
+  const int n = c->n;
+  for (int t = 0; t < 3; t++) {
+    e.q[t] = op.qubits[t];
+    e.q[t + 3] = op.qubits[t] + n;
+  }
+  e.mat = -1;
+  e.kd = off;
+  e.nk = nk;
+  e.kda = (int)c->cdata.size();
+  for (int k = 0; k < nk; k++)
+    for (int r = 0; r < 8; r++)
+      for (int col = 0; col < 8; col++) {
+        const cd v = std::conj(K[k * 64 + col * 8 + r]);
+        c->cdata.push_back(make_double2(v.real(), v.imag()));
+      }
+  std::vector<cd> S(4096, cd(0, 0)), A(4096), I(4096, cd(0, 0));
+  for (int k = 0; k < nk; k++)
+    for (int x = 0; x < 8; x++)
+      for (int y = 0; y < 8; y++)
+        for (int x2 = 0; x2 < 8; x2++)
+          for (int y2 = 0; y2 < 8; y2++)
+            S[(x + 8 * y) * 64 + (x2 + 8 * y2)] += K[k * 64 + x * 8 + x2] * std::conj(K[k * 64 + y * 8 + y2]);
+  A = S;
+  for (int i = 0; i < 64; i++) I[i * 64 + i] = 1.0;
+  bool singular = false;
+  for (int col = 0; col < 64 && !singular; col++) {
+    int piv = col;
+    for (int r = col + 1; r < 64; r++)
+      if (std::abs(A[r * 64 + col]) > std::abs(A[piv * 64 + col])) piv = r;
+    if (std::abs(A[piv * 64 + col]) == 0.0) { singular = true; break; }
+    if (piv != col)
+      for (int k = 0; k < 64; k++) {
+        std::swap(A[piv * 64 + k], A[col * 64 + k]);
+        std::swap(I[piv * 64 + k], I[col * 64 + k]);
+      }
+    const cd inv = 1.0 / A[col * 64 + col];
+    for (int k = 0; k < 64; k++) {
+      A[col * 64 + k] *= inv;
+      I[col * 64 + k] *= inv;
+    }
+    for (int r = 0; r < 64; r++) {
+      if (r == col) continue;
+      const cd f = A[r * 64 + col];
+      if (f == cd(0, 0)) continue;
+      for (int k = 0; k < 64; k++) {
+        A[r * 64 + k] -= f * A[col * 64 + k];
+        I[r * 64 + k] -= f * I[col * 64 + k];
+      }
+    }
+  }
+  double kappa = std::numeric_limits<double>::infinity();
+  if (!singular) {
+    auto norm1 = [](const std::vector<cd> &M) {
+      double best = 0;
+      for (int col = 0; col < 64; col++) {
+        double sum = 0;
+        for (int r = 0; r < 64; r++) sum += std::abs(M[r * 64 + col]);
+        best = std::max(best, sum);
+      }
+      return best;
+    };
+    kappa = norm1(S) * norm1(I);
+    if (!std::isfinite(kappa)) kappa = std::numeric_limits<double>::infinity();
+  }
+  e.sinv = (int)c->cdata.size();
+  for (int i = 0; i < 4096; i++) c->cdata.push_back(make_double2(singular ? 0.0 : I[i].real(), singular ? 0.0 : I[i].imag()));
+  c->special_kappa = std::max(c->special_kappa, kappa);
+  c->n_special++;
+}
+
 vqc_status lower(vqc_circuit c) {
   const int n = c->n;
   const bool mixed = c->kind == VQC_MIXED;
@@ -789,6 +894,12 @@ vqc_status lower(vqc_circuit c) {
         j = j2 - 1;
         continue;
       }
+    }
+    if (is_channel(op.type) && m == 3) {
+      Elem e;
+      lower_kraus3(c, op, data_off, n_data, e);
+      c->elems.push_back(e);
+      continue;
     }
     if (is_channel(op.type)) {
       Elem e;
@@ -1519,6 +1630,30 @@ hipError_t run_passes(vqc_circuit c, Plan &P, int mode, c128 *a, c128 *b, const 
   c128 *bufb[2] = {b, c->scratch2.as<c128>()};
   for (int k = 0; k < p1 - p0; k++) {
     const int p = dir > 0 ? p0 + k : p1 - 1 - k;
+    if (P.passes[p].special >= 0) {
+      // a three-qubit channel (its own kernel, in place; the layout is the
+      // same before and after, so the current buffers are the pass's source)
+      const PassH &ph = P.passes[p];
+      const Elem &e = c->elems[ph.special];
+      const c128 *cd = c->d_cdata;
+      c128 *phi = pingpong ? (mode == 0 ? bufs[ph.src] : bufs[ph.dst]) : a;
+      c128 *psi = pingpong && mode != 0 ? bufb[ph.dst] : b;
+      hipError_t e2 = hipSuccess;
+      if (mode == 0) {
+        if (b && !pingpong) {  // out of place: the channel on a copy
+          e2 = launch_copy(b, a, uint64_t(1) << c->nbits, st);
+          phi = b;
+        }
+        if (e2 == hipSuccess) e2 = launch_block6(phi, c->nbits, ph.sk, ph.sb, cd + e.kd, e.nk, 0, st);
+      } else {
+        // Phi <- M^{-1} Phi (inverse forms), Psi <- M^dagger Psi (every form;
+        // the adjoint of the Kraus sum is the sum over the K_s^dagger)
+        if (mode == 1 || mode == 3) e2 = launch_block6(phi, c->nbits, ph.sk, ph.sb, cd + e.sinv, 0, 1, st);
+        if (e2 == hipSuccess) e2 = launch_block6(psi, c->nbits, ph.sk, ph.sb, cd + e.kda, e.nk, 0, st);
+      }
+      if (e2 != hipSuccess) return e2;
+      continue;
+    }
     if (pingpong) {
       const PassH &ph = P.passes[p];
       if (mode == 0) {
@@ -2336,7 +2471,7 @@ vqc_status vqc_circuit_create(vqc_circuit *out, int n, vqc_kind kind, int n_ops,
   if (tune) c->tune = *tune;
   std::deque<std::vector<vqc_c128>> store;  // matrices of expanded ops, alive through lowering
   for (int j = 0; j < n_ops; j++) {
-    if (ops[j].n_qubits == 3) {
+    if (ops[j].n_qubits == 3 && ops[j].type != VQC_KRAUS) {
       vqc_status st = expand_gate3(ops[j], c->ops, store);
       if (st) return st;
     } else {
@@ -2499,6 +2634,7 @@ static vqc_status backward_impl(vqc_circuit c, const double *theta, vqc_state s,
     VQC_TRY(c->psi1.ensure(N * sizeof(c128)));
     c128 *psi = c->psi1.as<c128>();
     VQC_TRY(build_mats(c, nullptr, nullptr, 1, theta, mats, st));
+    if (c->n_special && !(c->special_kappa <= max_cond)) return VQC_ERR_ILL_CONDITIONED;
     if (!c->inv_list.empty()) {
       unsigned long long *kb = c->dinv.as<unsigned long long>();
       VQC_TRY(hipMemsetAsync(kb, 0, sizeof(*kb), st));
@@ -3022,6 +3158,7 @@ vqc_status vqc_batch_create(vqc_batch *out, int B, const vqc_circuit *circuits, 
     if (circuits[i]->n_params > 0 && (!thetas || !thetas[i])) return VQC_ERR_ARG;
     const vqc_circuit c = circuits[i], c0 = circuits[0];
     if (c->kind != c0->kind) return VQC_ERR_KIND;
+    if (c->n_special > 0) return VQC_ERR_UNSUPPORTED;  // three-qubit channels: single circuits only
     const Plan &A = batch_adj(c), &A0 = batch_adj(c0);
     if (c->fwd.reg_only != c0->fwd.reg_only || c->fwd.K != c0->fwd.K || c->fwd.R != c0->fwd.R ||
         c->fwd.d4 != c0->fwd.d4 || A.K != A0.K || A.R != A0.R || A.reg_only != A0.reg_only || A.d4 != A0.d4)

@@ -663,19 +663,25 @@ __global__ void __launch_bounds__(256) k_gm(c128 *__restrict__ psi, int nbits, i
   }
 }
 
-// three-qubit Kraus channel on vec(rho), Eq. (channel2) applied term by term:
-// rho' = sum_s K_s rho K_s^dagger on the 8 x 8 block of ket bits (q0, q1, q2)
-// and bra bits (q0 + n, q1 + n, q2 + n), q0 = bit 0 of the local index.  One
-// wave per block: lane a + 8 b holds rho[a][b]; the block goes through LDS so
-// each lane forms sum_{c,d} K_s[a][c] rho[c][d] conj(K_s[b][d]) for its own
-// (a, b).  K: n_kraus row-major 8 x 8 matrices.  The loop trip count is
-// block-uniform (waves past the last block idle through the barriers).
-__global__ void __launch_bounds__(256) k_kraus3(c128 *__restrict__ v, int nbits, int n, int4 q,
-                                                const c128 *__restrict__ K, int nk) {
+// three-qubit channel on vec(rho), Eq. (channel2), on the 8 x 8 blocks of rho
+// with ket bits qk (x, y, z: local bits 0, 1, 2) and bra bits qb (physical
+// positions; qb = qk + n in the standard layout).  One wave per block: lane
+// a + 8 b holds rho[a][b]; the block goes through LDS and each lane forms its
+// own entry of
+//   dense = 0: sum_s K_s rho K_s^dagger (the Kraus sum term by term,
+//              sum_{c,d} K_s[a][c] rho[c][d] conj(K_s[b][d]); K: nk row-major
+//              8 x 8 matrices)
+//   dense = 1: sum_{l'} S[a + 8 b][l'] v_{l'}, S a row-major 64 x 64
+//              superoperator in the same index order (used for the inverse
+//              of a channel's superoperator)
+// The loop trip count is block-uniform (waves past the last block idle
+// through the barriers).
+__global__ void __launch_bounds__(256) k_kraus3(c128 *__restrict__ v, int nbits, int4 qk, int4 qb,
+                                                const c128 *__restrict__ K, int nk, int dense) {
   __shared__ c128 xs[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int a = lane & 7, b = lane >> 3;
-  const int pos[6] = {q.x, q.y, q.z, q.x + n, q.y + n, q.z + n};
+  const int pos[6] = {qk.x, qk.y, qk.z, qb.x, qb.y, qb.z};
   int srt[6];
   for (int i = 0; i < 6; i++) srt[i] = pos[i];
   for (int i = 0; i < 6; i++)
@@ -695,7 +701,10 @@ __global__ void __launch_bounds__(256) k_kraus3(c128 *__restrict__ v, int nbits,
     if (ok) xs[w][lane] = v[base | off];
     __syncthreads();
     c128 y = make_double2(0.0, 0.0);
-    if (ok) {
+    if (ok && dense) {
+      const c128 *Sr = K + 64 * lane;
+      for (int l = 0; l < 64; l++) y = cfma(Sr[l], xs[w][l], y);
+    } else if (ok) {
       for (int s = 0; s < nk; s++) {
         const c128 *Ks = K + 64 * s;
         for (int c = 0; c < 8; c++) {
@@ -1065,10 +1074,16 @@ hipError_t launch_gm(c128 *psi, int nbits, int m, const int *q, const c128 *M, h
 }
 
 hipError_t launch_kraus3(c128 *v, int nbits, int n, const int *q, const c128 *K, int nk, hipStream_t st) {
-  if (nbits < 6 || nk < 1) return hipErrorInvalidValue;
-  const int4 qq = make_int4(q[0], q[1], q[2], 0);
+  const int qb[3] = {q[0] + n, q[1] + n, q[2] + n};
+  return launch_block6(v, nbits, q, qb, K, nk, 0, st);
+}
+
+hipError_t launch_block6(c128 *v, int nbits, const int *qk, const int *qb, const c128 *K, int nk, int dense,
+                         hipStream_t st) {
+  if (nbits < 6 || (!dense && nk < 1)) return hipErrorInvalidValue;
+  const int4 k4 = make_int4(qk[0], qk[1], qk[2], 0), b4 = make_int4(qb[0], qb[1], qb[2], 0);
   const dim3 grid(grid_for(1ull << (nbits - 6), 4));
-  hipLaunchKernelGGL(k_kraus3, grid, dim3(256), 0, st, v, nbits, n, qq, K, nk);
+  hipLaunchKernelGGL(k_kraus3, grid, dim3(256), 0, st, v, nbits, k4, b4, K, nk, dense);
   return hipGetLastError();
 }
 

@@ -59,7 +59,10 @@ enum GateKind : int8_t {
   GK_DEPOL4 = 22,
   // 8x8 on three register bits (a general three-qubit gate; local index
   // b_{q0} + 2 b_{q1} + 4 b_{q2})
-  GK_DENSE3 = 23
+  GK_DENSE3 = 23,
+  // a three-qubit channel on vec(rho) (6 bits): not a register op; the
+  // planner gives it a pass of its own, run by k_kraus3
+  GK_KRAUS3 = 24
 };
 // DGate.nd: derivative count in the low byte; this bit set when the op's
 // derivatives are generator kinds (taken on Phi before the op is undone)
@@ -258,6 +261,10 @@ hipError_t launch_g1(c128 *psi, int nbits, int q, const c128 *M, int kind, hipSt
 hipError_t launch_g2(c128 *psi, int nbits, int q0, int q1, const c128 *M, int kind, hipStream_t st);
 hipError_t launch_gm(c128 *psi, int nbits, int m, const int *q, const c128 *M, hipStream_t st);
 hipError_t launch_kraus3(c128 *v, int nbits, int n, const int *q, const c128 *K, int nk, hipStream_t st);
+// three-qubit channel on ket bits qk / bra bits qb (physical positions): the
+// Kraus sum of nk matrices K (dense = 0) or a dense 64 x 64 superoperator K
+hipError_t launch_block6(c128 *v, int nbits, const int *qk, const int *qb, const c128 *K, int nk, int dense,
+                         hipStream_t st);
 hipError_t launch_init_basis0(c128 *v, uint64_t N, hipStream_t st);
 hipError_t launch_fill_zero(c128 *v, uint64_t N, hipStream_t st);
 hipError_t launch_copy(c128 *dst, const c128 *src, uint64_t N, hipStream_t st);

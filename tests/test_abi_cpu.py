@@ -88,12 +88,14 @@ def test_circuit_create_rejects_bad_ops_on_host(L):
     bad = [np.eye(2) * 0.9, np.eye(2) * 0.1]
     assert _create(L, 2, [Op("kraus", (0,), (), (), bad)], mixed=True) == -5  # not trace preserving
     assert _create(L, 2, [Op("matrix", (0, 1, 2), (), (), np.eye(8))]) == -2  # qubit 2 of 2
-    assert _create(L, 3, [Op("matrix", (0, 1, 2), (), (), np.eye(8))]) == -3  # general 3q: single ops only
+    assert _create(L, 3, [Op("kraus", (0, 1, 2), (), (), [np.eye(8)])]) == -4  # a channel on a pure circuit
+    assert _create(L, 3, [Op("matrix", (0, 1, 2), (), (), np.eye(4))]) == -1  # 8 x 8 data needed
     assert _create(L, 4, [Op("matrix", (0, 1, 2, 3), (), (), np.eye(16))]) == -3  # m = 4
     assert _create(L, 3, [Op("toffoli", (0, 1))]) == -1                         # arity
     assert _create(L, 3, [Op("ccontrol", (0, 1, 2), (), (), np.eye(2) * 2)]) == -10  # V needs a unitary U
     K3 = [np.eye(8)]
-    assert _create(L, 3, [Op("kraus", (0, 1, 2), (), (), K3)], mixed=True) == -3  # no 3q channels
+    K3bad = [1.01 * k for k in K3]
+    assert _create(L, 3, [Op("kraus", (0, 1, 2), (), (), K3bad)], mixed=True) == -5  # 3q channel, not CPTP
 
 
 def test_state_init_rejects_bad_sizes_on_host(L):
