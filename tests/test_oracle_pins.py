@@ -558,6 +558,43 @@ def test_noiseless_mixed_gradient_equals_pure(oracle_mod):
     assert np.max(np.abs(gp - gm)) < 1e-13
 
 
+def four_term_shift(f, th, k):
+    """d f / d theta_k for a parameter of a controlled rotation CR_P(theta)
+    = |0><0| (x) I + |1><1| (x) exp(-i theta P / 2): the generator
+    |1><1| (x) P / 2 has the eigenvalues -1/2, 0, 1/2, for which the exact
+    four-term rule is d1 [f(+pi/2) - f(-pi/2)] - d2 [f(+3pi/2) - f(-3pi/2)],
+    d1,2 = (sqrt 2 +- 1) / (4 sqrt 2) (Anselmetti et al. 2021)."""
+    d1 = (math.sqrt(2) + 1) / (4 * math.sqrt(2))
+    d2 = (math.sqrt(2) - 1) / (4 * math.sqrt(2))
+
+    def at(a):
+        t = np.array(th, float)
+        t[k] += a
+        return f(t)
+    return d1 * (at(math.pi / 2) - at(-math.pi / 2)) - d2 * (at(1.5 * math.pi) - at(-1.5 * math.pi))
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_controlled_rotations_four_term_shift_rule(oracle_mod, mixed):
+    from paper_2406_19212_amd.workloads import Op
+    n = 3
+    ops = [Op("h", (0,)), Op("ry", (1,), (0.3,)), Op("crx", (0, 1), (0.0,), (0,)), Op("rx", (2,), (0.7,)),
+           Op("cnot", (1, 2)), Op("cry", (2, 0), (0.0,), (1,)), Op("crz", (1, 2), (0.0,), (2,))]
+    if mixed:
+        ops.insert(4, Op("depolarizing", (1,), (0.05,)))
+        ops.append(Op("amplitude_damping", (0,), (0.1,)))
+    th = np.array([0.9, -1.3, 2.2])
+    terms = W.tfim(n, 0.7) + [W.pauli_string({0: "y", 1: "y"}, 0.3)]
+    if mixed:
+        _, g = oracle_mod.grad_mixed(n, ops, th, terms)
+        f = lambda t: loss_mixed(oracle_mod, n, ops, t, terms)
+    else:
+        _, g, _ = oracle_mod.grad_pure(n, ops, th, terms)
+        f = lambda t: oracle_mod.expectation(oracle_mod.run(n, ops, t), n, terms).real
+    want = np.array([four_term_shift(f, th, k) for k in range(3)])
+    assert np.max(np.abs(g - want)) < 1e-12
+
+
 # ------------------------------------------- noisy gradient, inverse form
 
 @pytest.mark.parametrize("D", [2, 4, 16, 64])
