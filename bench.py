@@ -29,11 +29,18 @@ Also reported:
   (forward, backward with the gradient-matching term, Adam), and the BF16
   MFMA matrix product in TFLOP/s against the dense BF16 peak, at the
   network's layer shape and at 4096^3;
+  and the optimiser comparison: wall-clock to a stated energy gap from one
+  theta_0 for plain exact-gradient Adam over a step-size sweep against the
+  surrogate-assisted loop (its labels and training included);
+* the 12-qubit brick-wall circuit (20 layers of Rx, Ry, Rz on every qubit and
+  CZ on alternating neighbour pairs, final state and <Z_0>): time per run;
+* the per-gate sweep: H, Rx and CNOT alone on states of 14 to 30 qubits, on
+  the lowest and the highest qubit, as GB/s against algorithmic bytes;
 * cpu_baseline: the plain C oracle on this host, timed on a bounded prefix of
-  the same 28-qubit circuit.
+  the same 28-qubit circuit with all host threads, and with one.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-vqe] [--no-noisy]
-                       [--no-surrogate]
+                       [--no-surrogate] [--no-sweep]
        python bench.py --copy-calibration   (only a plain device copy of known
                                               size, for scaling HBM counters)
 """
@@ -68,6 +75,7 @@ def parse():
     ap.add_argument("--no-vqe", action="store_true")
     ap.add_argument("--no-noisy", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
@@ -111,21 +119,28 @@ def copy_calibration(torch):
 
 def cpu_baseline(ops, n, seconds):
     """The oracle as it stands, on a prefix of the circuit (one gate at a time
-    until `seconds` of work), reported in the same unit."""
+    until `seconds` of work), reported in the same unit; then the same with
+    one thread for half that time."""
     import oracle
-    cores = len(os.sched_getaffinity(0))
-    oracle.set_threads(cores)
-    st = oracle.initial_state(n)
-    done, t0 = 0, time.perf_counter()
-    tab_ops = list(ops)
-    while done < len(tab_ops) and time.perf_counter() - t0 < seconds:
-        oracle.apply_op_inplace(st, n, tab_ops[done])
-        done += 1
-    dt = time.perf_counter() - t0
-    del st
-    return {"value": done / dt, "unit": "gate-apps/s", "cores": oracle.get_threads(), "kind": "oracle",
+
+    def timed(threads, secs):
+        oracle.set_threads(threads)
+        st = oracle.initial_state(n)
+        done, t0 = 0, time.perf_counter()
+        while done < len(ops) and time.perf_counter() - t0 < secs:
+            oracle.apply_op_inplace(st, n, ops[done])
+            done += 1
+        dt = time.perf_counter() - t0
+        del st
+        return done, dt, oracle.get_threads()
+    ops = list(ops)
+    done, dt, used = timed(len(os.sched_getaffinity(0)), seconds)
+    d1, dt1, used1 = timed(1, seconds / 2)
+    return {"value": done / dt, "unit": "gate-apps/s", "cores": used, "kind": "oracle",
             "sample": "first %d of %d gates of the same 28-qubit circuit, one full-state pass each, %.1f s"
-                      % (done, len(tab_ops), dt)}
+                      % (done, len(ops), dt),
+            "single_thread": {"value": d1 / dt1, "cores": used1,
+                              "sample": "first %d gates of the same circuit, %.1f s" % (d1, dt1)}}
 
 
 def vqe_batched(torch, steps):
@@ -170,6 +185,20 @@ def vqe_batched(torch, steps):
         torch.cuda.synchronize()
         out["batched_grads_per_s"] = Bn * steps / (time.perf_counter() - t0)
         out["speedup_vs_plain"] = out["batched_grads_per_s"] / out["plain_grads_per_s"]
+        # algorithmic bytes of one replay, per item: |0..0> written (16 B/amp),
+        # forward passes (read + write, 32 B/amp), the energy with the seed
+        # H|psi> (read psi, write Phi: 32 B/amp), adjoint passes over Phi and
+        # Psi (64 B/amp); the gradient reduction's partials are negligible
+        cs = circ.stats()
+        nf, na = cs["n_passes"], cs["n_adj_passes"]
+        per_item = float(1 << n) * (16 + 32 * nf + 32 + 64 * na)
+        replay_s = Bn / out["batched_grads_per_s"]
+        ach = Bn * per_item / replay_s / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(ach / HBM_PEAK_GBS, 4), "forward_passes": nf, "adjoint_passes": na,
+                           "alg_bytes_per_replay": Bn * per_item, "replay_ms": round(1e3 * replay_s, 3),
+                           "specialised": bool(cs["n_jit_passes"] and cs["n_jit_adj_passes"]),
+                           "scope": "whole replay (every kernel) against its algorithmic bytes"}
     except Exception as e:  # report, do not hide
         out["batched_error"] = str(e)
     out.update({"workload": "hea-20q-40layers-1600params-tfim-batch64", "unit": "grads/s"})
@@ -232,8 +261,72 @@ def surrogate_leg(torch):
         gem[name] = {"ms": round(ms, 4), "TFLOP_per_s": round(tf, 2), "frac": round(tf / BF16_MFMA_PEAK_TFLOPS, 4)}
     out["gemm_bf16"] = gem
     out["gemm_peak_TFLOP_per_s"] = BF16_MFMA_PEAK_TFLOPS
-    del net
+    del net, theta, E, G, x, e, g
+    torch.cuda.empty_cache()
+    out["optimiser"] = S.compare()
     return out
+
+
+def config0(torch, steps):
+    """The 12-qubit brick-wall circuit: 20 layers of Rx, Ry, Rz on every qubit
+    then CZ on alternating neighbour pairs; one run = reset, the circuit, the
+    final state left in HBM and <Z_0> read back."""
+    from paper_2406_19212_amd import Circuit, State
+    from paper_2406_19212_amd import workloads as W
+    n, L = 12, 20
+    ops, theta = W.brickwall(n, L, W.CONFIG_SEED[0])
+    circ = Circuit(n, ops, n_params=len(theta))
+    th = torch.tensor(theta, dtype=torch.float64, device="cuda")
+    st = State(n)
+    z0 = [W.pauli_string({0: "z"}, 1.0)]
+
+    def run():
+        st.reset()
+        circ.apply(st, th)
+        return st.expectation(z0).real
+    for _ in range(3):
+        run()
+    torch.cuda.synchronize()
+    reps = max(50, 10 * steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        z = run()
+    dt = time.perf_counter() - t0
+    return {"workload": "brickwall-12q-20layers-rxryrz-cz", "gates": len(ops), "passes": circ.stats()["n_passes"],
+            "ms_per_run": round(1e3 * dt / reps, 4), "gate_apps_per_s": round(len(ops) * reps / dt, 1),
+            "z0": z, "runs": reps}
+
+
+def gate_sweep(torch):
+    """H, Rx(0.3) and CNOT applied alone (one kernel launch each) to states
+    of 14 to 30 qubits, on the lowest qubit (CNOT: control 0, target 1) and
+    on the highest (control n-2, target n-1): HIP events around repeated
+    launches.  Algorithmic bytes: H and Rx read and write every amplitude (32
+    B/amp); CNOT reads and writes only the control = 1 half (16 B/amp)."""
+    from paper_2406_19212_amd import State
+    from paper_2406_19212_amd.workloads import Op
+    rows = []
+    for n in range(14, 31):
+        st = State(n)
+        N = 1 << n
+        reps = 50 if n < 24 else (10 if n < 29 else 4)
+        for name, mk, bpa in (("h", lambda q: Op("h", (q,)), 32.0), ("rx", lambda q: Op("rx", (q,), (0.3,)), 32.0),
+                              ("cnot", lambda q: Op("cnot", (q, q + 1)), 16.0)):
+            for where, q in (("low", 0), ("high", n - 1 if name != "cnot" else n - 2)):
+                op = mk(q)
+                st.apply_op(op)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    st.apply_op(op)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                rows.append([n, name, where, round(ms * 1e3, 2), round(bpa * N / (ms * 1e-3) / 1e9, 1)])
+        del st
+        torch.cuda.empty_cache()
+    return {"columns": ["n", "gate", "qubit", "us", "GB_per_s"], "rows": rows,
+            "alg_bytes_per_amp": {"h": 32, "rx": 32, "cnot": 16}}
 
 
 def single_ops(torch, st, n):
@@ -437,6 +530,10 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_surrogate:
         rec["surrogate"] = surrogate_leg(torch)
+        torch.cuda.empty_cache()
+    rec["brickwall12"] = config0(torch, args.steps)
+    if not args.no_sweep:
+        rec["gate_sweep"] = gate_sweep(torch)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(ops, n, args.cpu_seconds)

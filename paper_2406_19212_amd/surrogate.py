@@ -27,6 +27,12 @@ from .api import Batch, Circuit, State
 from .mlp import MLP
 
 
+# Exact ground energy of the open transverse-field Ising chain with n = 16,
+# J = h = 1 (free-fermion solution; the tests pin it to Lanczos on the full
+# 2^16-dimensional Hamiltonian).
+GROUND_E_TFIM16 = -20.016387900485142
+
+
 class Simulator:
     """Energy and adjoint gradient of the ansatz for one theta or a batch."""
 
@@ -197,6 +203,65 @@ def optimize_surrogate(sim: Simulator, net: MLP, scale, theta0, steps, lr, K=10,
             log["fallback"] += 1
         hist.append((time.perf_counter() - t0, sim.evals, e))
     return theta, hist, log
+
+
+def time_to(hist, level, offset=0.0):
+    """First (seconds + offset, exact evaluations) of an optimiser history
+    at or below `level`, else None."""
+    for sec, ev, e in hist:
+        if e <= level:
+            return {"seconds": round(sec + offset, 4), "evals": int(ev)}
+    return None
+
+
+def compare(n=16, layers=10, h=1.0, e0=GROUND_E_TFIM16, gap=0.1, lrs=(0.01, 0.02, 0.05, 0.1, 0.2, 0.3),
+            plain_steps=1500, samples=50000, epochs=30, sur_steps=300, sur_lr=0.2, finetune=5, hidden=512,
+            seed=240619216):
+    """Wall-clock to E - e0 <= gap from one theta_0: plain exact-gradient Adam
+    at each step size in `lrs` (the target is stated as one this sweep
+    reaches) against the surrogate-assisted loop, whose time includes
+    generating its labels and training its network."""
+    rec = {"workload": "hea-%dq-%dlayers-tfim-h%g" % (n, layers, h), "e0": e0, "target_gap": gap,
+           "plain_steps_max": plain_steps}
+    sim = Simulator(n, layers, h)
+    theta0 = torch.tensor(W.theta_uniform(seed + 2, 1, sim.P)[0], device="cuda")
+    sim.energy_grad(theta0)  # first-call set-up outside the timings
+    level = e0 + gap
+    sweep = {}
+    for lr in lrs:
+        sim.evals = 0
+        _, hp = optimize_plain(sim, theta0, plain_steps, lr, target=level)
+        sweep[str(lr)] = {"to_target": time_to(hp, level), "lowest_gap": min(x[2] for x in hp) - e0,
+                          "evals": int(hp[-1][1]), "seconds": round(hp[-1][0], 4)}
+    rec["plain_sweep"] = sweep
+    reached = [(v["to_target"]["seconds"], lr) for lr, v in sweep.items() if v["to_target"]]
+    rec["best_plain"] = dict(lr=float(min(reached)[1]), **sweep[min(reached)[1]]["to_target"]) if reached else None
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    theta, E, G = generate(sim, samples, seed)
+    torch.cuda.synchronize()
+    labels_s = time.perf_counter() - t
+    scale = (float(E.mean()), float(E.std()) + 1e-12)
+    net = MLP(sim.P, hidden, hidden, max_batch=512)
+    init_params(net, seed + 1)
+    t = time.perf_counter()
+    train(net, theta, E, G, epochs=epochs, scale=scale)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    del theta, E, G
+    sim.evals = 0
+    _, hs, log = optimize_surrogate(sim, net, scale, theta0, sur_steps, sur_lr, finetune=finetune, target=level)
+    rec["surrogate"] = {"lr": sur_lr, "finetune_epochs": finetune, "samples": samples, "epochs": epochs,
+                        "labels_s": round(labels_s, 4), "train_s": round(train_s, 4),
+                        "to_target": time_to(hs, level, labels_s + train_s),
+                        "lowest_gap": min(x[2] for x in hs) - e0, "evals": int(hs[-1][1]),
+                        "loop_s": round(hs[-1][0], 4), "accepted": log["accepted"], "fallback": log["fallback"]}
+    s_t = rec["surrogate"]["to_target"]
+    if rec["best_plain"] is None:
+        rec["winner"] = "surrogate" if s_t else "neither"
+    else:
+        rec["winner"] = "surrogate" if s_t and s_t["seconds"] < rec["best_plain"]["seconds"] else "plain"
+    return rec
 
 
 def run(n=16, layers=10, h=1.0, samples=50000, epochs=30, steps=200, lr=0.05, seed=240619216, target=None,

@@ -91,3 +91,11 @@ def test_lanczos_tfim_12():
     n = 12
     e = lanczos.ground_energy(n, W.tfim(n, 1.0))
     assert abs(e - lanczos.tfim_free_fermion(n, 1.0)) < 1e-10
+
+
+def test_surrogate_target_ground_energy():
+    """The surrogate experiment's stated ground energy (16-qubit open chain,
+    J = h = 1) is the free-fermion value, itself pinned to dense
+    diagonalisation and Lanczos above."""
+    from paper_2406_19212_amd.surrogate import GROUND_E_TFIM16
+    assert abs(lanczos.tfim_free_fermion(16, 1.0) - GROUND_E_TFIM16) < 1e-12
