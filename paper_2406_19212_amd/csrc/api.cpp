@@ -1111,6 +1111,90 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
 // and register bits, in program order) and the kernel vqc_jf<p>, which
 // instantiates jit_pass.h's driver for it.  The op parameters stay in the
 // item's op program, so one compiled plan serves every theta.
+// LDS bank layout of a specialised pass's tile.  Local index l sits at slot
+// (l & ~m) | N(l), m = 2^swb - 1 and N(l) the XOR of col[q] (swb bits) over
+// the set bits q of l: a bijection, linear over XOR.  An access of
+// consecutive lanes covers the banks once when the low bits of their slots
+// differ, i.e. when the columns of their lowest varying bits are
+// independent: for 16-byte elements (swb = 4) groups of 8 and of 16 lanes
+// (32 or 64 banks), for 8-byte elements (swb = 5, a tile exchanged as real
+// and imaginary halves) groups of 16 and 32.  The accesses are the stages'
+// (lanes over the bits outside the stage's register bits), the tile's load
+// (lanes over local bits 0..) and its store in the output layout (lanes over
+// lbo[0..]).  col starts as the interpreter's fixed swizzle (low bits ^=
+// bits 4..7 ^ bits 8..11) and a seeded random search replaces it when it
+// finds fewer conflicting accesses.
+std::vector<int> lds_swizzle(int K, int R, const PassH &ph, const std::vector<int> &lbo, int swb, uint64_t seed) {
+  std::vector<std::pair<std::vector<int>, int>> pats;  // lowest lane bits, accesses per lane
+  auto lanes_of = [&](const std::vector<int> &bits, int w) {
+    std::vector<int> v(bits.begin(), bits.begin() + std::min<size_t>(swb, bits.size()));
+    pats.emplace_back(v, w);
+  };
+  std::vector<int> id;
+  for (int q = 0; q < K - R; q++) id.push_back(q);
+  lanes_of(id, 1 << R);
+  lanes_of(std::vector<int>(lbo.begin(), lbo.begin() + (K - R)), 1 << R);
+  for (const auto &S : ph.stages) {
+    std::vector<int> lb;
+    for (int q = 0; q < K; q++) {
+      bool reg = false;
+      for (int i = 0; i < R; i++) reg = reg || S.rbit[i] == q;
+      if (!reg) lb.push_back(q);
+    }
+    lanes_of(lb, 2 << R);
+  }
+  auto indep = [](const int *v, int n, int mask) {
+    int rows[8], nr = 0;
+    for (int i = 0; i < n; i++) {
+      int x = v[i] & mask;
+      for (int r = 0; r < nr; r++) x = std::min(x, x ^ rows[r]);
+      if (!x) return false;
+      rows[nr++] = x;
+      std::sort(rows, rows + nr, [](int a, int b) { return a > b; });
+    }
+    return true;
+  };
+  const int full = (1 << swb) - 1, part = (1 << (swb - 1)) - 1;
+  auto cost = [&](const std::vector<int> &col) {
+    int c = 0;
+    for (const auto &pw : pats) {
+      int v[8];
+      const int n = (int)pw.first.size();
+      for (int i = 0; i < n; i++) v[i] = col[pw.first[i]];
+      if (!indep(v, n, full) || !indep(v, std::min(n, swb - 1), part)) c += pw.second;
+    }
+    return c;
+  };
+  std::vector<int> best(K);
+  for (int q = 0; q < K; q++) best[q] = q < swb ? 1 << q : 1 << (q & 3);
+  int bc = cost(best);
+  uint64_t x = seed * 0x9e3779b97f4a7c15ull + 0x632be59bd9b4e019ull;
+  std::vector<int> col(K);
+  for (int it = 0; it < 6000 && bc > 0; it++) {
+    for (int q = 0; q < K; q++) {
+      x ^= x << 13;
+      x ^= x >> 7;
+      x ^= x << 17;
+      col[q] = (int)(x >> 40) & full;
+    }
+    if (!indep(col.data(), std::min(K, swb), full)) continue;  // N must stay a bijection of each slot group
+    const int cc = cost(col);
+    if (cc < bc) {
+      bc = cc;
+      best = col;
+    }
+  }
+  return best;
+}
+
+// forward passes exchange the tile through LDS as real and imaginary halves
+// (half the LDS per block, so more resident blocks, for two more barriers
+// per stage change); VQC_JIT_FWD_SPLIT=0 keeps whole amplitudes
+bool jit_fwd_split() {
+  const char *e = std::getenv("VQC_JIT_FWD_SPLIT");
+  return !(e && e[0] == '0');
+}
+
 std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::string s) {
   char buf[512];
   auto arr = [&](const char *name, const std::vector<int> &v) {
@@ -1133,10 +1217,13 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
     }
     std::snprintf(buf, sizeof(buf),
                   "struct JP%zu {\n  static constexpr int K = %d, R = %d, NST = %d, PROG = %d, G0 = %d;\n"
-                  "  static constexpr bool DOUT = %s;\n",
-                  p, K, R, nst, P.prog, g, (ph.lowfree & 2) ? "true" : "false");
+                  "  static constexpr bool DIN = %s, DOUT = %s;\n",
+                  p, K, R, nst, P.prog, g, (ph.lowfree & 1) ? "true" : "false", (ph.lowfree & 2) ? "true" : "false");
     s += buf;
-    s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo);
+    const bool split = jit_fwd_split();
+    s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) +
+         arr("SWC", lds_swizzle(K, R, ph, lbo, split ? 5 : 4, 2 * p + 1));
+    s += split ? "  static constexpr int SWB = 5;\n" : "  static constexpr int SWB = 4;\n";
     const int rows = std::max(nst, 1);  // a pass without ops only moves qubits
     std::string rb = "  static constexpr int RBIT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
     std::string sr = "  static constexpr int SRT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
@@ -1183,9 +1270,9 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
     s += nst ? "    else return E;\n  }\n};\n" : "    return E;\n  }\n};\n";
     std::snprintf(buf, sizeof(buf),
                   "extern \"C\" __global__ void __launch_bounds__(%d) vqc_jf%zu(const DJob *__restrict__ jobs, "
-                  "int n_jobs, int64_t total_units, DOverride ov) {\n  jit_pass_fwd<JP%zu, %s>(jobs, n_jobs, "
+                  "int n_jobs, int64_t total_units, DOverride ov) {\n  jit_pass_fwd<JP%zu, %s, %s>(jobs, n_jobs, "
                   "total_units, ov);\n}\n",
-                  1 << (K - R), p, p, persist ? "true" : "false");
+                  1 << (K - R), p, p, persist ? "true" : "false", split ? "true" : "false");
     s += buf;
   }
   return s;
@@ -1239,7 +1326,8 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::strin
                   p, K, R, nst, P.prog, g0 + n_ops - 1, (int)vslot.size(), WS, NW,
                   (ph.lowfree & 2) ? "true" : "false", (ph.lowfree & 1) ? "true" : "false");
     s += buf;
-    s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("VSLOT", vslot);
+    s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("VSLOT", vslot) +
+         arr("SWC", lds_swizzle(K, R, ph, lbo, 4, 2 * p + 2)) + "  static constexpr int SWB = 4;\n";
     const int rows = std::max(nst, 1);
     std::string rb = "  static constexpr int RBIT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
     std::string sr = "  static constexpr int SRT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";

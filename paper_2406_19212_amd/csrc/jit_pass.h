@@ -19,6 +19,13 @@
 //   TQO[K], LBO[K]         output layout: physical bits in ascending order and
 //                          the tile-local bit stored at each
 //   RBIT[NST][R]           tile-local bit held in register bit i of a stage
+//   SRT[NST][R]            the same bits in ascending order
+//   SWC[K]                 LDS bank swizzle: tile-local index l is kept at
+//                          slot (l & ~15) | (XOR of SWC[q] over the set bits q
+//                          of l), chosen by the planner for this pass's access
+//                          patterns
+//   DIN                    the first stage holds none of the low bits: it
+//                          reads HBM directly
 //   DOUT                   the last stage holds none of the low bits and the
 //                          pass does not move qubits: it stores straight to HBM
 //   PROG                   c128 offset of the op program in the item's matrices
@@ -117,28 +124,138 @@ __device__ __forceinline__ DOp jop(c128 (&a)[1 << R], const DOp &E, const DOp *n
   return En;
 }
 
-// stages S .. NST-1 of one tile (template recursion keeps every stage's bit
-// layout a compile-time constant)
+// LDS slot of tile-local index l under the pass's bank swizzle; linear over
+// XOR, so the slot of base | o (disjoint bits) is jswz(base) ^ jswz(o) and a
+// compile-time o costs one XOR
+template <class P>
+__device__ __forceinline__ int jswz(int l) {
+  int n = 0;
+#pragma unroll
+  for (int q = 0; q < P::K; q++)
+    if (P::SWC[q]) n ^= ((l >> q) & 1) ? P::SWC[q] : 0;
+  return (l & ~((1 << P::SWB) - 1)) | n;
+}
+
+// tile-local index of lane t with zeros at stage S's register bits
 template <class P, int S>
-__device__ __forceinline__ void jit_stages(c128 *la, DOp E, const DOp *prog, cmat *MT, int t, uint64_t gbase,
+__device__ __forceinline__ int jbase(int t) {
+  int base = t;
+#pragma unroll
+  for (int i = 0; i < P::R; i++) base = ins0<int>(base, P::SRT[S][i]);
+  return base;
+}
+
+// tile-local offset of register j of stage S
+template <class P, int S>
+__device__ __forceinline__ constexpr int joff(int j) {
+  int o = 0;
+  for (int i = 0; i < P::R; i++)
+    if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
+  return o;
+}
+
+// Tile layouts over (lane t, register j): tile-local index lane(t) | reg(j).
+// The load layout (registers over the top R tile bits, lanes over the rest),
+// stage S's, and the store layout (lanes and registers in the order of the
+// output's physical bits).
+template <class P>
+struct JLoad {
+  __device__ static __forceinline__ int lane(int t) { return t; }
+  __device__ static __forceinline__ constexpr int reg(int j) { return j << (P::K - P::R); }
+};
+template <class P, int S>
+struct JStage {
+  __device__ static __forceinline__ int lane(int t) { return jbase<P, S>(t); }
+  __device__ static __forceinline__ constexpr int reg(int j) { return joff<P, S>(j); }
+};
+template <class P>
+struct JStore {
+  __device__ static __forceinline__ int lane(int t) {
+    int sl = 0;
+#pragma unroll
+    for (int i = 0; i < P::K - P::R; i++)
+      if ((t >> i) & 1) sl |= 1 << P::LBO[i];
+    return sl;
+  }
+  __device__ static __forceinline__ constexpr int reg(int j) {
+    int ol = 0;
+    for (int i = 0; i < P::R; i++)
+      if ((j >> i) & 1) ol |= 1 << P::LBO[P::K - P::R + i];
+    return ol;
+  }
+};
+
+template <bool SPLIT>
+struct JLdsT {
+  using T = c128;
+};
+template <>
+struct JLdsT<true> {
+  using T = double;
+};
+
+// The registers of every lane from layout X to layout Y through the LDS
+// tile.  SPLIT: the tile holds one double per amplitude and the real and
+// imaginary halves go through it one after the other.  A lane's first write
+// goes to the slots it read itself in the exchange before (X is that
+// exchange's Y), so no barrier is needed before it.
+template <class P, bool SPLIT, class X, class Y>
+__device__ __forceinline__ void jxch(typename JLdsT<SPLIT>::T *buf, c128 (&a)[1 << P::R], int t) {
+  constexpr int NR = 1 << P::R;
+  const int xs = jswz<P>(X::lane(t)), ys = jswz<P>(Y::lane(t));
+  if constexpr (!SPLIT) {
+#pragma unroll
+    for (int j = 0; j < NR; j++) buf[xs ^ jswz<P>(X::reg(j))] = a[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NR; j++) a[j] = buf[ys ^ jswz<P>(Y::reg(j))];
+  } else {
+    double re[NR];
+#pragma unroll
+    for (int j = 0; j < NR; j++) buf[xs ^ jswz<P>(X::reg(j))] = a[j].x;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NR; j++) re[j] = buf[ys ^ jswz<P>(Y::reg(j))];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NR; j++) buf[xs ^ jswz<P>(X::reg(j))] = a[j].y;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NR; j++) a[j] = make_double2(re[j], buf[ys ^ jswz<P>(Y::reg(j))]);
+  }
+}
+
+// the registers of the store layout to HBM (the pass's output layout)
+template <class P>
+__device__ __forceinline__ void jit_store_tile(const c128 (&a)[1 << P::R], gc128 *dst, int64_t tile, int t) {
+  constexpr int K = P::K, R = P::R, NR = 1 << R;
+  uint64_t gbo = (uint64_t)tile;
+#pragma unroll
+  for (int i = 0; i < K; i++) gbo = ins0<uint64_t>(gbo, P::TQO[i]);
+#pragma unroll
+  for (int i = 0; i < K - R; i++)
+    if ((t >> i) & 1) gbo |= 1ull << P::TQO[i];
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    uint64_t oj = 0;
+#pragma unroll
+    for (int i = 0; i < R; i++)
+      if ((j >> i) & 1) oj |= 1ull << P::TQO[K - R + i];
+    stg(&dst[gbo | oj], a[j]);
+  }
+}
+
+// stages S .. NST-1 of one tile; a holds stage S's registers on entry
+template <class P, bool SPLIT, int S>
+__device__ __forceinline__ void jit_stages(typename JLdsT<SPLIT>::T *buf, c128 (&a)[1 << P::R], DOp E,
+                                           const DOp *prog, cmat *MT, int t, uint64_t gbase, int64_t tile,
                                            gc128 *dst) {
-  if constexpr (S < P::NST) {
-    constexpr int K = P::K, R = P::R, NR = 1 << R;
-    int base = t;
-#pragma unroll
-    for (int i = 0; i < R; i++) base = ins0<int>(base, P::SRT[S][i]);
-    c128 a[NR];
-#pragma unroll
-    for (int j = 0; j < NR; j++) {
-      int o = 0;
-#pragma unroll
-      for (int i = 0; i < R; i++)
-        if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
-      a[j] = la[swz(base | o)];
-    }
-    E = P::template stage<S>(a, E, prog, MT);
-    if constexpr (S == P::NST - 1 && P::DOUT) {
+  constexpr int K = P::K, R = P::R, NR = 1 << R;
+  E = P::template stage<S>(a, E, prog, MT);
+  if constexpr (S == P::NST - 1) {
+    if constexpr (P::DOUT) {
       // the last stage's lanes run over the low tile bits: store to HBM
+      const int base = jbase<P, S>(t);
       uint64_t gb = gbase;
 #pragma unroll
       for (int i = 0; i < K; i++)
@@ -152,17 +269,12 @@ __device__ __forceinline__ void jit_stages(c128 *la, DOp E, const DOp *prog, cma
         stg(&dst[gb | go], a[j]);
       }
     } else {
-#pragma unroll
-      for (int j = 0; j < NR; j++) {
-        int o = 0;
-#pragma unroll
-        for (int i = 0; i < R; i++)
-          if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
-        la[swz(base | o)] = a[j];
-      }
-      __syncthreads();
-      jit_stages<P, S + 1>(la, E, prog, MT, t, gbase, dst);
+      jxch<P, SPLIT, JStage<P, S>, JStore<P>>(buf, a, t);
+      jit_store_tile<P>(a, dst, tile, t);
     }
+  } else {
+    jxch<P, SPLIT, JStage<P, S>, JStage<P, S + 1>>(buf, a, t);
+    jit_stages<P, SPLIT, S + 1>(buf, a, E, prog, MT, t, gbase, tile, dst);
   }
 }
 
@@ -174,8 +286,10 @@ __device__ __forceinline__ int jit_job(const DJob *__restrict__ jobs, int n_jobs
   return find_job(jobs, n_jobs, u);
 }
 
-// the 2^R amplitudes lane t holds of tile u (input layout), read from HBM:
-// lanes run over the tile's lowest bits, so the loads are coalesced
+// the 2^R amplitudes lane t holds of tile u (input layout), read from HBM.
+// DIN: the registers are stage 0's and the lanes run over the other bits;
+// else the load layout.  Either way the lanes run over the lowest tile bits
+// first, so the loads are coalesced.
 template <class P>
 __device__ __forceinline__ void jit_load_tile(c128 (&r)[1 << P::R], const DJob *__restrict__ jobs, int n_jobs,
                                               int64_t u, const DOverride &ov, int t) {
@@ -185,14 +299,21 @@ __device__ __forceinline__ void jit_load_tile(c128 (&r)[1 << P::R], const DJob *
   uint64_t g = (uint64_t)(u - J.unit0);
 #pragma unroll
   for (int i = 0; i < K; i++) g = ins0<uint64_t>(g, P::TQ[i]);
+  if constexpr (P::DIN) {
+    const int base = jbase<P, 0>(t);
 #pragma unroll
-  for (int i = 0; i < K - R; i++) g |= (uint64_t)((t >> i) & 1) << P::TQ[i];
+    for (int i = 0; i < K; i++)
+      if ((base >> i) & 1) g |= 1ull << P::TQ[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < K - R; i++) g |= (uint64_t)((t >> i) & 1) << P::TQ[i];
+  }
 #pragma unroll
   for (int j = 0; j < NR; j++) {
     uint64_t oj = 0;
 #pragma unroll
     for (int i = 0; i < R; i++)
-      if ((j >> i) & 1) oj |= 1ull << P::TQ[K - R + i];
+      if ((j >> i) & 1) oj |= 1ull << P::TQ[P::DIN ? P::RBIT[0][i] : K - R + i];
     r[j] = ldg(&A[g | oj]);
   }
 }
@@ -201,12 +322,13 @@ __device__ __forceinline__ void jit_load_tile(c128 (&r)[1 << P::R], const DJob *
 // of every job, 2^(K-R) threads per block.  PERSIST = false: one block per
 // tile.  PERSIST = true: at most as many blocks as the chip holds at once,
 // block b taking tiles b, b + grid, ..., each block reading its next tile
-// from HBM into registers while the current tile's stages run.
-template <class P, bool PERSIST>
+// from HBM into registers while the current tile's stages run.  SPLIT: the
+// LDS tile holds doubles (see jxch).
+template <class P, bool PERSIST, bool SPLIT>
 __device__ __forceinline__ void jit_pass_fwd(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units,
                                              const DOverride &ov) {
-  constexpr int K = P::K, R = P::R, NR = 1 << R, T = 1 << (K - R);
-  __shared__ c128 la[1 << K];
+  constexpr int K = P::K, R = P::R, NR = 1 << R;
+  __shared__ typename JLdsT<SPLIT>::T buf[1 << K];
   const int t = threadIdx.x;
   int64_t u = blockIdx.x;
   if (u >= total_units) return;
@@ -224,42 +346,22 @@ __device__ __forceinline__ void jit_pass_fwd(const DJob *__restrict__ jobs, int 
     uint64_t gbase = (uint64_t)tile;
 #pragma unroll
     for (int i = 0; i < K; i++) gbase = ins0<uint64_t>(gbase, P::TQ[i]);
+    c128 a[NR];
 #pragma unroll
-    for (int j = 0; j < NR; j++) la[swz(j * T + t)] = pf[j];
-    __syncthreads();
+    for (int j = 0; j < NR; j++) a[j] = pf[j];
     if constexpr (PERSIST) {
       const int64_t un = u + gridDim.x;
       if (un < total_units) jit_load_tile<P>(pf, jobs, n_jobs, un, ov, t);
     }
-    const DOp E = ldc(prog + P::G0);
-    jit_stages<P, 0>(la, E, prog, MT, t, gbase, dst);
-    if constexpr (!P::DOUT) {
-      // LDS -> HBM in the output layout
-      uint64_t gbo = (uint64_t)tile;
-#pragma unroll
-      for (int i = 0; i < K; i++) gbo = ins0<uint64_t>(gbo, P::TQO[i]);
-      uint64_t so = 0;
-      int sl = 0;
-#pragma unroll
-      for (int i = 0; i < K - R; i++)
-        if ((t >> i) & 1) {
-          so |= 1ull << P::TQO[i];
-          sl |= 1 << P::LBO[i];
-        }
-#pragma unroll
-      for (int j = 0; j < NR; j++) {
-        uint64_t oj = 0;
-        int ol = 0;
-#pragma unroll
-        for (int i = 0; i < R; i++)
-          if ((j >> i) & 1) {
-            oj |= 1ull << P::TQO[K - R + i];
-            ol |= 1 << P::LBO[K - R + i];
-          }
-        stg(&dst[gbo | so | oj], la[swz(sl | ol)]);
-      }
+    if constexpr (P::NST == 0) {
+      // a pass without ops only moves qubits
+      jxch<P, SPLIT, JLoad<P>, JStore<P>>(buf, a, t);
+      jit_store_tile<P>(a, dst, tile, t);
+    } else {
+      if constexpr (!P::DIN) jxch<P, SPLIT, JLoad<P>, JStage<P, 0>>(buf, a, t);
+      jit_stages<P, SPLIT, 0>(buf, a, ldc(prog + P::G0), prog, MT, t, gbase, tile, dst);
     }
-    __syncthreads();  // the next tile overwrites la
+    __syncthreads();  // the next tile overwrites the LDS tile
   }
 }
 
@@ -295,22 +397,10 @@ __device__ __forceinline__ double jgrad(const c128 (&a)[1 << R], const c128 (&b)
   else return 0.0;
 }
 
-// LDS index of register j of stage S for lane base `base`
+// LDS slot of register j of stage S for lane base `base`
 template <class P, int S>
 __device__ __forceinline__ int jslot(int base, int j) {
-  int o = 0;
-#pragma unroll
-  for (int i = 0; i < P::R; i++)
-    if ((j >> i) & 1) o |= 1 << P::RBIT[S][i];
-  return swz(base | o);
-}
-
-template <class P, int S>
-__device__ __forceinline__ int jbase(int t) {
-  int base = t;
-#pragma unroll
-  for (int i = 0; i < P::R; i++) base = ins0<int>(base, P::SRT[S][i]);
-  return base;
+  return jswz<P>(base) ^ jswz<P>(joff<P, S>(j));
 }
 
 // a tile (in LDS) to HBM in the pass's output layout
@@ -338,7 +428,7 @@ __device__ __forceinline__ void jit_store_out(const c128 *lx, gc128 *dst, int64_
         oj |= 1ull << P::TQO[K - R + i];
         ol |= 1 << P::LBO[K - R + i];
       }
-    stg(&dst[gbo | so | oj], lx[swz(sl | ol)]);
+    stg(&dst[gbo | so | oj], lx[jswz<P>(sl) ^ jswz<P>(ol)]);
   }
 }
 
@@ -355,7 +445,7 @@ __device__ __forceinline__ void jit_load_in(c128 *lx, const gc128 *src, uint64_t
 #pragma unroll
     for (int i = 0; i < R; i++)
       if ((j >> i) & 1) oj |= 1ull << P::TQ[K - R + i];
-    lx[swz(j * T + t)] = ldg(&src[gbase | st | oj]);
+    lx[jswz<P>(t) ^ jswz<P>(j * T)] = ldg(&src[gbase | st | oj]);
   }
 }
 
