@@ -249,6 +249,9 @@ struct Elem {
   // GK_KRAUS3: offsets in the circuit's constant data of the Kraus set, its
   // adjoint set (K_s^dagger) and the inverse 64 x 64 superoperator; count
   int kd = -1, kda = -1, sinv = -1, nk = 0;
+  // the unnormalised kind (GK_HX1..GK_HW1) the specialised forward passes
+  // use for a phase-factored sqrt(X), sqrt(Y), sqrt(W), else 0
+  int hk = 0;
   uint64_t mask() const {
     uint64_t m = 0;
     for (int i = 0; i < nq; i++) m |= 1ull << q[i];
@@ -920,6 +923,7 @@ vqc_status lower(vqc_circuit c) {
       for (int t = 0; t < m; t++) e.q[t] = op.qubits[t];
       const bool fac = phase_factored(op.type);
       n_factored += fac;
+      if (fac) e.hk = op.type == VQC_SX ? GK_HX1 : op.type == VQC_SY ? GK_HY1 : GK_HW1;
       e.mat = m == 3 ? add_recipe(c, op.type, RF_COPY, 0, m, op, data_off, n_data, d * d)
                      : add_gate_recipe(c, gk, op.type, fac ? RF_GATE_F : RF_GATE, m, op, data_off, n_data);
       // Pauli rotations exp(-i theta G / 2): derivative from the generator
@@ -1195,6 +1199,14 @@ bool jit_fwd_split() {
   return !(e && e[0] == '0');
 }
 
+// forward passes apply phase-factored sqrt(X), sqrt(Y), sqrt(W) unnormalised
+// (GK_HX1..GK_HW1) and rescale the tile once; VQC_JIT_HSQRT=0 keeps the
+// rotation forms
+bool jit_fwd_hsqrt() {
+  const char *e = std::getenv("VQC_JIT_HSQRT");
+  return !(e && e[0] == '0');
+}
+
 std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::string s) {
   char buf[512];
   auto arr = [&](const char *name, const std::vector<int> &v) {
@@ -1221,6 +1233,12 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
                   p, K, R, nst, P.prog, g, (ph.lowfree & 1) ? "true" : "false", (ph.lowfree & 2) ? "true" : "false");
     s += buf;
     const bool split = jit_fwd_split();
+    const bool hsq = jit_fwd_hsqrt();
+    int nh = 0;
+    for (const auto &S : ph.stages)
+      for (int ei : S.elems) nh += hsq && c->elems[ei].hk != 0;
+    std::snprintf(buf, sizeof(buf), "  static constexpr int NH = %d;\n", nh);
+    s += buf;
     s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) +
          arr("SWC", lds_swizzle(K, R, ph, lbo, split ? 5 : 4, 2 * p + 1));
     s += split ? "  static constexpr int SWB = 5;\n" : "  static constexpr int SWB = 4;\n";
@@ -1260,7 +1278,8 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
         const Elem &e = c->elems[ei];
         const int b0 = e.nq > 0 ? regpos[loc[e.q[0]]] : 0, b1 = e.nq > 1 ? regpos[loc[e.q[1]]] : 0;
         const int b2 = e.nq > 2 ? regpos[loc[e.q[2]]] : 0;
-        std::snprintf(buf, sizeof(buf), "      E = jop<%d, %d, %d, %d, %d>(a, E, prog + %d, M);\n", R, e.kind, b0, b1,
+        const int kind = hsq && e.hk ? e.hk : e.kind;
+        std::snprintf(buf, sizeof(buf), "      E = jop<%d, %d, %d, %d, %d>(a, E, prog + %d, M);\n", R, kind, b0, b1,
                       b2, g + 1);
         s += buf;
         g++;

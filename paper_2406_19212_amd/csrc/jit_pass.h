@@ -28,6 +28,8 @@
 //                          reads HBM directly
 //   DOUT                   the last stage holds none of the low bits and the
 //                          pass does not move qubits: it stores straight to HBM
+//   NH                     ops of the unnormalised kinds GK_HX1..GK_HW1: the
+//                          tile is multiplied by 2^(-NH/2) after the last stage
 //   PROG                   c128 offset of the op program in the item's matrices
 //   G0                     program index of the pass's first op
 //   template <int S> static DOp stage(c128 (&a)[1 << R], DOp E, const DOp *prog, cmat *M)
@@ -73,6 +75,12 @@ __device__ __forceinline__ void japply(c128 (&a)[1 << R], const DOp &E, cmat *ma
       case 2: rg_sfx<NR, B0, B1, ADJ, false, true>(a, r); break;
       default: rg_sfx<NR, B0, B1, ADJ, true, true>(a, r); break;
     }
+  } else if constexpr (KIND == GK_HX1) {
+    rg_hx1<NR, B0>(a);
+  } else if constexpr (KIND == GK_HY1) {
+    rg_hy1<NR, B0>(a);
+  } else if constexpr (KIND == GK_HW1) {
+    rg_hw1<NR, B0>(a);
   } else if constexpr (KIND == GK_DENSE1) {
     rg_dense1<NR, B0, ADJ>(a, M);
   } else if constexpr (KIND == GK_DIAG1) {
@@ -253,6 +261,14 @@ __device__ __forceinline__ void jit_stages(typename JLdsT<SPLIT>::T *buf, c128 (
   constexpr int K = P::K, R = P::R, NR = 1 << R;
   E = P::template stage<S>(a, E, prog, MT);
   if constexpr (S == P::NST - 1) {
+    if constexpr (P::NH > 0) {
+      // the factor the unnormalised ops left out: 2^(-NH/2), a power of two
+      // times 1/sqrt(2) for odd NH
+      double f = (P::NH & 1) ? 0.70710678118654752440 : 1.0;
+      for (int i = 0; i < P::NH / 2; i++) f *= 0.5;
+#pragma unroll
+      for (int j = 0; j < NR; j++) a[j] = make_double2(a[j].x * f, a[j].y * f);
+    }
     if constexpr (P::DOUT) {
       // the last stage's lanes run over the low tile bits: store to HBM
       const int base = jbase<P, S>(t);

@@ -365,6 +365,48 @@ __device__ __forceinline__ void shr(double &u, double &v, double a, double b) {
   }
 }
 
+// sqrt(2) sqrt(X) (phase-factored): x' = x - i y, y' = y - i x
+template <int NR, int B>
+__device__ __forceinline__ void rg_hx1(c128 (&a)[NR]) {
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    const c128 x = a[j], y = a[k];
+    a[j] = make_double2(x.x + y.y, x.y - y.x);
+    a[k] = make_double2(y.x + x.y, y.y - x.x);
+  }
+}
+
+// sqrt(2) sqrt(Y) (phase-factored): x' = x - y, y' = x + y
+template <int NR, int B>
+__device__ __forceinline__ void rg_hy1(c128 (&a)[NR]) {
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    const c128 x = a[j], y = a[k];
+    a[j] = make_double2(x.x - y.x, x.y - y.y);
+    a[k] = make_double2(x.x + y.x, x.y + y.y);
+  }
+}
+
+// sqrt(2) sqrt(W) (phase-factored): x' = x + e^{-3 i pi/4} y,
+// y' = e^{-i pi/4} x + y; (-1 - i) y = (Im y - Re y) - i (Re y + Im y) and
+// (1 - i) x = (Re x + Im x) + i (Im x - Re x), each scaled by 1/sqrt(2)
+template <int NR, int B>
+__device__ __forceinline__ void rg_hw1(c128 (&a)[NR]) {
+  constexpr double h = 0.70710678118654752440;
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    const c128 x = a[j], y = a[k];
+    a[j] = make_double2(fma(h, y.y - y.x, x.x), fma(-h, y.x + y.y, x.y));
+    a[k] = make_double2(fma(h, x.x + x.y, y.x), fma(h, x.y - x.x, y.y));
+  }
+}
+
 // Rx-type [[C, -iS], [-iS, C]]: (Re x, Im y) rotate by p, (Im x, Re y) by -p
 template <int NR, int B, bool ADJ, bool N0>
 __device__ __forceinline__ void rg_sxr1(c128 (&a)[NR], const SRec &r) {

@@ -62,7 +62,14 @@ enum GateKind : int8_t {
   GK_DENSE3 = 23,
   // a three-qubit channel on vec(rho) (6 bits): not a register op; the
   // planner gives it a pass of its own, run by k_kraus3
-  GK_KRAUS3 = 24
+  GK_KRAUS3 = 24,
+  // sqrt(X), sqrt(Y), sqrt(W) (phase-factored) times sqrt(2), for the
+  // specialised forward passes: four additions per pair for the first two,
+  // four additions and four FMAs for the third; the pass multiplies its tile
+  // by 2^(-k/2) for its k such ops before storing it
+  GK_HX1 = 25,    // [[1, -i], [-i, 1]]
+  GK_HY1 = 26,    // [[1, -1], [1, 1]]
+  GK_HW1 = 27     // [[1, e^{-3 i pi/4}], [e^{-i pi/4}, 1]]
 };
 // DGate.nd: derivative count in the low byte; this bit set when the op's
 // derivatives are generator kinds (taken on Phi before the op is undone)
