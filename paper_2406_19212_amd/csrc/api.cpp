@@ -1227,13 +1227,31 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
       lbo[i] = ord[i];
       tqo[i] = ph.tq_out[ord[i]];
     }
+    const bool split = jit_fwd_split();
+    const bool hsq = jit_fwd_hsqrt();
+    // program entries are read only by ops whose kind takes a record or a
+    // matrix; each such op loads the entry of the next one (the pass's first
+    // is loaded by the driver as G0)
+    const char *rf = std::getenv("VQC_JIT_RECFREE");
+    const bool recfree = !(rf && rf[0] == '0');
+    std::vector<int> kinds, need;
+    for (const auto &S : ph.stages)
+      for (int ei : S.elems) {
+        const Elem &e = c->elems[ei];
+        kinds.push_back(hsq && e.hk ? e.hk : e.kind);
+        const int k = kinds.back();
+        need.push_back(!recfree || !(k == GK_CX || k == GK_HX1 || k == GK_HY1 || k == GK_HW1 || k == GK_NONE));
+      }
+    const int n_ops = (int)kinds.size();
+    std::vector<int> next_need(n_ops + 1, g + std::max(n_ops - 1, 0));
+    for (int k = n_ops - 1; k >= 0; k--) next_need[k] = need[k] ? g + k : next_need[k + 1];
     std::snprintf(buf, sizeof(buf),
                   "struct JP%zu {\n  static constexpr int K = %d, R = %d, NST = %d, PROG = %d, G0 = %d;\n"
                   "  static constexpr bool DIN = %s, DOUT = %s;\n",
-                  p, K, R, nst, P.prog, g, (ph.lowfree & 1) ? "true" : "false", (ph.lowfree & 2) ? "true" : "false");
+                  p, K, R, nst, P.prog, next_need[0], (ph.lowfree & 1) ? "true" : "false",
+                  (ph.lowfree & 2) ? "true" : "false");
     s += buf;
-    const bool split = jit_fwd_split();
-    const bool hsq = jit_fwd_hsqrt();
+    const int g_pass = g;
     int nh = 0;
     for (const auto &S : ph.stages)
       for (int ei : S.elems) nh += hsq && c->elems[ei].hk != 0;
@@ -1278,9 +1296,12 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
         const Elem &e = c->elems[ei];
         const int b0 = e.nq > 0 ? regpos[loc[e.q[0]]] : 0, b1 = e.nq > 1 ? regpos[loc[e.q[1]]] : 0;
         const int b2 = e.nq > 2 ? regpos[loc[e.q[2]]] : 0;
-        const int kind = hsq && e.hk ? e.hk : e.kind;
-        std::snprintf(buf, sizeof(buf), "      E = jop<%d, %d, %d, %d, %d>(a, E, prog + %d, M);\n", R, kind, b0, b1,
-                      b2, g + 1);
+        const int k = g - g_pass, kind = kinds[k];
+        if (need[k])
+          std::snprintf(buf, sizeof(buf), "      E = jop<%d, %d, %d, %d, %d>(a, E, prog + %d, M);\n", R, kind, b0,
+                        b1, b2, next_need[k + 1]);
+        else
+          std::snprintf(buf, sizeof(buf), "      jopn<%d, %d, %d, %d>(a);\n", R, kind, b0, b1);
         s += buf;
         g++;
       }

@@ -31,11 +31,12 @@
 //   NH                     ops of the unnormalised kinds GK_HX1..GK_HW1: the
 //                          tile is multiplied by 2^(-NH/2) after the last stage
 //   PROG                   c128 offset of the op program in the item's matrices
-//   G0                     program index of the pass's first op
+//   G0                     program index of the pass's first op that reads its
+//                          entry (a record or a matrix offset)
 //   template <int S> static DOp stage(c128 (&a)[1 << R], DOp E, const DOp *prog, cmat *M)
-//                          the ops of stage S in order (calls of jop below);
-//                          E is the entry of the stage's first op, the result
-//                          the entry of the op after the stage
+//                          the ops of stage S in order (calls of jop and jopn
+//                          below); E is the entry of the next op that reads
+//                          one, the result likewise after the stage
 #pragma once
 #include "pass_kernels.h"
 
@@ -130,6 +131,20 @@ __device__ __forceinline__ DOp jop(c128 (&a)[1 << R], const DOp &E, const DOp *n
   japply<R, false, KIND, B0, B1, B2>(a, E, mats);
   __builtin_amdgcn_sched_barrier(0);
   return En;
+}
+
+// an op whose kind takes neither a record nor a matrix (controlled X, the
+// unnormalised sqrt kinds): no program entry is read
+template <int R, int KIND, int B0, int B1>
+__device__ __forceinline__ void jopn(c128 (&a)[1 << R]) {
+  constexpr int NR = 1 << R;
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (KIND == GK_CX) rg_cx<NR, B0, B1>(a);
+  else if constexpr (KIND == GK_HX1) rg_hx1<NR, B0>(a);
+  else if constexpr (KIND == GK_HY1) rg_hy1<NR, B0>(a);
+  else if constexpr (KIND == GK_HW1) rg_hw1<NR, B0>(a);
+  // GK_NONE: nothing
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // LDS slot of tile-local index l under the pass's bank swizzle; linear over
