@@ -269,6 +269,9 @@ struct PassH {
   int lowfree = 0;          // DPass.lowfree as uploaded
   int special = -1;         // elem of a pass run by its own kernel (GK_KRAUS3), else -1
   int sk[3] = {0, 0, 0}, sb[3] = {0, 0, 0};  // its ket and bra bits in the pass's layout
+  // a forward pass that moves qubits whose last stage's wave lanes cover the
+  // new low set: the specialised kernel stores from registers
+  bool jit_dout = false;
   struct Stage {
     int rbit[4];
     std::vector<int> elems;  // indices into elems
@@ -350,7 +353,9 @@ void layout_of(uint64_t L, int nbits, std::vector<int> &pos) {
 }
 
 // the c-subset of `tile` that lets the next pass take the most ops
-uint64_t choose_low(const std::vector<Elem> &E, const std::vector<int> &rem, uint64_t tile, int c, int TK) {
+// (among the subsets that tie, one inside `prefer` if there is one)
+uint64_t choose_low(const std::vector<Elem> &E, const std::vector<int> &rem, uint64_t tile, int c, int TK,
+                    uint64_t prefer = 0) {
   std::vector<int> q;
   for (int b = 0; b < 64; b++)
     if ((tile >> b) & 1) q.push_back(b);
@@ -363,7 +368,10 @@ uint64_t choose_low(const std::vector<Elem> &E, const std::vector<int> &rem, uin
     uint64_t L = 0;
     for (int i = 0; i < c; i++) L |= 1ull << q[idx[i]];
     const int n = count_fit(E, rem, L, TK, 256);
-    if (n > best_n) { best_n = n; best = L; }
+    if (n > best_n || (n == best_n && prefer && !(L & ~prefer) && (best & ~prefer))) {
+      best_n = n;
+      best = L;
+    }
     int i = c - 1;
     while (i >= 0 && idx[i] == t - c + i) i--;
     if (i < 0) break;
@@ -394,11 +402,11 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
   uint64_t L = home;
   std::vector<int> pos, pos_next;
   layout_of(L, nbits, pos);
-  auto finish_pass = [&](PassH &ph, uint64_t tile, const std::vector<int> &rest) {
+  auto finish_pass = [&](PassH &ph, uint64_t tile, const std::vector<int> &rest, uint64_t prefer) {
     uint64_t Ln = L;
     if (P.remap) {
       if (rest.empty()) Ln = ((home & ~tile) == 0) ? home : L;
-      else Ln = choose_low(E, rest, tile, c, TK);
+      else Ln = choose_low(E, rest, tile, c, TK, prefer);
     }
     layout_of(Ln, nbits, pos_next);
     // tile-local bits in ascending position of the layout the kernel reads
@@ -456,7 +464,17 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
     for (int b = 0; b < nbits && popc(tile) < TK; b++) tile |= 1ull << b;
     PassH ph;
     ph.K = TK;
-    finish_pass(ph, tile, rem);
+    // a forward pass's tile-local order follows the layout it reads, known
+    // before the next layout is chosen: plan the stages first, so the next
+    // low set can favour bits the last stage's wave lanes cover
+    if (adjoint) {
+      finish_pass(ph, tile, rem, 0);
+    } else {
+      ph.lq.clear();
+      for (int b = 0; b < nbits; b++)
+        if ((tile >> b) & 1) ph.lq.push_back(b);
+      std::sort(ph.lq.begin(), ph.lq.end(), [&](int x, int y) { return pos[x] < pos[y]; });
+    }
     int loc[64];
     for (int i = 0; i < (int)ph.lq.size(); i++) loc[ph.lq[i]] = i;
     // stages over tile-local bits: plain first fit, and a variant whose first
@@ -543,6 +561,24 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
       for (int i : best_rest) rem.push_back(i);
       std::sort(rem.begin(), rem.end());
     }
+    if (!adjoint) {
+      // the qubits at the last stage's six lowest lane bits (one wave's
+      // lanes): a next low set among them lets the specialised kernel store
+      // that stage's registers straight to HBM in the new layout, coalesced
+      uint64_t prefer = 0;
+      if (!ph.stages.empty() && !reg_only) {
+        int nl = 0;
+        for (int b = 0; b < TK && nl < 6; b++) {
+          bool reg = false;
+          for (int i = 0; i < R; i++) reg = reg || ph.stages.back().rbit[i] == b;
+          if (reg) continue;
+          prefer |= 1ull << ph.lq[b];
+          nl++;
+        }
+      }
+      finish_pass(ph, tile, rem, prefer);
+      ph.jit_dout = ph.moves && prefer && !(L & ~prefer);
+    }
     P.passes.push_back(ph);
   }
   if (!P.remap) return;
@@ -553,7 +589,7 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
     PassH ph;
     ph.K = TK;
     const std::vector<int> none;
-    finish_pass(ph, tile, none);
+    finish_pass(ph, tile, none, 0);
     P.passes.push_back(ph);
   };
   if (L != home) empty_pass();  // bring the layout back to the identity
@@ -1249,15 +1285,16 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
                   "struct JP%zu {\n  static constexpr int K = %d, R = %d, NST = %d, PROG = %d, G0 = %d;\n"
                   "  static constexpr bool DIN = %s, DOUT = %s;\n",
                   p, K, R, nst, P.prog, next_need[0], (ph.lowfree & 1) ? "true" : "false",
-                  (ph.lowfree & 2) ? "true" : "false");
+                  ((ph.lowfree & 2) || ph.jit_dout) ? "true" : "false");
     s += buf;
+    s += ph.moves ? "  static constexpr bool MOVES = true;\n" : "  static constexpr bool MOVES = false;\n";
     const int g_pass = g;
     int nh = 0;
     for (const auto &S : ph.stages)
       for (int ei : S.elems) nh += hsq && c->elems[ei].hk != 0;
     std::snprintf(buf, sizeof(buf), "  static constexpr int NH = %d;\n", nh);
     s += buf;
-    s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) +
+    s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("TQL", ph.tq_out) +
          arr("SWC", lds_swizzle(K, R, ph, lbo, split ? 5 : 4, 2 * p + 1));
     s += split ? "  static constexpr int SWB = 5;\n" : "  static constexpr int SWB = 4;\n";
     const int rows = std::max(nst, 1);  // a pass without ops only moves qubits

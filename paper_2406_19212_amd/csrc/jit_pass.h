@@ -26,8 +26,10 @@
 //                          patterns
 //   DIN                    the first stage holds none of the low bits: it
 //                          reads HBM directly
-//   DOUT                   the last stage holds none of the low bits and the
-//                          pass does not move qubits: it stores straight to HBM
+//   DOUT                   the last stage's wave lanes cover the output's low
+//                          bits: it stores straight to HBM
+//   MOVES, TQL[K]          the output layout differs from the input's; output
+//                          physical bit of tile-local bit i
 //   NH                     ops of the unnormalised kinds GK_HX1..GK_HW1: the
 //                          tile is multiplied by 2^(-NH/2) after the last stage
 //   PROG                   c128 offset of the op program in the item's matrices
@@ -285,18 +287,24 @@ __device__ __forceinline__ void jit_stages(typename JLdsT<SPLIT>::T *buf, c128 (
       for (int j = 0; j < NR; j++) a[j] = make_double2(a[j].x * f, a[j].y * f);
     }
     if constexpr (P::DOUT) {
-      // the last stage's lanes run over the low tile bits: store to HBM
+      // the last stage's wave lanes cover the low bits of the output layout:
+      // store to HBM from registers (MOVES: local bit i at output bit TQL[i])
       const int base = jbase<P, S>(t);
       uint64_t gb = gbase;
+      if constexpr (P::MOVES) {
+        gb = (uint64_t)tile;
+#pragma unroll
+        for (int i = 0; i < K; i++) gb = ins0<uint64_t>(gb, P::TQO[i]);
+      }
 #pragma unroll
       for (int i = 0; i < K; i++)
-        if ((base >> i) & 1) gb |= 1ull << P::TQ[i];
+        if ((base >> i) & 1) gb |= 1ull << (P::MOVES ? P::TQL[i] : P::TQ[i]);
 #pragma unroll
       for (int j = 0; j < NR; j++) {
         uint64_t go = 0;
 #pragma unroll
         for (int i = 0; i < R; i++)
-          if ((j >> i) & 1) go |= 1ull << P::TQ[P::RBIT[S][i]];
+          if ((j >> i) & 1) go |= 1ull << (P::MOVES ? P::TQL[P::RBIT[S][i]] : P::TQ[P::RBIT[S][i]]);
         stg(&dst[gb | go], a[j]);
       }
     } else {
