@@ -1164,7 +1164,8 @@ vqc_status upload_plan(vqc_circuit c, Plan &P, bool adjoint) {
 // lbo[0..]).  col starts as the interpreter's fixed swizzle (low bits ^=
 // bits 4..7 ^ bits 8..11) and a seeded random search replaces it when it
 // finds fewer conflicting accesses.
-std::vector<int> lds_swizzle(int K, int R, const PassH &ph, const std::vector<int> &lbo, int swb, uint64_t seed) {
+std::vector<int> lds_swizzle(int K, int R, const PassH &ph, const std::vector<int> &lbo, int swb, uint64_t seed,
+                             bool search = true) {
   std::vector<std::pair<std::vector<int>, int>> pats;  // lowest lane bits, accesses per lane
   auto lanes_of = [&](const std::vector<int> &bits, int w) {
     std::vector<int> v(bits.begin(), bits.begin() + std::min<size_t>(swb, bits.size()));
@@ -1210,7 +1211,7 @@ std::vector<int> lds_swizzle(int K, int R, const PassH &ph, const std::vector<in
   int bc = cost(best);
   uint64_t x = seed * 0x9e3779b97f4a7c15ull + 0x632be59bd9b4e019ull;
   std::vector<int> col(K);
-  for (int it = 0; it < 6000 && bc > 0; it++) {
+  for (int it = 0; search && it < 6000 && bc > 0; it++) {
     for (int q = 0; q < K; q++) {
       x ^= x << 13;
       x ^= x >> 7;
@@ -1225,6 +1226,27 @@ std::vector<int> lds_swizzle(int K, int R, const PassH &ph, const std::vector<in
     }
   }
   return best;
+}
+
+// the swizzle arrays of a pass description: SWC, SWB and SWDEF (SWC is the
+// fixed fold l ^ ((l >> 4) ^ (l >> 8)) & 15, which the device computes in
+// four instructions)
+std::string swizzle_decl(const std::vector<int> &col, int swb) {
+  bool def = swb == 4;
+  for (size_t q = 0; q < col.size(); q++) def = def && col[q] == (q < 4 ? 1 << q : 1 << (q & 3)) && q < 12;
+  std::string r = "  static constexpr int SWC[" + std::to_string(col.size()) + "] = {";
+  for (size_t i = 0; i < col.size(); i++) r += (i ? ", " : "") + std::to_string(col[i]);
+  r += "};\n  static constexpr int SWB = " + std::to_string(swb) + ";\n";
+  r += def ? "  static constexpr bool SWDEF = true;\n" : "  static constexpr bool SWDEF = false;\n";
+  return r;
+}
+
+// adjoint passes keep the fixed fold (measured faster: their per-lane slot
+// arithmetic is not hoisted out of the stages); VQC_JIT_ADJ_SWZ=1 searches
+// one per pass as the forward passes do
+bool jit_adj_swizzle() {
+  const char *e = std::getenv("VQC_JIT_ADJ_SWZ");
+  return e && e[0] == '1';
 }
 
 // forward passes exchange the tile through LDS as real and imaginary halves
@@ -1295,8 +1317,7 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
     std::snprintf(buf, sizeof(buf), "  static constexpr int NH = %d;\n", nh);
     s += buf;
     s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("TQL", ph.tq_out) +
-         arr("SWC", lds_swizzle(K, R, ph, lbo, split ? 5 : 4, 2 * p + 1));
-    s += split ? "  static constexpr int SWB = 5;\n" : "  static constexpr int SWB = 4;\n";
+         swizzle_decl(lds_swizzle(K, R, ph, lbo, split ? 5 : 4, 2 * p + 1), split ? 5 : 4);
     const int rows = std::max(nst, 1);  // a pass without ops only moves qubits
     std::string rb = "  static constexpr int RBIT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
     std::string sr = "  static constexpr int SRT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
@@ -1404,7 +1425,7 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::strin
                   (ph.lowfree & 2) ? "true" : "false", (ph.lowfree & 1) ? "true" : "false");
     s += buf;
     s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("VSLOT", vslot) +
-         arr("SWC", lds_swizzle(K, R, ph, lbo, 4, 2 * p + 2)) + "  static constexpr int SWB = 4;\n";
+         swizzle_decl(lds_swizzle(K, R, ph, lbo, 4, 2 * p + 2, jit_adj_swizzle()), 4);
     const int rows = std::max(nst, 1);
     std::string rb = "  static constexpr int RBIT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
     std::string sr = "  static constexpr int SRT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";

@@ -23,7 +23,8 @@
 //   SWC[K]                 LDS bank swizzle: tile-local index l is kept at
 //                          slot (l & ~15) | (XOR of SWC[q] over the set bits q
 //                          of l), chosen by the planner for this pass's access
-//                          patterns
+//                          patterns; SWB its width, SWDEF when it is the fixed
+//                          fold l ^ ((l >> 4) ^ (l >> 8)) & 15
 //   DIN                    the first stage holds none of the low bits: it
 //                          reads HBM directly
 //   DOUT                   the last stage's wave lanes cover the output's low
@@ -154,6 +155,7 @@ __device__ __forceinline__ void jopn(c128 (&a)[1 << R]) {
 // compile-time o costs one XOR
 template <class P>
 __device__ __forceinline__ int jswz(int l) {
+  if constexpr (P::SWDEF) return l ^ (((l >> 4) ^ (l >> 8)) & 15);
   int n = 0;
 #pragma unroll
   for (int q = 0; q < P::K; q++)
