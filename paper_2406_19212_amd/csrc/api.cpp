@@ -300,6 +300,10 @@ struct Plan {
   // plan is jit->fn[jit_base + p]; empty: the interpreting kernels run
   std::shared_ptr<JitModule> jit;
   int jit_base = 0;
+  // LDS slots of every lane in every tile layout of the specialised forward
+  // passes (see jit_source_fwd), read by those kernels
+  DevBuf slots_buf;
+  const uint16_t *d_slots = nullptr;
 };
 
 int popc(uint64_t v) { return __builtin_popcountll(v); }
@@ -320,6 +324,7 @@ void reset_plan(Plan &P) {
   P.d_gates = nullptr;
   P.d_derivs = nullptr;
   P.jit.reset();
+  P.d_slots = nullptr;
 }
 
 // First-fit fusion: walk the remaining ops in order; an op joins the pass if
@@ -1265,7 +1270,42 @@ bool jit_fwd_hsqrt() {
   return !(e && e[0] == '0');
 }
 
-std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::string s) {
+// Lane slots of a forward pass: for each tile layout the kernel exchanges
+// through LDS -- row 0 the load layout (lanes over the low tile bits), row
+// 1 + S stage S's (lanes over the bits outside its register bits), row
+// NST + 1 the store layout (lanes in output order) -- the byte offset in the
+// LDS tile (elements of `width` bytes) of the swizzled slot of each lane's
+// register 0, 2^(K-R) entries per row.  The kernel reads one entry per
+// exchange instead of computing it.
+void lane_slots(int K, int R, const PassH &ph, const std::vector<int> &lbo, const std::vector<int> &col, int swb,
+                int width, std::vector<uint16_t> &tab) {
+  const int T = 1 << (K - R), mask = (1 << swb) - 1;
+  auto slot = [&](int l) {
+    int n = 0;
+    for (int q = 0; q < K; q++)
+      if ((l >> q) & 1) n ^= col[q];
+    return (uint16_t)(((l & ~mask) | n) * width);
+  };
+  for (int t = 0; t < T; t++) tab.push_back(slot(t));
+  for (const auto &S : ph.stages) {
+    int srt[4];
+    for (int i = 0; i < R; i++) srt[i] = S.rbit[i];
+    std::sort(srt, srt + R);
+    for (int t = 0; t < T; t++) {
+      int b = t;
+      for (int i = 0; i < R; i++) b = ((b >> srt[i]) << (srt[i] + 1)) | (b & ((1 << srt[i]) - 1));
+      tab.push_back(slot(b));
+    }
+  }
+  for (int t = 0; t < T; t++) {
+    int sl = 0;
+    for (int i = 0; i < K - R; i++)
+      if ((t >> i) & 1) sl |= 1 << lbo[i];
+    tab.push_back(slot(sl));
+  }
+}
+
+std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::string s, std::vector<uint16_t> &tab) {
   char buf[512];
   auto arr = [&](const char *name, const std::vector<int> &v) {
     std::string r = std::string("  static constexpr int ") + name + "[" + std::to_string(v.size()) + "] = {";
@@ -1316,8 +1356,12 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
       for (int ei : S.elems) nh += hsq && c->elems[ei].hk != 0;
     std::snprintf(buf, sizeof(buf), "  static constexpr int NH = %d;\n", nh);
     s += buf;
+    const std::vector<int> col = lds_swizzle(K, R, ph, lbo, split ? 5 : 4, 2 * p + 1);
+    std::snprintf(buf, sizeof(buf), "  static constexpr int TAB = %zu;\n", tab.size());
+    s += buf;
+    lane_slots(K, R, ph, lbo, col, split ? 5 : 4, split ? 8 : 16, tab);
     s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("TQL", ph.tq_out) +
-         swizzle_decl(lds_swizzle(K, R, ph, lbo, split ? 5 : 4, 2 * p + 1), split ? 5 : 4);
+         swizzle_decl(col, split ? 5 : 4);
     const int rows = std::max(nst, 1);  // a pass without ops only moves qubits
     std::string rb = "  static constexpr int RBIT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
     std::string sr = "  static constexpr int SRT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
@@ -1368,8 +1412,8 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
     s += nst ? "    else return E;\n  }\n};\n" : "    return E;\n  }\n};\n";
     std::snprintf(buf, sizeof(buf),
                   "extern \"C\" __global__ void __launch_bounds__(%d) vqc_jf%zu(const DJob *__restrict__ jobs, "
-                  "int n_jobs, int64_t total_units, DOverride ov) {\n  jit_pass_fwd<JP%zu, %s, %s>(jobs, n_jobs, "
-                  "total_units, ov);\n}\n",
+                  "int n_jobs, int64_t total_units, DOverride ov, const uint16_t *__restrict__ slots) {\n"
+                  "  jit_pass_fwd<JP%zu, %s, %s>(jobs, n_jobs, total_units, ov, slots);\n}\n",
                   1 << (K - R), p, p, persist ? "true" : "false", split ? "true" : "false");
     s += buf;
   }
@@ -1500,8 +1544,8 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::strin
     g = g0 + n_ops;
     std::snprintf(buf, sizeof(buf),
                   "extern \"C\" __global__ void __launch_bounds__(%d) vqc_ja%zu(const DJob *__restrict__ jobs, "
-                  "int n_jobs, int64_t total_units, DOverride ov) {\n  jit_pass_adj<JA%zu, %s>(jobs, n_jobs, "
-                  "total_units, ov);\n}\n",
+                  "int n_jobs, int64_t total_units, DOverride ov, const uint16_t *) {\n  jit_pass_adj<JA%zu, %s>(jobs, "
+                  "n_jobs, total_units, ov);\n}\n",
                   T, p, p, shared ? "true" : "false");
     s += buf;
   }
@@ -1536,6 +1580,7 @@ bool jit_plan_ok(const Plan &P) { return !P.reg_only && !P.d4 && !P.passes.empty
 vqc_status jit_prepare(vqc_circuit c, bool with_adj = true) {
   c->fwd.jit.reset();
   c->adj.jit.reset();
+  c->fwd.d_slots = nullptr;
   c->jit_ms = 0;
   if (!jit_wanted(c)) return VQC_OK;
   // persistent grids when the caller asked for a grid size (vqc_tune.grid_blocks)
@@ -1544,7 +1589,8 @@ vqc_status jit_prepare(vqc_circuit c, bool with_adj = true) {
   std::vector<std::string> names;
   std::vector<int> threads;
   std::string src = "#include \"jit_pass.h\"\nnamespace vqc {\n";
-  src = jit_source_fwd(c, c->fwd, persist, src);
+  std::vector<uint16_t> tab;
+  src = jit_source_fwd(c, c->fwd, persist, src, tab);
   for (size_t p = 0; p < c->fwd.passes.size(); p++) {
     names.push_back("vqc_jf" + std::to_string(p));
     threads.push_back(1 << (c->fwd.passes[p].K - c->fwd.R));
@@ -1578,10 +1624,17 @@ vqc_status jit_prepare(vqc_circuit c, bool with_adj = true) {
     if (k < nf && persist) m->resident[k] = std::min(m->resident[k], c->tune.grid_blocks);
     else m->resident[k] = 0x7fffffff;  // one block per tile
   }
+  {
+    hipError_t ue = c->fwd.slots_buf.ensure(tab.size() * sizeof(uint16_t));
+    if (ue == hipSuccess)
+      ue = hipMemcpy(c->fwd.slots_buf.p, tab.data(), tab.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    if (ue != hipSuccess) return c->tune.jit > 0 ? VQC_ERR_HIP : VQC_OK;
+  }
   c->jit_ms = m->ms;
   c->jit_cached = m->cached;
   c->fwd.jit = m;
   c->fwd.jit_base = 0;
+  c->fwd.d_slots = c->fwd.slots_buf.as<uint16_t>();
   if (adj) {
     c->adj.jit = m;
     c->adj.jit_base = (int)nf;
@@ -1787,7 +1840,8 @@ hipError_t launch_jit_pass(const JitModule &m, size_t p, const Plan &P, const DJ
   if (p >= P.passes.size() || k >= m.fn.size() || k >= m.resident.size()) return hipErrorInvalidValue;
   const int64_t grid = std::min<int64_t>(total, m.resident[k]);
   DOverride o = ov;
-  void *args[] = {&jobs, &n_jobs, &total, &o};
+  const uint16_t *slots = P.d_slots;
+  void *args[] = {&jobs, &n_jobs, &total, &o, &slots};
   return hipModuleLaunchKernel(m.fn[k], (unsigned)grid, 1, 1, 1u << (P.passes[p].K - P.R), 1, 1, 0, st, args,
                                nullptr);
 }

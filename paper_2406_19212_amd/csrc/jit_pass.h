@@ -25,6 +25,8 @@
 //                          of l), chosen by the planner for this pass's access
 //                          patterns; SWB its width, SWDEF when it is the fixed
 //                          fold l ^ ((l >> 4) ^ (l >> 8)) & 15
+//   TAB                    offset of the pass's rows in the lane-slot table
+//                          (a kernel argument)
 //   DIN                    the first stage holds none of the low bits: it
 //                          reads HBM directly
 //   DOUT                   the last stage's wave lanes cover the output's low
@@ -184,19 +186,23 @@ __device__ __forceinline__ constexpr int joff(int j) {
 // Tile layouts over (lane t, register j): tile-local index lane(t) | reg(j).
 // The load layout (registers over the top R tile bits, lanes over the rest),
 // stage S's, and the store layout (lanes and registers in the order of the
-// output's physical bits).
+// output's physical bits).  ROW: the layout's row in the pass's lane-slot
+// table (the swizzled slot of lane(t), written by the planner).
 template <class P>
 struct JLoad {
+  static constexpr int ROW = 0;
   __device__ static __forceinline__ int lane(int t) { return t; }
   __device__ static __forceinline__ constexpr int reg(int j) { return j << (P::K - P::R); }
 };
 template <class P, int S>
 struct JStage {
+  static constexpr int ROW = 1 + S;
   __device__ static __forceinline__ int lane(int t) { return jbase<P, S>(t); }
   __device__ static __forceinline__ constexpr int reg(int j) { return joff<P, S>(j); }
 };
 template <class P>
 struct JStore {
+  static constexpr int ROW = P::NST + 1;
   __device__ static __forceinline__ int lane(int t) {
     int sl = 0;
 #pragma unroll
@@ -221,34 +227,46 @@ struct JLdsT<true> {
   using T = double;
 };
 
-// The registers of every lane from layout X to layout Y through the LDS
-// tile.  SPLIT: the tile holds one double per amplitude and the real and
-// imaginary halves go through it one after the other.  A lane's first write
-// goes to the slots it read itself in the exchange before (X is that
-// exchange's Y), so no barrier is needed before it.
+// a layout's slot of lane t as a byte offset into the LDS tile (tab: the
+// pass's lane-slot table at lane t)
+template <class P, class X>
+__device__ __forceinline__ int jrow(const uint16_t *tab) {
+  return tab[X::ROW << (P::K - P::R)];
+}
+
+// The registers of every lane from layout X (slot xs of lane t) to layout Y
+// (slot ys) through the LDS tile.  SPLIT: the tile holds one double per
+// amplitude and the real and imaginary halves go through it one after the
+// other.  A lane's first write goes to the slots it read itself in the
+// exchange before (X is that exchange's Y), so no barrier is needed before
+// it.
 template <class P, bool SPLIT, class X, class Y>
-__device__ __forceinline__ void jxch(typename JLdsT<SPLIT>::T *buf, c128 (&a)[1 << P::R], int t) {
+__device__ __forceinline__ void jxch(typename JLdsT<SPLIT>::T *buf, c128 (&a)[1 << P::R], int xs, int ys) {
   constexpr int NR = 1 << P::R;
-  const int xs = jswz<P>(X::lane(t)), ys = jswz<P>(Y::lane(t));
+  using T = typename JLdsT<SPLIT>::T;
+  constexpr int W = sizeof(T);
+  // xs, ys and the register offsets are byte offsets into the tile
+  char *b = reinterpret_cast<char *>(buf);
+  auto at = [&](int off) -> T & { return *reinterpret_cast<T *>(b + off); };
   if constexpr (!SPLIT) {
 #pragma unroll
-    for (int j = 0; j < NR; j++) buf[xs ^ jswz<P>(X::reg(j))] = a[j];
+    for (int j = 0; j < NR; j++) at(xs ^ (jswz<P>(X::reg(j)) * W)) = a[j];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NR; j++) a[j] = buf[ys ^ jswz<P>(Y::reg(j))];
+    for (int j = 0; j < NR; j++) a[j] = at(ys ^ (jswz<P>(Y::reg(j)) * W));
   } else {
     double re[NR];
 #pragma unroll
-    for (int j = 0; j < NR; j++) buf[xs ^ jswz<P>(X::reg(j))] = a[j].x;
+    for (int j = 0; j < NR; j++) at(xs ^ (jswz<P>(X::reg(j)) * W)) = a[j].x;
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NR; j++) re[j] = buf[ys ^ jswz<P>(Y::reg(j))];
+    for (int j = 0; j < NR; j++) re[j] = at(ys ^ (jswz<P>(Y::reg(j)) * W));
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NR; j++) buf[xs ^ jswz<P>(X::reg(j))] = a[j].y;
+    for (int j = 0; j < NR; j++) at(xs ^ (jswz<P>(X::reg(j)) * W)) = a[j].y;
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NR; j++) a[j] = make_double2(re[j], buf[ys ^ jswz<P>(Y::reg(j))]);
+    for (int j = 0; j < NR; j++) a[j] = make_double2(re[j], at(ys ^ (jswz<P>(Y::reg(j)) * W)));
   }
 }
 
@@ -276,8 +294,16 @@ __device__ __forceinline__ void jit_store_tile(const c128 (&a)[1 << P::R], gc128
 template <class P, bool SPLIT, int S>
 __device__ __forceinline__ void jit_stages(typename JLdsT<SPLIT>::T *buf, c128 (&a)[1 << P::R], DOp E,
                                            const DOp *prog, cmat *MT, int t, uint64_t gbase, int64_t tile,
-                                           gc128 *dst) {
+                                           gc128 *dst, const uint16_t *tab) {
   constexpr int K = P::K, R = P::R, NR = 1 << R;
+  // this exchange's slots, read before the stage's arithmetic hides them
+  constexpr bool LAST = S == P::NST - 1;
+  int xs = 0, ys = 0;
+  if constexpr (!(LAST && P::DOUT)) {
+    xs = jrow<P, JStage<P, S>>(tab);
+    if constexpr (LAST) ys = jrow<P, JStore<P>>(tab);
+    else ys = jrow<P, JStage<P, S + 1>>(tab);
+  }
   E = P::template stage<S>(a, E, prog, MT);
   if constexpr (S == P::NST - 1) {
     if constexpr (P::NH > 0) {
@@ -310,12 +336,12 @@ __device__ __forceinline__ void jit_stages(typename JLdsT<SPLIT>::T *buf, c128 (
         stg(&dst[gb | go], a[j]);
       }
     } else {
-      jxch<P, SPLIT, JStage<P, S>, JStore<P>>(buf, a, t);
+      jxch<P, SPLIT, JStage<P, S>, JStore<P>>(buf, a, xs, ys);
       jit_store_tile<P>(a, dst, tile, t);
     }
   } else {
-    jxch<P, SPLIT, JStage<P, S>, JStage<P, S + 1>>(buf, a, t);
-    jit_stages<P, SPLIT, S + 1>(buf, a, E, prog, MT, t, gbase, tile, dst);
+    jxch<P, SPLIT, JStage<P, S>, JStage<P, S + 1>>(buf, a, xs, ys);
+    jit_stages<P, SPLIT, S + 1>(buf, a, E, prog, MT, t, gbase, tile, dst, tab);
   }
 }
 
@@ -367,10 +393,11 @@ __device__ __forceinline__ void jit_load_tile(c128 (&r)[1 << P::R], const DJob *
 // LDS tile holds doubles (see jxch).
 template <class P, bool PERSIST, bool SPLIT>
 __device__ __forceinline__ void jit_pass_fwd(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units,
-                                             const DOverride &ov) {
+                                             const DOverride &ov, const uint16_t *__restrict__ slots) {
   constexpr int K = P::K, R = P::R, NR = 1 << R;
   __shared__ typename JLdsT<SPLIT>::T buf[1 << K];
   const int t = threadIdx.x;
+  const uint16_t *tab = slots + P::TAB + t;
   int64_t u = blockIdx.x;
   if (u >= total_units) return;
   c128 pf[NR];
@@ -396,11 +423,11 @@ __device__ __forceinline__ void jit_pass_fwd(const DJob *__restrict__ jobs, int 
     }
     if constexpr (P::NST == 0) {
       // a pass without ops only moves qubits
-      jxch<P, SPLIT, JLoad<P>, JStore<P>>(buf, a, t);
+      jxch<P, SPLIT, JLoad<P>, JStore<P>>(buf, a, jrow<P, JLoad<P>>(tab), jrow<P, JStore<P>>(tab));
       jit_store_tile<P>(a, dst, tile, t);
     } else {
-      if constexpr (!P::DIN) jxch<P, SPLIT, JLoad<P>, JStage<P, 0>>(buf, a, t);
-      jit_stages<P, SPLIT, 0>(buf, a, ldc(prog + P::G0), prog, MT, t, gbase, tile, dst);
+      if constexpr (!P::DIN) jxch<P, SPLIT, JLoad<P>, JStage<P, 0>>(buf, a, jrow<P, JLoad<P>>(tab), jrow<P, JStage<P, 0>>(tab));
+      jit_stages<P, SPLIT, 0>(buf, a, ldc(prog + P::G0), prog, MT, t, gbase, tile, dst, tab);
     }
     __syncthreads();  // the next tile overwrites the LDS tile
   }
