@@ -926,7 +926,6 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
   extern __shared__ c128 smem[];
   __shared__ double red[ADJ ? kMaxVarPerPass : 1][NW];
   c128 *la = smem;
-  c128 *lb = smem + (1 << K);
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
 
@@ -1001,6 +1000,44 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
     // direct HBM access for the first / last stage in execution order
     const bool din = ADJ ? (P->lowfree >> 1) & 1 : false;
     const bool dout = ADJ ? P->lowfree & 1 : (P->lowfree >> 1) & 1;
+    // LDS -> HBM in the pass's output layout (the input layout unless the
+    // pass moves qubits): lanes run over the output's lowest tile bits
+    auto store_out = [&](const c128 *lx, gc128 *d) {
+      uint64_t gbo = (uint64_t)tile;
+#pragma unroll
+      for (int i = 0; i < K; i++) gbo = ins0<uint64_t>(gbo, P->tqo[i]);
+      uint64_t so = 0;
+      int sl = 0;
+#pragma unroll
+      for (int i = 0; i < K - R; i++)
+        if ((t >> i) & 1) {
+          so |= 1ull << P->tqo[i];
+          sl |= 1 << P->lbo[i];
+        }
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        uint64_t oj = 0;
+        int ol = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) {
+            oj |= 1ull << P->tqo[K - R + i];
+            ol |= 1 << P->lbo[K - R + i];
+          }
+        stg(&d[gbo | so | oj], lx[swz(sl | ol)]);
+      }
+    };
+    // HBM -> LDS, coalesced over the low tile bits
+    auto load_in = [&](c128 *lx, const gc128 *sp) {
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        uint64_t oj = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) oj |= 1ull << P->tq[K - R + i];
+        lx[swz(j * T + t)] = ldg(&sp[gbase | st | oj]);
+      }
+    };
     if constexpr (!ADJ) {
       // the tile was prefetched by the previous iteration (or before the loop)
 #pragma unroll
@@ -1008,66 +1045,106 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
       const int64_t un = u + gridDim.x;
       if (un < total_units) prefetch(un);
       __syncthreads();
-    } else if (!din) {
-      // HBM -> LDS, coalesced over the low tile bits
+      for (int s = 0; s < nst; s++) {
+        const DStage S = ldc(&P->stages[s]);
+        int base = t;
 #pragma unroll
-      for (int j = 0; j < NR; j++) {
-        uint64_t oj = 0;
-#pragma unroll
-        for (int i = 0; i < R; i++)
-          if ((j >> i) & 1) oj |= 1ull << P->tq[K - R + i];
-        const uint64_t gi = gbase | st | oj;
-        la[swz(j * T + t)] = ldg(&src[gi]);
-        if constexpr (ADJ) lb[swz(j * T + t)] = ldg(&srcb[gi]);
-      }
-      __syncthreads();
-    }
-    for (int si = 0; si < nst; si++) {
-      const int s = ADJ ? nst - 1 - si : si;
-      const DStage S = ldc(&P->stages[s]);
-      int base = t;
-#pragma unroll
-      for (int i = 0; i < R; i++) base = ins0<int>(base, S.srt[i]);
-      int lo[NR];
-#pragma unroll
-      for (int j = 0; j < NR; j++) {
-        int o = 0;
-#pragma unroll
-        for (int i = 0; i < R; i++)
-          if ((j >> i) & 1) o |= 1 << S.rbit[i];
-        lo[j] = o;
-      }
-      const bool first = (si == 0) && din, last = (si == nst - 1) && dout;
-      uint64_t gb = 0;
-      if (first || last) {
-        // HBM address of local index base | lo[j]: gbase + scatter(base) + scatter(lo[j])
-        gb = gbase;
-#pragma unroll
-        for (int i = 0; i < K; i++)
-          if ((base >> i) & 1) gb |= 1ull << P->tq[i];
-      }
-      c128 a[NR];
-      [[maybe_unused]] c128 b[NR];
-      if (first) {
+        for (int i = 0; i < R; i++) base = ins0<int>(base, S.srt[i]);
+        int lo[NR];
 #pragma unroll
         for (int j = 0; j < NR; j++) {
-          uint64_t go = 0;
+          int o = 0;
 #pragma unroll
           for (int i = 0; i < R; i++)
-            if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
-          a[j] = ldg(&src[gb | go]);
-          if constexpr (ADJ) b[j] = ldg(&srcb[gb | go]);
+            if ((j >> i) & 1) o |= 1 << S.rbit[i];
+          lo[j] = o;
         }
-      } else {
+        const bool last = (s == nst - 1) && dout;
+        c128 a[NR];
 #pragma unroll
-        for (int j = 0; j < NR; j++) {
-          a[j] = la[swz(base | lo[j])];
-          if constexpr (ADJ) b[j] = lb[swz(base | lo[j])];
+        for (int j = 0; j < NR; j++) a[j] = la[swz(base | lo[j])];
+        rg_run<R, D4>(a, prog, S.g0, S.g1, MT);
+        if (last) {
+          // HBM address of local index base | lo[j]: gbase + scatter(base) + scatter(lo[j])
+          uint64_t gb = gbase;
+#pragma unroll
+          for (int i = 0; i < K; i++)
+            if ((base >> i) & 1) gb |= 1ull << P->tq[i];
+#pragma unroll
+          for (int j = 0; j < NR; j++) {
+            uint64_t go = 0;
+#pragma unroll
+            for (int i = 0; i < R; i++)
+              if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
+            stg(&dst[gb | go], a[j]);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < NR; j++) la[swz(base | lo[j])] = a[j];
+          __syncthreads();
         }
       }
-      if constexpr (!ADJ) {
-        rg_run<R, D4>(a, prog, S.g0, S.g1, MT);
-      } else {
+      if (!dout) store_out(la, dst);
+    } else {
+      // Phi and Psi share the one LDS tile: every change of layout moves Phi
+      // through it, then Psi (half the LDS of two tiles, so twice the
+      // resident blocks, for two more barriers per stage change).  Registers
+      // a, b carry a stage's amplitudes into the next; pb / plo: the layout
+      // Psi waits in until the next stage's read.
+      c128 a[NR], b[NR];
+      int pb = 0, plo[NR];
+#pragma unroll
+      for (int j = 0; j < NR; j++) plo[j] = 0;
+      if (!din) load_in(la, src);
+      __syncthreads();
+      for (int si = 0; si < nst; si++) {
+        const int s = nst - 1 - si;
+        const DStage S = ldc(&P->stages[s]);
+        int base = t;
+#pragma unroll
+        for (int i = 0; i < R; i++) base = ins0<int>(base, S.srt[i]);
+        int lo[NR];
+#pragma unroll
+        for (int j = 0; j < NR; j++) {
+          int o = 0;
+#pragma unroll
+          for (int i = 0; i < R; i++)
+            if ((j >> i) & 1) o |= 1 << S.rbit[i];
+          lo[j] = o;
+        }
+        const bool first = (si == 0) && din, last = (si == nst - 1) && dout;
+        uint64_t gb = 0;
+        if (first || last) {
+          gb = gbase;
+#pragma unroll
+          for (int i = 0; i < K; i++)
+            if ((base >> i) & 1) gb |= 1ull << P->tq[i];
+        }
+        if (first) {
+#pragma unroll
+          for (int j = 0; j < NR; j++) {
+            uint64_t go = 0;
+#pragma unroll
+            for (int i = 0; i < R; i++)
+              if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
+            a[j] = ldg(&src[gb | go]);
+            b[j] = ldg(&srcb[gb | go]);
+          }
+        } else {
+          // Phi is in the tile (loaded, or written by the previous stage)
+#pragma unroll
+          for (int j = 0; j < NR; j++) a[j] = la[swz(base | lo[j])];
+          __syncthreads();
+          if (si == 0) {
+            load_in(la, srcb);
+          } else {
+#pragma unroll
+            for (int j = 0; j < NR; j++) la[swz(pb | plo[j])] = b[j];
+          }
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < NR; j++) b[j] = la[swz(base | lo[j])];
+        }
         DOp E = ldc(&prog[S.g1 - 1]);
         for (int g = S.g1 - 1; g >= S.g0; g--) {
           lgkm_wait();
@@ -1099,53 +1176,41 @@ k_pass_lds(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units, DOver
           rg_apply_op<R, true, D4>(b, E, MT);  // Psi <- Q^dagger Psi
           E = En;
         }
-      }
-      if (last) {
+        if (last) {
 #pragma unroll
-        for (int j = 0; j < NR; j++) {
-          uint64_t go = 0;
+          for (int j = 0; j < NR; j++) {
+            uint64_t go = 0;
 #pragma unroll
-          for (int i = 0; i < R; i++)
-            if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
-          stg(&dst[gb | go], a[j]);
-          if constexpr (ADJ) stg(&dstb[gb | go], b[j]);
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < NR; j++) {
-          la[swz(base | lo[j])] = a[j];
-          if constexpr (ADJ) lb[swz(base | lo[j])] = b[j];
-        }
-        __syncthreads();
-      }
-    }
-    if (!dout) {
-      // LDS -> HBM in the pass's output layout (the input layout unless the
-      // pass moves qubits): lanes run over the output's lowest tile bits
-      uint64_t gbo = (uint64_t)tile;
-#pragma unroll
-      for (int i = 0; i < K; i++) gbo = ins0<uint64_t>(gbo, P->tqo[i]);
-      uint64_t so = 0;
-      int sl = 0;
-#pragma unroll
-      for (int i = 0; i < K - R; i++)
-        if ((t >> i) & 1) {
-          so |= 1ull << P->tqo[i];
-          sl |= 1 << P->lbo[i];
-        }
-#pragma unroll
-      for (int j = 0; j < NR; j++) {
-        uint64_t oj = 0;
-        int ol = 0;
-#pragma unroll
-        for (int i = 0; i < R; i++)
-          if ((j >> i) & 1) {
-            oj |= 1ull << P->tqo[K - R + i];
-            ol |= 1 << P->lbo[K - R + i];
+            for (int i = 0; i < R; i++)
+              if ((j >> i) & 1) go |= 1ull << tq_at(J.pass, S.rbit[i]);
+            stg(&dst[gb | go], a[j]);
+            stg(&dstb[gb | go], b[j]);
           }
-        const uint64_t gi = gbo | so | oj;
-        stg(&dst[gi], la[swz(sl | ol)]);
-        if constexpr (ADJ) stg(&dstb[gi], lb[swz(sl | ol)]);
+        } else {
+          // Phi into the tile in this stage's layout (the slots this lane
+          // read), Psi held back in registers until the next stage's read
+#pragma unroll
+          for (int j = 0; j < NR; j++) la[swz(base | lo[j])] = a[j];
+          pb = base;
+#pragma unroll
+          for (int j = 0; j < NR; j++) plo[j] = lo[j];
+          __syncthreads();
+        }
+      }
+      if (nst == 0) {
+        // a pass without ops only moves qubits
+        store_out(la, dst);
+        __syncthreads();
+        load_in(la, srcb);
+        __syncthreads();
+        store_out(la, dstb);
+      } else if (!dout) {
+        store_out(la, dst);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NR; j++) la[swz(pb | plo[j])] = b[j];
+        __syncthreads();
+        store_out(la, dstb);
       }
     }
     if constexpr (ADJ) {
@@ -1292,7 +1357,7 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
 template <int K, int R, int MODE>
 hipError_t launch_lds_t(const DJob *jobs, int n_jobs, int64_t total, int grid, const DOverride &ov,
                         hipStream_t st) {
-  const size_t shmem = ((MODE & 1) ? 2 : 1) * (size_t(1) << K) * sizeof(c128);
+  const size_t shmem = (size_t(1) << K) * sizeof(c128);  // the adjoint shares one tile between Phi and Psi
   static bool attr_set = false;
   if (!attr_set && shmem > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)k_pass_lds<K, R, MODE>,
