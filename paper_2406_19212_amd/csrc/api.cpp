@@ -497,18 +497,54 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
     };
     std::vector<PassH::Stage> best;
     std::vector<int> best_rest;
-    for (int attempt = 0; attempt < (reg_only ? 1 : 2); attempt++) {
+    // attempts 2 and 3 (unordered kinds only): each stage's register bits are
+    // the R-subset of the tile's bits that takes the most of the remaining
+    // ops (first fit restricted to the subset), the first stage of attempt 3
+    // without low bits
+    bool ordered_pass = false;
+    for (int i : chosen) ordered_pass = ordered_pass || E[i].kind == GK_DENSE4 || E[i].kind == GK_DEPOL4;
+    const int n_attempts = reg_only ? 1 : (ordered_pass ? 2 : 4);
+    std::vector<uint64_t> subsets;
+    if (n_attempts > 2) {
+      for (uint64_t m = 0; m < (1ull << TK); m++)
+        if (popc(m) == R) subsets.push_back(m);
+    }
+    auto local_mask = [&](int i) {
+      uint64_t lm = 0;
+      for (int t = 0; t < E[i].nq; t++) lm |= 1ull << loc[E[i].q[t]];
+      return lm;
+    };
+    for (int attempt = 0; attempt < n_attempts; attempt++) {
       std::vector<PassH::Stage> stages;
       std::vector<int> srem = chosen, rest;
+      bool failed = false;
       while (!srem.empty()) {
         uint64_t reg = 0, sblk = 0;
-        if (attempt == 1 && stages.empty()) sblk = lowloc;  // first stage: defer low bits
+        if ((attempt == 1 || attempt == 3) && stages.empty()) sblk = lowloc;  // first stage: defer low bits
+        uint64_t only = ~0ull;  // register bits a stage may use
+        if (attempt >= 2) {
+          int best_n = 0;
+          for (uint64_t Q : subsets) {
+            if (Q & sblk) continue;
+            uint64_t blk = 0;
+            int n = 0;
+            for (int i : srem) {
+              const uint64_t lm = local_mask(i);
+              if (!(lm & blk) && !(lm & ~Q)) n++;
+              else blk |= lm;
+            }
+            if (n > best_n) {
+              best_n = n;
+              only = Q;
+            }
+          }
+          if (best_n == 0) only = ~0ull;
+        }
         int order4[4] = {-1, -1, -1, -1};
         std::vector<int> st, sleft;
         for (int i : srem) {
-          uint64_t lm = 0;
-          for (int t = 0; t < E[i].nq; t++) lm |= 1ull << loc[E[i].q[t]];
-          bool ok = !(lm & sblk) && popc(reg | lm) <= R;
+          const uint64_t lm = local_mask(i);
+          bool ok = !(lm & sblk) && !(lm & ~only) && popc(reg | lm) <= R;
           const bool ordered = E[i].kind == GK_DENSE4 || E[i].kind == GK_DEPOL4;  // register bits 0..3 in order
           if (ok && ordered) {
             if (order4[0] >= 0) {
@@ -527,18 +563,20 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
         }
         if (st.empty()) {
           // nothing fitted (possible only when the first stage deferred the
-          // low bits): drop the deferral for this stage
-          if (attempt == 1 && stages.empty()) { attempt = 2; break; }
+          // low bits): this attempt is dropped
+          if ((attempt == 1 || attempt == 3) && stages.empty()) { failed = true; break; }
           // an op wider than the register set cannot be planned; take it
           // alone so the loop always progresses (lowering never emits one)
           st.push_back(sleft.front());
           sleft.erase(sleft.begin());
+          reg |= local_mask(st.back());
         }
         srem.swap(sleft);
         PassH::Stage S;
         if (order4[0] >= 0) {
           for (int t = 0; t < 4; t++) S.rbit[t] = order4[t];
         } else {
+          if (only != ~0ull && popc(only) == R && !(reg & ~only)) reg = only;
           // pad with bits outside the low range first, so a stage stays low-free
           for (int b = TK - 1; b >= 0 && popc(reg) < R; b--)
             if (!((lowloc >> b) & 1) && !((reg >> b) & 1)) reg |= 1ull << b;
@@ -554,7 +592,7 @@ void plan_passes(const std::vector<Elem> &E, int nbits, int K, int c, int R, boo
           break;
         }
       }
-      if (attempt == 2) continue;
+      if (failed) continue;
       if (best.empty() || cost(stages) < cost(best)) {
         best = stages;
         best_rest = rest;
