@@ -1499,11 +1499,27 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::strin
         n_ops++;
       }
     const int g0 = g;
+    // execution order (stages and their ops in reverse); ops of kinds that
+    // read no program entry (controlled X) skip the entry chain, each other op
+    // loading the entry of the next such op
+    std::vector<int> first_op(nst + 1, 0);
+    for (int si = 0; si < nst; si++) first_op[si + 1] = first_op[si] + (int)ph.stages[si].elems.size();
+    std::vector<int> exec_gi, exec_need;
+    for (int si = nst - 1; si >= 0; si--)
+      for (int q = (int)ph.stages[si].elems.size() - 1; q >= 0; q--) {
+        const int kind = c->elems[ph.stages[si].elems[q]].kind;
+        exec_gi.push_back(g0 + first_op[si] + q);
+        exec_need.push_back(!(kind == GK_CX || kind == GK_NONE));
+      }
+    std::vector<int> next_exec(exec_gi.size() + 1, g0 + std::max(n_ops - 1, 0));
+    for (int k = (int)exec_gi.size() - 1; k >= 0; k--) next_exec[k] = exec_need[k] ? exec_gi[k] : next_exec[k + 1];
+    std::vector<int> exec_pos(n_ops, 0);
+    for (size_t k = 0; k < exec_gi.size(); k++) exec_pos[exec_gi[k] - g0] = (int)k;
     std::snprintf(buf, sizeof(buf),
                   "struct JA%zu {\n  static constexpr int K = %d, R = %d, NST = %d, PROG = %d, GLAST = %d, NVAR = %d;\n"
                   "  static constexpr int WS = %d, NW = %d;\n"
                   "  static constexpr bool DIN = %s, DOUT = %s;\n",
-                  p, K, R, nst, P.prog, g0 + n_ops - 1, (int)vslot.size(), WS, NW,
+                  p, K, R, nst, P.prog, next_exec[0], (int)vslot.size(), WS, NW,
                   (ph.lowfree & 2) ? "true" : "false", (ph.lowfree & 1) ? "true" : "false");
     s += buf;
     s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("VSLOT", vslot) +
@@ -1550,10 +1566,20 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::strin
         const int b0 = e.nq > 0 ? regpos[loc[e.q[0]]] : 0, b1 = e.nq > 1 ? regpos[loc[e.q[1]]] : 0;
         const int b2 = e.nq > 2 ? regpos[loc[e.q[2]]] : 0;
         const bool gen = !e.d.empty() && e.d[0].kind >= GK_GENX && e.d[0].kind <= GK_GENZ;
+        const int xp = exec_pos[gi - g0];
+        if (!exec_need[xp]) {
+          std::snprintf(buf, sizeof(buf),
+                        "      {\n        __builtin_amdgcn_sched_barrier(0);\n"
+                        "        japply<R, true, %d, %d, %d, %d>(a, E, M);\n        japply<R, true, %d, %d, %d, %d>(b, E, M);\n"
+                        "        __builtin_amdgcn_sched_barrier(0);\n      }\n",
+                        e.kind, b0, b1, b2, e.kind, b0, b1, b2);
+          s += buf;
+          continue;
+        }
         std::snprintf(buf, sizeof(buf),
                       "      {\n        lgkm_wait();\n        const DOp En = ldc(prog + %d);\n"
                       "        __builtin_amdgcn_sched_barrier(0);\n",
-                      gi - 1);
+                      next_exec[xp + 1]);
         s += buf;
         if (gen) {
           std::snprintf(buf, sizeof(buf),

@@ -447,11 +447,12 @@ __device__ __forceinline__ void jit_pass_fwd(const DJob *__restrict__ jobs, int 
 //   template <int S> static DOp astage(a, b, E, prog, M, red, lane, wave)
 //                          stage S's ops in reverse (calls of the helpers below)
 
-// wave sum of a tile's partial, stored by lane 0 into the reduction slot
+// wave sum of a tile's partial, stored by the wave's last lane (which holds
+// it) into the reduction slot
 template <int WS, int NW>
 __device__ __forceinline__ void jred(double (*red)[NW], int slot, double v, int lane, int wave) {
-  v = wave_sum<WS>(v);
-  if (lane == 0) red[slot][wave] = v;
+  v = wave_sum_last<WS>(v);
+  if (lane == WS - 1) red[slot][wave] = v;
 }
 
 // Re<b| D |a> over the lane's groups for a derivative matrix D of kind DK

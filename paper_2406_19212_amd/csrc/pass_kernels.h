@@ -873,6 +873,24 @@ __device__ __forceinline__ double dpp_d(double v) {
 // the row-15 and row-31 broadcasts), all in the VALU, and the total is read
 // from lane 63 into a scalar; narrower groups use lane shuffles.  The result
 // is the same in every lane.
+// the sum over a wave of W lanes, valid in lane W - 1 (all lanes for W < 64)
+template <int W>
+__device__ __forceinline__ double wave_sum_last(double v) {
+  if constexpr (W == 64) {
+    v += dpp_d<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);       // row_half_mirror: sum of 8
+    v += dpp_d<0x140>(v);       // row_mirror: sum of 16
+    v += dpp_d<0x142, 0xA>(v);  // row_bcast15 into rows 1 and 3
+    v += dpp_d<0x143, 0xC>(v);  // row_bcast31 into rows 2 and 3: lane 63 = total
+    return v;
+  } else {
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+    return v;
+  }
+}
+
 template <int W>
 __device__ __forceinline__ double wave_sum(double v) {
   if constexpr (W == 64) {
