@@ -139,3 +139,34 @@ def test_code_cache_reused(tmp_path):
             del os.environ["VQC_JIT_CACHE"]
         else:
             os.environ["VQC_JIT_CACHE"] = old
+
+
+@pytest.mark.parametrize("env", [{"VQC_JIT_FWD_SPLIT": "0"}, {"VQC_JIT_HSQRT": "0"}, {"VQC_JIT_RECFREE": "0"},
+                                 {"VQC_JIT_ADJ_SWZ": "1"},
+                                 {"VQC_JIT_FWD_SPLIT": "0", "VQC_JIT_HSQRT": "0", "VQC_JIT_RECFREE": "0"}])
+def test_specialised_pass_variants(env, monkeypatch):
+    """The specialised passes' alternative forms (whole-amplitude LDS tile,
+    rotation forms of the sqrt gates, a program entry read by every op, a
+    searched LDS swizzle for the adjoint) give the oracle's state and
+    gradient: a random grid circuit with qubit moves (sqrt gates, fSim) and
+    the mixed-kind circuit."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    n = 20
+    ops = W.rqc_grid(4, 5, 8, 71)
+    c = _jit_circuit(n, ops, tile_bits=11, low_bits=4, remap=1)
+    psi0 = W.random_state(n, 9)
+    st = State(n, init=psi0)
+    c.apply(st)
+    assert maxdiff(st.numpy(), oracle.run(n, ops, init=psi0)) < AMP_TOL
+    n = 12
+    ops, th = _mixed_gate_circuit(n, 812, 9)
+    c = _jit_circuit(n, ops, tile_bits=11, low_bits=3, reg_bits=3, remap=1)
+    tht = torch.tensor(th, device="cuda")
+    st = State(n)
+    c.apply(st, tht)
+    terms = W.heisenberg_1d(n, 0.3, 1.0)
+    g, e = c.backward(tht, st, terms)
+    e_ref, g_ref, _ = oracle.grad_pure(n, ops, th, terms)
+    assert abs(e - e_ref) < AMP_TOL
+    assert maxdiff(g.cpu().numpy(), g_ref) < GRAD_TOL
