@@ -143,7 +143,14 @@ typedef struct {
  * VQC_ERR_HIP if the compile fails), -1 off, 0 default (on from 20 qubits
  * with tiles of at most 11 qubits, silently off if the compile fails).  The
  * environment variable VQC_JIT=0 (or 1) turns them off (on) for every
- * eligible circuit. */
+ * eligible circuit.  Read at circuit creation, each 0/1: VQC_JIT_FWD_SPLIT
+ * (forward tiles exchanged through LDS as real and imaginary halves; default
+ * 1), VQC_JIT_HSQRT (phase-factored sqrt(X), sqrt(Y), sqrt(W) applied times
+ * sqrt(2), the tile rescaled once per pass; default 1), VQC_JIT_RECFREE (ops
+ * without a parameter record skip the program-entry chain; default 1),
+ * VQC_JIT_ADJ_SHARED (adjoint Phi and Psi share one LDS tile; default 1),
+ * VQC_JIT_ADJ_SWZ (adjoint passes search an LDS bank swizzle of their own;
+ * default 0).  VQC_JIT_CACHE names the code-object cache directory. */
 typedef struct {
   int tile_bits;
   int low_bits;
