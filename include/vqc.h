@@ -148,9 +148,12 @@ typedef struct {
  * 1), VQC_JIT_HSQRT (phase-factored sqrt(X), sqrt(Y), sqrt(W) applied times
  * sqrt(2), the tile rescaled once per pass; default 1), VQC_JIT_RECFREE (ops
  * without a parameter record skip the program-entry chain; default 1),
- * VQC_JIT_ADJ_SHARED (adjoint Phi and Psi share one LDS tile; default 1),
- * VQC_JIT_ADJ_SWZ (adjoint passes search an LDS bank swizzle of their own;
- * default 0).  VQC_JIT_CACHE names the code-object cache directory. */
+ * VQC_JIT_ADJ_SPLIT (adjoint driver: 1, the default, reads lane slots from
+ * the planner's table and moves the tile through LDS as real and imaginary
+ * halves; 2 the same with whole amplitudes; 0 the older driver, where
+ * VQC_JIT_ADJ_SHARED (Phi and Psi share one LDS tile; default 1) and
+ * VQC_JIT_ADJ_SWZ (a searched swizzle instead of the fixed fold; default 0)
+ * apply).  VQC_JIT_CACHE names the code-object cache directory. */
 typedef struct {
   int tile_bits;
   int low_bits;

@@ -1462,7 +1462,17 @@ std::string jit_source_fwd(vqc_circuit c, const Plan &P, bool persist, std::stri
 // description JA<p> with its stages' ops in reverse program order, each op
 // with its derivative reductions (generator form before Phi is uncomputed,
 // derivative matrices after), and the kernel vqc_ja<p>.
-std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::string s) {
+// adjoint driver (VQC_JIT_ADJ_SPLIT): 1 (default) jit_pass_adj2, lane slots
+// from the table and the tile exchanged as real and imaginary halves; 2 the
+// same with whole amplitudes; 0 jit_pass_adj (lane slots computed, fixed
+// fold, VQC_JIT_ADJ_SHARED / VQC_JIT_ADJ_SWZ apply)
+int jit_adj_driver() {
+  const char *e = std::getenv("VQC_JIT_ADJ_SPLIT");
+  return e && (e[0] == '0' || e[0] == '2') ? e[0] - '0' : 1;
+}
+
+std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::string s, std::vector<uint16_t> &tab) {
+  const int drv = jit_adj_driver();
   char buf[512];
   auto arr = [&](const char *name, const std::vector<int> &v) {
     std::string r = std::string("  static constexpr int ") + name + "[" + std::to_string(std::max<size_t>(1, v.size())) +
@@ -1522,8 +1532,17 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::strin
                   p, K, R, nst, P.prog, next_exec[0], (int)vslot.size(), WS, NW,
                   (ph.lowfree & 2) ? "true" : "false", (ph.lowfree & 1) ? "true" : "false");
     s += buf;
-    s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("VSLOT", vslot) +
-         swizzle_decl(lds_swizzle(K, R, ph, lbo, 4, 2 * p + 2, jit_adj_swizzle()), 4);
+    if (drv == 0) {
+      s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("VSLOT", vslot) +
+           swizzle_decl(lds_swizzle(K, R, ph, lbo, 4, 2 * p + 2, jit_adj_swizzle()), 4);
+    } else {
+      const int swb = drv == 1 ? 5 : 4;
+      const std::vector<int> col = lds_swizzle(K, R, ph, lbo, swb, 2 * p + 2);
+      std::snprintf(buf, sizeof(buf), "  static constexpr int TAB = %zu;\n", tab.size());
+      s += buf;
+      lane_slots(K, R, ph, lbo, col, swb, drv == 1 ? 8 : 16, tab);
+      s += arr("TQ", tq) + arr("TQO", tqo) + arr("LBO", lbo) + arr("VSLOT", vslot) + swizzle_decl(col, swb);
+    }
     const int rows = std::max(nst, 1);
     std::string rb = "  static constexpr int RBIT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
     std::string sr = "  static constexpr int SRT[" + std::to_string(rows) + "][" + std::to_string(R) + "] = {";
@@ -1608,9 +1627,15 @@ std::string jit_source_adj(vqc_circuit c, const Plan &P, bool shared, std::strin
     g = g0 + n_ops;
     std::snprintf(buf, sizeof(buf),
                   "extern \"C\" __global__ void __launch_bounds__(%d) vqc_ja%zu(const DJob *__restrict__ jobs, "
-                  "int n_jobs, int64_t total_units, DOverride ov, const uint16_t *) {\n  jit_pass_adj<JA%zu, %s>(jobs, "
-                  "n_jobs, total_units, ov);\n}\n",
-                  T, p, p, shared ? "true" : "false");
+                  "int n_jobs, int64_t total_units, DOverride ov, const uint16_t *slots) {\n  %s",
+                  T, p, "");
+    s += buf;
+    if (drv == 0)
+      std::snprintf(buf, sizeof(buf), "jit_pass_adj<JA%zu, %s>(jobs, n_jobs, total_units, ov);\n}\n", p,
+                    shared ? "true" : "false");
+    else
+      std::snprintf(buf, sizeof(buf), "jit_pass_adj2<JA%zu, %s>(jobs, n_jobs, total_units, ov, slots);\n}\n", p,
+                    drv == 1 ? "true" : "false");
     s += buf;
   }
   return s;
@@ -1645,6 +1670,7 @@ vqc_status jit_prepare(vqc_circuit c, bool with_adj = true) {
   c->fwd.jit.reset();
   c->adj.jit.reset();
   c->fwd.d_slots = nullptr;
+  c->adj.d_slots = nullptr;
   c->jit_ms = 0;
   if (!jit_wanted(c)) return VQC_OK;
   // persistent grids when the caller asked for a grid size (vqc_tune.grid_blocks)
@@ -1662,7 +1688,7 @@ vqc_status jit_prepare(vqc_circuit c, bool with_adj = true) {
   if (adj) {
     // Phi and Psi share one LDS tile (set VQC_JIT_ADJ_SHARED=0 for one each)
     const char *sh = std::getenv("VQC_JIT_ADJ_SHARED");
-    src = jit_source_adj(c, c->adj, !(sh && sh[0] == '0'), src);
+    src = jit_source_adj(c, c->adj, !(sh && sh[0] == '0'), src, tab);
     for (size_t p = 0; p < c->adj.passes.size(); p++) {
       names.push_back("vqc_ja" + std::to_string(p));
       threads.push_back(1 << (c->adj.passes[p].K - c->adj.R));
@@ -1702,6 +1728,7 @@ vqc_status jit_prepare(vqc_circuit c, bool with_adj = true) {
   if (adj) {
     c->adj.jit = m;
     c->adj.jit_base = (int)nf;
+    c->adj.d_slots = c->fwd.d_slots;  // the adjoint's rows follow the forward's in one table
   }
   return VQC_OK;
 }

@@ -679,4 +679,152 @@ __device__ __forceinline__ void jit_pass_adj(const DJob *__restrict__ jobs, int 
   }
 }
 
+// ---------------------------------------------- adjoint pass on lane slots
+// The same step of Alg. 2 with the forward pass's tile machinery: the tile's
+// layouts exchanged through LDS by jxch (SPLIT: as real and imaginary halves,
+// half the LDS), lane slots read from the planner's table (P::TAB), Phi and
+// Psi moved one after the other through the one tile.
+
+// the 2^R amplitudes of lane t in the load layout, read from HBM
+template <class P>
+__device__ __forceinline__ void jit_load_regs(c128 (&r)[1 << P::R], const gc128 *src, uint64_t gbase, int t) {
+  constexpr int K = P::K, R = P::R, NR = 1 << R;
+  uint64_t g = gbase;
+#pragma unroll
+  for (int i = 0; i < K - R; i++) g |= (uint64_t)((t >> i) & 1) << P::TQ[i];
+#pragma unroll
+  for (int j = 0; j < NR; j++) {
+    uint64_t oj = 0;
+#pragma unroll
+    for (int i = 0; i < R; i++)
+      if ((j >> i) & 1) oj |= 1ull << P::TQ[K - R + i];
+    r[j] = ldg(&src[g | oj]);
+  }
+}
+
+// stages S .. 0 (reverse order); a and b hold stage S's registers on entry
+template <class P, bool SPLIT, int S, int NW>
+__device__ __forceinline__ void jit_astages2(typename JLdsT<SPLIT>::T *buf, c128 (&a)[1 << P::R],
+                                             c128 (&b)[1 << P::R], DOp E, const DOp *prog, cmat *MT, int t,
+                                             uint64_t gbase, int64_t tile, gc128 *dst, gc128 *dstb,
+                                             double (*red)[NW], const uint16_t *tab) {
+  constexpr int K = P::K, R = P::R, NR = 1 << R;
+  const int lane = t & 63, wave = t >> 6;
+  // this stage's exchange slots, read before its arithmetic hides them
+  int xs = 0, ys = 0;
+  if constexpr (!(S == 0 && P::DOUT)) {
+    xs = jrow<P, JStage<P, S>>(tab);
+    if constexpr (S == 0) ys = jrow<P, JStore<P>>(tab);
+    else ys = jrow<P, JStage<P, (S > 0 ? S - 1 : 0)>>(tab);
+  }
+  E = P::template astage<S>(a, b, E, prog, MT, red, lane, wave);
+  if constexpr (S == 0) {
+    if constexpr (P::DOUT) {
+      const int base = jbase<P, 0>(t);
+      uint64_t gb = gbase;
+#pragma unroll
+      for (int i = 0; i < K; i++)
+        if ((base >> i) & 1) gb |= 1ull << P::TQ[i];
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        uint64_t go = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) go |= 1ull << P::TQ[P::RBIT[0][i]];
+        stg(&dst[gb | go], a[j]);
+        stg(&dstb[gb | go], b[j]);
+      }
+      __syncthreads();  // every wave's reduction entries are written
+    } else {
+      jxch<P, SPLIT, JStage<P, 0>, JStore<P>>(buf, a, xs, ys);
+      jit_store_tile<P>(a, dst, tile, t);
+      __syncthreads();  // other lanes may still read Phi from this lane's stage slots
+      jxch<P, SPLIT, JStage<P, 0>, JStore<P>>(buf, b, xs, ys);
+      jit_store_tile<P>(b, dstb, tile, t);
+    }
+  } else {
+    jxch<P, SPLIT, JStage<P, S>, JStage<P, S - 1>>(buf, a, xs, ys);
+    __syncthreads();
+    jxch<P, SPLIT, JStage<P, S>, JStage<P, S - 1>>(buf, b, xs, ys);
+    jit_astages2<P, SPLIT, S - 1, NW>(buf, a, b, E, prog, MT, t, gbase, tile, dst, dstb, red, tab);
+  }
+}
+
+template <class P, bool SPLIT>
+__device__ __forceinline__ void jit_pass_adj2(const DJob *__restrict__ jobs, int n_jobs, int64_t total_units,
+                                              const DOverride &ov, const uint16_t *__restrict__ slots) {
+  constexpr int K = P::K, R = P::R, NR = 1 << R, T = 1 << (K - R);
+  constexpr int NW = (T + 63) / 64;
+  __shared__ typename JLdsT<SPLIT>::T buf[1 << K];
+  __shared__ double red[P::NVAR > 0 ? P::NVAR : 1][NW];
+  const int t = threadIdx.x;
+  const int64_t u = blockIdx.x;
+  if (u >= total_units) return;
+  const uint16_t *tab = slots + P::TAB + t;
+  const DJob J = ldc(&jobs[jit_job(jobs, n_jobs, u, ov)]);
+  const int64_t tile = u - J.unit0;
+  const gc128 *src = (const gc128 *)(ov.use ? ov.a : J.a);
+  const gc128 *srcb = (const gc128 *)(ov.use ? ov.b : J.b);
+  gc128 *dst = (gc128 *)(ov.use ? ov.a : J.a);
+  gc128 *dstb = (gc128 *)(ov.use ? ov.b : J.b);
+  if ((ov.use ? ov.mode : J.mode) == 1) {
+    dst = (gc128 *)(ov.use ? ov.a2 : J.a2);
+    dstb = (gc128 *)(ov.use ? ov.b2 : J.b2);
+  }
+  cmat *MT = (cmat *)(ov.use ? ov.mats : J.mats);
+  const DOp *prog = (const DOp *)(MT + P::PROG) + 1;
+  double *PT = ov.use ? ov.partials : J.partials;
+  uint64_t gbase = (uint64_t)tile;
+#pragma unroll
+  for (int i = 0; i < K; i++) gbase = ins0<uint64_t>(gbase, P::TQ[i]);
+  c128 a[NR], b[NR];
+  if constexpr (P::NST == 0) {
+    // a pass without ops only moves qubits
+    const int xs = jrow<P, JLoad<P>>(tab), ys = jrow<P, JStore<P>>(tab);
+    jit_load_regs<P>(a, src, gbase, t);
+    jxch<P, SPLIT, JLoad<P>, JStore<P>>(buf, a, xs, ys);
+    jit_store_tile<P>(a, dst, tile, t);
+    jit_load_regs<P>(b, srcb, gbase, t);
+    __syncthreads();
+    jxch<P, SPLIT, JLoad<P>, JStore<P>>(buf, b, xs, ys);
+    jit_store_tile<P>(b, dstb, tile, t);
+  } else {
+    constexpr int S = P::NST - 1;
+    const DOp E = ldc(prog + P::GLAST);  // the pass's last op runs first
+    if constexpr (P::DIN) {
+      // the first stage's lanes run over the low tile bits: read HBM directly
+      const int base = jbase<P, S>(t);
+      uint64_t gb = gbase;
+#pragma unroll
+      for (int i = 0; i < K; i++)
+        if ((base >> i) & 1) gb |= 1ull << P::TQ[i];
+#pragma unroll
+      for (int j = 0; j < NR; j++) {
+        uint64_t go = 0;
+#pragma unroll
+        for (int i = 0; i < R; i++)
+          if ((j >> i) & 1) go |= 1ull << P::TQ[P::RBIT[S][i]];
+        a[j] = ldg(&src[gb | go]);
+        b[j] = ldg(&srcb[gb | go]);
+      }
+    } else {
+      const int xs = jrow<P, JLoad<P>>(tab), ys = jrow<P, JStage<P, S>>(tab);
+      jit_load_regs<P>(a, src, gbase, t);
+      jit_load_regs<P>(b, srcb, gbase, t);
+      jxch<P, SPLIT, JLoad<P>, JStage<P, S>>(buf, a, xs, ys);
+      __syncthreads();
+      jxch<P, SPLIT, JLoad<P>, JStage<P, S>>(buf, b, xs, ys);
+    }
+    jit_astages2<P, SPLIT, S, NW>(buf, a, b, E, prog, MT, t, gbase, tile, dst, dstb, red, tab);
+  }
+  if constexpr (P::NVAR > 0) {
+    for (int v = t; v < P::NVAR; v += T) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; w++) sum += red[v][w];
+      PT[(int64_t)P::VSLOT[v] * J.n_units + tile] = sum;
+    }
+  }
+}
+
 }  // namespace vqc

@@ -142,12 +142,14 @@ def test_code_cache_reused(tmp_path):
 
 
 @pytest.mark.parametrize("env", [{"VQC_JIT_FWD_SPLIT": "0"}, {"VQC_JIT_HSQRT": "0"}, {"VQC_JIT_RECFREE": "0"},
-                                 {"VQC_JIT_ADJ_SWZ": "1"},
+                                 {"VQC_JIT_ADJ_SPLIT": "2"}, {"VQC_JIT_ADJ_SPLIT": "0"},
+                                 {"VQC_JIT_ADJ_SPLIT": "0", "VQC_JIT_ADJ_SWZ": "1"},
                                  {"VQC_JIT_FWD_SPLIT": "0", "VQC_JIT_HSQRT": "0", "VQC_JIT_RECFREE": "0"}])
 def test_specialised_pass_variants(env, monkeypatch):
     """The specialised passes' alternative forms (whole-amplitude LDS tile,
-    rotation forms of the sqrt gates, a program entry read by every op, a
-    searched LDS swizzle for the adjoint) give the oracle's state and
+    rotation forms of the sqrt gates, a program entry read by every op, the
+    adjoint on whole amplitudes or on its older driver with the fixed fold or a
+    searched swizzle) give the oracle's state and
     gradient: a random grid circuit with qubit moves (sqrt gates, fSim) and
     the mixed-kind circuit."""
     for k, v in env.items():
