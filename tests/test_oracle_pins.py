@@ -74,7 +74,7 @@ def unvec(v, n):
 
 # ------------------------------------------------------------- application
 
-@pytest.mark.parametrize("n", [1, 3, 6])
+@pytest.mark.parametrize("n", [1, 3, 6, 10])
 def test_apply_1q_every_position_vs_kron(oracle_mod, n):
     psi = W.random_state(n, 11 + n)
     for q in range(n):
@@ -96,6 +96,32 @@ def test_apply_2q_every_pair_vs_dense(oracle_mod, n):
             v = psi.copy()
             oracle_mod.apply_matrix(v, n, [a, b], G)
             assert np.max(np.abs(v - dense_op(n, [a, b], G) @ psi)) < 1e-14
+
+
+def test_apply_at_ten_qubits_vs_dense(oracle_mod):
+    # the dense-operator pins up to n = 10: two- and three-qubit matrices on
+    # far-apart, reversed and adjacent positions, then a sequence of 24 random
+    # one-, two- and three-qubit matrices against the product of their dense
+    # operators applied to |0..0>
+    n = 10
+    psi = W.random_state(n, 1010)
+    for k, qs in enumerate([(0, 9), (9, 0), (3, 7), (7, 3), (4, 5), (8, 1), (9, 0, 5), (2, 8, 6)]):
+        G = W.random_unitary(1 << len(qs), 500 + k)
+        v = psi.copy()
+        oracle_mod.apply_matrix(v, n, list(qs), G)
+        assert np.max(np.abs(v - dense_op(n, list(qs), G) @ psi)) < 1e-13, qs
+    rng = np.random.default_rng(1011)
+    v = np.zeros(1 << n, complex)
+    v[0] = 1
+    ref = v.copy()
+    for k in range(24):
+        m = 1 + k % 3
+        qs = [int(q) for q in rng.choice(n, size=m, replace=False)]
+        G = W.random_unitary(1 << m, 600 + k)
+        oracle_mod.apply_matrix(v, n, qs, G)
+        ref = dense_op(n, qs, G) @ ref
+    assert abs(np.linalg.norm(v) - 1) < 1e-13
+    assert np.max(np.abs(v - ref)) < 1e-13
 
 
 def test_apply_2q_adjacent_matches_kron(oracle_mod):
