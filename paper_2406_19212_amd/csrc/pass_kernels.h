@@ -1372,28 +1372,48 @@ __global__ void __launch_bounds__(256) k_pass_reg(const DJob *__restrict__ jobs,
 
 
 #ifndef __HIPCC_RTC__  // host launchers
+}  // namespace vqc
+#include <atomic>
+namespace vqc {
+
+// Per-device launch facts of one kernel instantiation, shared by every handle
+// and stream of the process: whether the dynamic-LDS limit was raised and how
+// many blocks the chip holds at once.  Racing first calls compute and store
+// the same values (atomics, so no torn or unordered reads).
+constexpr int kLaunchMaxDev = 64;
+struct LaunchFacts {
+  std::atomic<int> attr_set[kLaunchMaxDev];
+  std::atomic<int> resident[kLaunchMaxDev];
+};
+
 template <int K, int R, int MODE>
 hipError_t launch_lds_t(const DJob *jobs, int n_jobs, int64_t total, int grid, const DOverride &ov,
                         hipStream_t st) {
   const size_t shmem = (size_t(1) << K) * sizeof(c128);  // the adjoint shares one tile between Phi and Psi
-  static bool attr_set = false;
-  if (!attr_set && shmem > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_pass_lds<K, R, MODE>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  static LaunchFacts facts;  // zero-initialised (static storage)
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kLaunchMaxDev) return hipErrorInvalidDevice;
+  if (shmem > 65536 && !facts.attr_set[dev].load(std::memory_order_acquire)) {
+    e = hipFuncSetAttribute((const void *)k_pass_lds<K, R, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shmem);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    facts.attr_set[dev].store(1, std::memory_order_release);
   }
   int g = grid;
   if (g <= 0) {
     // persistent grid: as many resident blocks as the chip holds
-    static int resident = 0;
+    int resident = facts.resident[dev].load(std::memory_order_acquire);
     if (!resident) {
-      int per_cu = 0, dev = 0, cus = 0;
-      (void)hipGetDevice(&dev);
-      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_pass_lds<K, R, MODE>, 1 << (K - R),
-                                                         shmem);
+      int per_cu = 0, cus = 0;
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_pass_lds<K, R, MODE>, 1 << (K - R),
+                                                       shmem);
+      if (e != hipSuccess) return e;
       resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 256);
+      facts.resident[dev].store(resident, std::memory_order_release);
     }
     g = (int)(total < resident ? total : resident);
   }
