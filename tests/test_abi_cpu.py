@@ -140,3 +140,23 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_bench_traffic_only_for_the_recorded_sources(tmp_path, monkeypatch):
+    """The bench line's measured HBM traffic comes from the committed counter
+    summary only while the kernel sources have the digest recorded there;
+    another digest, a missing file or a malformed figure gives null."""
+    import sys
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, here)
+    import bench
+    f = tmp_path / "traffic.txt"
+    f.write_text("# comment: with a colon\nsource_digest: %s\nbytes_per_pass: 8591374339\n" % bench.kernel_digest())
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic() == 8591374339.0
+    f.write_text("source_digest: 0000000000000000\nbytes_per_pass: 8591374339\n")
+    assert bench.measured_traffic() is None
+    f.write_text("source_digest: %s\nbytes_per_pass: n/a\n" % bench.kernel_digest())
+    assert bench.measured_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.measured_traffic() is None
